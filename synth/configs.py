@@ -1,0 +1,127 @@
+"""Workload descriptions: image grids, scanner geometries, TOF, counts, prior settings.
+
+Plain parameter records; no arithmetic of the reconstruction method lives here.
+Both the oracle and the GPU library read the same records, so a parameter choice
+(ring pitch, radial sampling, phantom layout) is made once.
+
+Names: ``c0_2d`` (2D parallel beam), ``c1_3d`` (3D brain-sized non-TOF),
+``c2_tof`` (3D TOF, the headline workload), ``c3_diff`` (small 3D used by the
+unrolled/differentiable form), plus small ``mini_*`` geometries used by tests so
+the FP64 oracle finishes in seconds while still covering ragged shapes.
+"""
+
+import math
+from copy import deepcopy
+
+FWHM_TO_SIGMA = 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+
+# Water attenuation used for the multiplicative factors a_j = exp(-mu L_j).
+MU_WATER = 0.0096  # 1/mm
+
+_C1_PITCH = 71 * 2.03 / 64  # scanner axial FOV equals the image's axial extent
+
+CONFIGS = {
+    # 2D parallel-beam, 64x64 image at 4 mm, 91 radial x 60 views over 180 deg.
+    "c0_2d": dict(
+        name="c0_2d", kind="parallel2d",
+        nx=64, ny=64, nz=1, vx=4.0, vy=4.0, vz=4.0,
+        n_views=60, n_rad=91, rad_spacing=4.0, half_length=500.0,
+        n_tof=1, tof_bin=0.0, tof_sigma=0.0, tof_nsigma=0.0,
+        n_subsets=6, phantom="c0", counts_total=1e5, bg_fraction_of_mean=0.1,
+        beta=0.01, gamma=2.0, seed=0, epochs=20,
+    ),
+    # 3D non-TOF brain-sized: 128x128x71, 504-crystal ring of radius 328 mm,
+    # 64 rings, span-1 planes with ring difference <= 20 (2204 planes).
+    "c1_3d": dict(
+        name="c1_3d", kind="cylinder",
+        nx=128, ny=128, nz=71, vx=2.086, vy=2.086, vz=2.03,
+        radius=328.0, n_crystals=504, n_views=252, n_rad=344,
+        n_rings=64, ring_pitch=_C1_PITCH, max_ring_diff=20,
+        n_tof=1, tof_bin=0.0, tof_sigma=0.0, tof_nsigma=0.0,
+        n_subsets=25, phantom="head", counts=1e7, bg_fraction_of_prompts=0.2,
+        beta_tilde=4.0, gamma=2.0, seed=0, epochs=30,
+    ),
+    # 3D TOF: as c1_3d plus 13 TOF bins of 40 mm, Gaussian 60 mm FWHM, 3 sigma.
+    "c2_tof": dict(
+        name="c2_tof", kind="cylinder",
+        nx=128, ny=128, nz=71, vx=2.086, vy=2.086, vz=2.03,
+        radius=328.0, n_crystals=504, n_views=252, n_rad=344,
+        n_rings=64, ring_pitch=_C1_PITCH, max_ring_diff=20,
+        n_tof=13, tof_bin=40.0, tof_sigma=60.0 * FWHM_TO_SIGMA, tof_nsigma=3.0,
+        n_subsets=25, phantom="head", counts=3e7, bg_fraction_of_prompts=0.2,
+        beta_tilde=4.0, gamma=2.0, seed=0, epochs=30,
+    ),
+    # Small 3D geometry of the unrolled form: 96x96x32, 240-crystal ring,
+    # 32 rings, ring difference <= 4 (268 planes), 8 subsets.
+    "c3_diff": dict(
+        name="c3_diff", kind="cylinder",
+        nx=96, ny=96, nz=32, vx=128 * 2.086 / 96, vy=128 * 2.086 / 96, vz=4.5,
+        radius=328.0, n_crystals=240, n_views=120, n_rad=180,
+        n_rings=32, ring_pitch=4.5, max_ring_diff=4,
+        n_tof=1, tof_bin=0.0, tof_sigma=0.0, tof_nsigma=0.0,
+        n_subsets=8, phantom="head", counts=5e6, bg_fraction_of_prompts=0.2,
+        beta_tilde=4.0, gamma=2.0, seed=0, epochs=10,
+    ),
+    # Test geometries: ragged sizes, several segments, TOF on/off.
+    "mini_tof": dict(
+        name="mini_tof", kind="cylinder",
+        nx=21, ny=19, nz=9, vx=4.0, vy=4.2, vz=3.7,
+        radius=90.0, n_crystals=42, n_views=21, n_rad=17,
+        n_rings=8, ring_pitch=4.1, max_ring_diff=3,
+        n_tof=5, tof_bin=22.0, tof_sigma=14.0, tof_nsigma=3.0,
+        n_subsets=4, phantom="head_small", counts=2e4, bg_fraction_of_prompts=0.2,
+        beta_tilde=4.0, gamma=2.0, seed=1, epochs=4,
+    ),
+    "mini_nontof": dict(
+        name="mini_nontof", kind="cylinder",
+        nx=21, ny=19, nz=9, vx=4.0, vy=4.2, vz=3.7,
+        radius=90.0, n_crystals=42, n_views=21, n_rad=17,
+        n_rings=8, ring_pitch=4.1, max_ring_diff=3,
+        n_tof=1, tof_bin=0.0, tof_sigma=0.0, tof_nsigma=0.0,
+        n_subsets=4, phantom="head_small", counts=2e4, bg_fraction_of_prompts=0.2,
+        beta_tilde=4.0, gamma=2.0, seed=2, epochs=4,
+    ),
+    "mini_2d": dict(
+        name="mini_2d", kind="parallel2d",
+        nx=23, ny=17, nz=1, vx=4.0, vy=4.0, vz=4.0,
+        n_views=12, n_rad=31, rad_spacing=3.5, half_length=300.0,
+        n_tof=1, tof_bin=0.0, tof_sigma=0.0, tof_nsigma=0.0,
+        n_subsets=3, phantom="c0_small", counts_total=5e4, bg_fraction_of_mean=0.1,
+        beta=0.01, gamma=2.0, seed=3, epochs=4,
+    ),
+}
+
+
+def get(name, **overrides):
+    """Return a copy of the named workload with ``overrides`` applied."""
+    cfg = deepcopy(CONFIGS[name])
+    cfg.update(overrides)
+    return cfg
+
+
+def n_planes(cfg):
+    if cfg["kind"] == "parallel2d":
+        return 1
+    nr, md = cfg["n_rings"], cfg["max_ring_diff"]
+    return nr + 2 * sum(nr - d for d in range(1, md + 1))
+
+
+def n_bins(cfg):
+    return cfg["n_views"] * cfg["n_rad"] * n_planes(cfg) * cfg["n_tof"]
+
+
+def n_vox(cfg):
+    return cfg["nx"] * cfg["ny"] * cfg["nz"]
+
+
+def subset_views(cfg, i):
+    """Views of subset i: every n-th view starting at i (interleaved)."""
+    return list(range(i, cfg["n_views"], cfg["n_subsets"]))
+
+
+def beta_value(cfg):
+    """Prior strength: the explicit ``beta`` if given, else the count-scaled rule
+    beta = beta_tilde * 2e-4 * counts / 3e7 (Section 3.1, simulation setup)."""
+    if "beta" in cfg:
+        return float(cfg["beta"])
+    return float(cfg["beta_tilde"] * 2e-4 * cfg["counts"] / 3e7)
