@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: preconditioned-SVRG epochs/s on the 3D TOF brain-sized workload.
+
+Workload (default): 128x128x71 image (2.086 x 2.086 x 2.03 mm), 504-crystal
+ring of radius 328 mm, 344 radial x 252 views, 64 rings with ring difference
+<= 20 (2204 planes), 13 TOF bins of 40 mm with a 60 mm FWHM Gaussian truncated
+at 3 sigma (2.48e9 TOF bins), head phantom with 3e7 true counts, background
+r = 20% of prompts, 25 subsets, RDP gamma = 2 with 26 neighbours, harmonic
+preconditioner updated in epochs 1-3, stepsize 1 / (1 + 0.02 k / n).
+
+A step is one SVRG epoch (n iterations of the fused subset gradient, the RDP
+stencil, the preconditioner (first epochs) and the clipped update; every
+second epoch starts with a full snapshot pass).  Inputs are synthetic and
+resident in HBM before timing starts.  One JSON line is printed.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SVRG epochs/s (fwd+back+RDP), 3D TOF; HBM GB/s vs peak; time to NRMSE<1%"
+
+# Algorithmic floating-point work of the fused subset gradient (forward
+# projection, ratio, backprojection): per Joseph sample, the z position (2) and
+# bilinear interpolation (9) forward plus the position (2), bilinear spread (6)
+# and accumulation (4) backward; per sample-TOF-bin pair, the TOF weight as a
+# tabulated function (5) and its multiply-accumulate (2), forward and backward.
+FLOP_PER_SAMPLE = 23.0
+FLOP_PER_PAIR_TOF = 14.0
+FLOP_PER_SAMPLE_NONTOF = 2.0  # accumulate forward + scale backward
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, d, x0, beta, eps, view=0):
+    """Time the FP64 oracle's subset-gradient arithmetic on one view and scale
+    it to one SVRG epoch (data passes per epoch x views) plus the prior."""
+    import numpy as np
+    from oracle import projector, rdp
+    from synth import configs
+
+    threads = len(os.sched_getaffinity(0))
+    os.environ["ORACLE_THREADS"] = str(threads)
+    projector._NTHREADS = threads
+    T = cfg["n_tof"]
+    p1, p2 = projector.view_lors(cfg, [view])
+    a = d["mult"][view].reshape(-1, 1).astype(np.float64)
+    r = d["r"][view].reshape(-1, T).astype(np.float64)
+    y = d["y"][view].reshape(-1, T).astype(np.float64)
+    x = np.asarray(x0, np.float64).reshape(cfg["nz"], cfg["ny"], cfg["nx"])
+    t0 = time.perf_counter()
+    yb = a * projector.fwd(cfg, x, p1, p2) + r
+    g = projector.back(cfg, a * (1.0 - y / yb), p1, p2)
+    t_view = time.perf_counter() - t0
+    w = rdp.default_weights(cfg["vx"], cfg["vy"], cfg["vz"], cfg["nz"])
+    t0 = time.perf_counter()
+    rdp.grad(x, w, 2.0, eps)
+    t_rdp = time.perf_counter() - t0
+    n = cfg["n_subsets"]
+    passes = (3 * n - 1) / (2 * n)  # data passes per epoch with a snapshot every 2 epochs
+    epoch_s = passes * cfg["n_views"] * t_view + n * t_rdp
+    del g
+    return {"value": 1.0 / epoch_s, "unit": "epochs/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle fused subset gradient (fwd, ratio, back) on view {view} "
+                      f"({p1.shape[0]} LORs x {T} TOF bins) in {t_view:.1f} s plus one RDP gradient in "
+                      f"{t_rdp:.2f} s, scaled by {passes:.3f} data passes x {cfg['n_views']} views and "
+                      f"{n} RDP evaluations per epoch"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8, help="timed SVRG epochs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed SVRG epochs before timing")
+    ap.add_argument("--config", default="c2_tof")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the reconstruction would shard views across GPUs with one image all-reduce per iteration; "
+              "that path is not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_04976_amd as pm
+    from synth import configs, data
+
+    cfg = configs.get(args.config)
+    dev = torch.device("cuda:0")
+    n = cfg["n_subsets"]
+    t0 = time.time()
+    log(f"[bench] generating {cfg['name']} data ...")
+    d = data.make_dataset(cfg)
+    log(f"[bench] data ready in {time.time() - t0:.1f} s: y {d['y'].dtype} {d['y'].shape}")
+    y = torch.from_numpy(d["y"].reshape(-1)).to(dev)
+    r = torch.from_numpy(d["r"].reshape(-1)).to(dev)
+    a = torch.from_numpy(d["mult"].reshape(-1)).to(dev)
+    keep = {"y": d["y"][:1].copy(), "r": d["r"][:1].copy(), "mult": d["mult"][:1].copy()}
+    del d
+    geom = pm.Geometry(cfg)
+    torch.cuda.synchronize()
+    log(f"[bench] uploaded; geometry ready ({geom.n_bins} bins, {geom.n_vox} voxels)")
+
+    sens = torch.empty(geom.n_vox, device=dev)
+    pm.pet_back(geom, -1, None, a, sens)
+    x = torch.ones(geom.n_vox, device=dev)
+    xmax = torch.zeros(1, device=dev)
+    pm.pet_osem_epoch(geom, x, y, r, a, list(range(n)), xmax)
+    mx = float(xmax.cpu())
+    beta = configs.beta_value(cfg)
+    eps = delta = 1e-3 * mx
+    x0_host = x.cpu().numpy()
+    st = pm.SvrgStateBuffers(geom, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0, delta=delta)
+    total = args.warmup + args.steps
+    orders = data.subset_orders(cfg, total)
+    upd_iters = {0, n, 2 * n}
+
+    def epoch(e):
+        ks = [e * n + j for j in range(n)]
+        pm.pet_svrg_epoch(geom, st, x, orders[e], [1.0 / (1.0 + 0.02 * k / n) for k in ks],
+                          [k in upd_iters for k in ks])
+
+    log("[bench] OSEM done; warmup epochs ...")
+    for e in range(args.warmup):
+        epoch(e)
+    torch.cuda.synchronize()
+    pm.pet_profile_enable(geom, True)
+    for kern in (pm.PET_KERNEL_GRAD,):
+        pm.pet_profile_read(geom, kern)
+    log(f"[bench] timing {args.steps} epochs ...")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for e in range(args.warmup, total):
+        epoch(e)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    grad_ms, grad_launches = pm.pet_profile_read(geom, pm.PET_KERNEL_GRAD)
+    pm.pet_profile_enable(geom, False)
+    log(f"[bench] {args.steps} epochs in {elapsed:.3f} s; fused-gradient kernel {grad_launches} launches, "
+        f"{grad_ms:.1f} ms total")
+
+    # algorithmic work of the launches in the timed region
+    launched = []
+    for e in range(args.warmup, total):
+        for j in range(n):
+            k = e * n + j
+            launched += list(range(n)) if k % (2 * n) == 0 else [int(orders[e][j])]
+    assert len(launched) == grad_launches, (len(launched), grad_launches)
+    counts = {}
+    cnt = torch.zeros(2, dtype=torch.float64, device=dev)
+    for i in range(n):
+        pm.pet_work_counts(geom, i, cnt)
+        counts[i] = tuple(float(v) for v in cnt.cpu())
+    tof = cfg["n_tof"] > 1
+    flops = 0.0
+    hbm = 0.0
+    for i in launched:
+        s, p = counts[i]
+        flops += FLOP_PER_SAMPLE * s + (FLOP_PER_PAIR_TOF * p if tof else FLOP_PER_SAMPLE_NONTOF * s)
+        nb, nl, _ = geom.info(i)
+        hbm += nb * (y.element_size() + 4) + nl * 4 + 4 * geom.n_vox * 2
+    grad_s = grad_ms / 1e3
+    achieved = flops / grad_s / 1e12
+    kernel_gbps = hbm / grad_s / 1e9
+    # whole-epoch algorithmic HBM traffic: sinogram data of every subset
+    # gradient plus the image-space passes (RDP stencil and update)
+    epoch_bytes = hbm / args.steps + n * 7 * 4 * geom.n_vox
+
+    obj = torch.zeros(1, dtype=torch.float64, device=dev)
+    pm.pet_objective(geom, x, y, r, a, None, pm.rdp_weights27(cfg["vx"], cfg["vy"], cfg["vz"]), beta,
+                     cfg["gamma"], eps, obj)
+    objective = float(obj.cpu())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a one-view sample ...")
+        del y, r, a, st
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(cfg, keep, x0_host, beta, eps)
+
+    value = args.steps / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "epochs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg['name']}: {cfg['nx']}x{cfg['ny']}x{cfg['nz']} image, "
+                               f"{cfg['n_views']} views x {cfg['n_rad']} radial x {geom.n_lors // (cfg['n_views'] * cfg['n_rad'])} planes"
+                               f" x {cfg['n_tof']} TOF, {n} subsets, preconditioned SVRG",
+                   "bins": geom.n_bins, "voxels": geom.n_vox, "counts": cfg.get("counts"),
+                   "y_dtype": str(keep["y"].dtype), "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_line<TOF, M_GRAD> (fused forward projection, ratio, backprojection)",
+                     "avg_launch_ms": grad_ms / grad_launches, "launches": grad_launches,
+                     "algorithmic_hbm_gbps": kernel_gbps, "hbm_frac": kernel_gbps / PEAK_HBM_GBPS},
+        "hbm_gbps_epoch": epoch_bytes * value / 1e9,
+        "objective_final": objective,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

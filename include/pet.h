@@ -1,0 +1,214 @@
+/* pet.h — C ABI of the MI355X (gfx950) library for RDP-regularised PET
+ * reconstruction with prior-aware preconditioned SVRG.
+ *
+ * Problem (Section 1, eq. (1) with the prior of eq. (prior)):
+ *     minimise  D(A x + r, y) + beta S(x) + i_{>=0}(x),
+ * D the Poisson (KL) data fidelity (Section 1.2), S the relative difference
+ * prior (eq. (rdp)), A = diag(mult) P with P the Joseph line-integral
+ * projector (TOF-resolved when the scanner has TOF bins) and r > 0 the additive
+ * background.  The data are split into n subsets of interleaved views
+ * (Section 2.4): subset i holds views v = i, i + n, i + 2n, ...
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Image:     float [nz][ny][nx] (x fastest), voxel (ix, iy, iz) centred at
+ *            ((ix - (nx-1)/2) vx, (iy - (ny-1)/2) vy, (iz - (nz-1)/2) vz) mm.
+ * Sinogram:  flat index ((view * n_rad + radial) * n_planes + plane) * n_tof + tof
+ *            (view-major, TOF innermost).  Every sinogram argument is a FULL
+ *            sinogram (all views); a call on subset i reads/writes only the views
+ *            of subset i and leaves the others untouched.  subset = -1 means all
+ *            views.
+ * mult:      float per LOR, index (view * n_rad + radial) * n_planes + plane,
+ *            shared by all TOF bins of the LOR.
+ * Pointers:  device pointers unless stated otherwise; all are caller-owned and
+ *            never freed by the library.  Only pet_geom_create allocates (its
+ *            geometry tables and a scratch arena owned by the handle).
+ * Streams:   `stream` is a hipStream_t (NULL = default stream).  Calls enqueue
+ *            work on it and return without synchronising, except
+ *            pet_geom_create / pet_geom_destroy (synchronous) and the host-side
+ *            reads of pet_osem_epoch / pet_svrg_epoch noted below.
+ * Threads:   a pet_geom handle owns scratch memory: calls on one handle must
+ *            not overlap in time (same or different streams).  Separate handles
+ *            are independent.
+ * Errors:    argument errors return PET_E_ARG before anything is enqueued;
+ *            a HIP launch failure returns PET_E_HIP.  pet_last_error() returns a
+ *            thread-local message for the last non-OK status.  Domain
+ *            preconditions (x >= 0, r > 0, y >= 0) are the caller's: values
+ *            outside them give unspecified results (the paper's d(s, t) and R(x)
+ *            are infinite there).
+ */
+#ifndef PET_H
+#define PET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PET_OK = 0,
+    PET_E_ARG = 1,
+    PET_E_DOMAIN = 2,
+    PET_E_OOM = 3,
+    PET_E_HIP = 4,
+    PET_E_NUMERIC = 5,
+    PET_E_STATE = 6
+} pet_status;
+
+enum { PET_SCANNER_PARALLEL2D = 0, PET_SCANNER_CYLINDER = 1 };
+enum { PET_BACK_AUTO = 0, PET_BACK_SCATTER = 1 };
+enum { PET_Y_F32 = 0, PET_Y_U16 = 1, PET_Y_U8 = 2 };
+
+/* Scanner + image description.
+ * PET_SCANNER_CYLINDER: n_crystals per ring (= 2 n_views), ring radius, rings
+ *   at z_r = (r - (n_rings-1)/2) ring_pitch; LOR (view v, radial k, plane p)
+ *   joins s n - h t (ring r1) to s n + h t (ring r2) with phi = pi v / n_views,
+ *   n = (cos phi, sin phi), t = (-sin phi, cos phi),
+ *   s = R sin(pi (k - (n_rad-1)/2) / n_crystals), h = sqrt(R^2 - s^2);
+ *   planes (r1, r2) with |r2 - r1| <= max_ring_diff ordered by segment
+ *   d = r2 - r1 = 0, -1, +1, -2, +2, ... and r1 ascending.
+ * PET_SCANNER_PARALLEL2D: nz = 1, one plane, s = (k - (n_rad-1)/2) rad_spacing,
+ *   endpoints s n -/+ half_length t.
+ * TOF (n_tof > 1): bin b centred at t_b = (b - (n_tof-1)/2) tof_bin along the
+ *   LOR (signed distance from the LOR centre towards the second endpoint);
+ *   weight of a point at t: the Gaussian kernel (sigma tof_sigma) truncated to
+ *   |t' - t| <= tof_nsigma sigma, integrated over the bin [t_b -/+ tof_bin/2].
+ */
+typedef struct {
+    int kind;
+    int nx, ny, nz;
+    double vx, vy, vz;
+    int n_views, n_rad;
+    double radius_mm;
+    int n_crystals, n_rings;
+    double ring_pitch_mm;
+    int max_ring_diff;
+    double rad_spacing_mm, half_length_mm;
+    int n_tof;
+    double tof_bin_mm, tof_sigma_mm, tof_nsigma;
+    int n_subsets;
+} pet_geom_desc;
+
+typedef struct pet_geom_s *pet_geom;
+
+/* Build the geometry tables (FP64 on the host, FP32 on the device) and the
+ * scratch arena on the current HIP device.  Synchronous.  PET_E_ARG for an
+ * inconsistent description or one the projector does not support (a principal
+ * axis along z, LOR endpoints inside the padded image box, a sheet larger than
+ * the LDS); PET_E_OOM if device allocation fails. */
+pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out);
+pet_status pet_geom_destroy(pet_geom g);
+
+/* Sizes: number of sinogram bins (incl. TOF) and LORs of `subset` (-1: all),
+ * and voxels.  Any output pointer may be NULL. */
+pet_status pet_geom_info(pet_geom g, int subset, int64_t *n_bins, int64_t *n_lors, int64_t *n_vox);
+
+/* Forward model of one subset (eq. (1)): out = mult * (P_subset x) + add.
+ * mult, add nullable (1 and 0).  Writes only the bins of the subset's views. */
+pet_status pet_fwd(pet_geom g, int subset, const float *x, const float *mult, const float *add,
+                   float *out, void *stream);
+
+/* Adjoint: x_out (+)= P_subset^T (mult * sino).  sino NULL means all ones (so
+ * pet_back(g, -1, NULL, mult, sens, 0, ...) gives the sensitivity A^T 1).
+ * accumulate = 0 overwrites x_out.  algo: PET_BACK_AUTO / PET_BACK_SCATTER
+ * (line-driven scatter through LDS sheets with global float atomics; the sum
+ * order is not deterministic). */
+pet_status pet_back(pet_geom g, int subset, const float *sino, const float *mult, float *x_out,
+                    int accumulate, int algo, void *stream);
+
+/* Gradient of the subset data term D_i (Section 2, eq. (template)):
+ * grad_out = P_i^T [mult (1 - y / (mult P_i x + add))], fused per LOR (no
+ * sinogram-sized intermediate).  y has type y_dtype.  kl_out (device double,
+ * nullable) receives sum over the subset's bins of d(ybar, y) (FP64). */
+pet_status pet_subset_grad(pet_geom g, int subset, const float *x, const void *y, int y_dtype,
+                           const float *add, const float *mult, float *grad_out, double *kl_out,
+                           void *stream);
+
+/* Relative difference prior (eq. (rdp)) and its derivatives (Appendix A),
+ * scaled by beta: grad_out = beta dS/dx, hessdiag_out = beta d2S/dx2 (nullable),
+ * value_out = beta S (device double, nullable).  w[27]: weight of neighbour
+ * offset (dz, dy, dx) at index (dz+1)*9 + (dy+1)*3 + (dx+1) (centre ignored);
+ * neighbours outside the grid are omitted.  kappa nullable (1). */
+pet_status pet_rdp_grad_hessdiag(pet_geom g, const float *x, const float *kappa, const float w[27],
+                                 float beta, float gamma, float eps, float *grad_out,
+                                 float *hessdiag_out, double *value_out, void *stream);
+
+/* Prior-aware preconditioner (eq. (preconditioner)):
+ * D = (x + delta) / (sens + alpha hessdiag (x + delta)), D = 0 where the
+ * denominator is 0.  hessdiag is the diagonal of the Hessian of beta S. */
+pet_status pet_precond(pet_geom g, const float *x, const float *sens, const float *hessdiag,
+                       float alpha, float delta, float *D_out, void *stream);
+
+/* One OSEM epoch (Section 3.1 initialisation): for each subset i in order[]
+ * (host array of n_subsets entries): x <- x * P_i^T(mult y / ybar) / P_i^T mult
+ * (voxels with P_i^T mult = 0 keep x).  xmax_out (device float, nullable)
+ * receives max(x) after the epoch. */
+pet_status pet_osem_epoch(pet_geom g, float *x, const void *y, int y_dtype, const float *add,
+                          const float *mult, const int32_t *order, float *xmax_out, void *stream);
+
+/* Objective D(A x + r, y) + beta S(x) in FP64 (device double). */
+pet_status pet_objective(pet_geom g, const float *x, const void *y, int y_dtype, const float *add,
+                         const float *mult, const float *kappa, const float w[27], float beta,
+                         float gamma, float eps, double *out, void *stream);
+
+/* Caller-owned state of preconditioned SVRG (Algorithm 1).  Device buffers
+ * sized from pet_geom_info: ghat_i [n_subsets][n_vox] float, ghat [n_vox]
+ * double, x_snap [n_vox] float, D [n_vox] float, sens [n_vox] float (A^T 1
+ * over all subsets, e.g. from pet_back).  ghat_i stores the data-term part of
+ * the subset gradients at the snapshot; the prior enters each step through its
+ * exact current gradient, which equals Algorithm 1's estimator (the prior's
+ * 1/n shares cancel). */
+typedef struct {
+    float *ghat_i;
+    double *ghat;
+    float *x_snap;
+    float *D;
+    const float *sens;
+    const void *y;
+    int y_dtype;
+    const float *add;
+    const float *mult;
+    const float *kappa;
+    float w[27];
+    float beta, gamma, eps, alpha, delta;
+    int omega;
+    int64_t k;
+} pet_svrg_state;
+
+/* One epoch = n_subsets iterations of Algorithm 1 with the nonnegativity
+ * proximal step of eq. (sgm).  Iteration j (global k = state->k + j):
+ *   if update_pc[j]: D <- pet_precond at x;
+ *   if k mod (omega n) == 0: snapshot (all ghat_i, ghat = sum ghat_i in FP64,
+ *     x_snap = x) and g = ghat + beta grad S(x);
+ *   else i = subset_seq[j], g = n (grad D_i(x) - ghat_i) + ghat + beta grad S(x);
+ *   x <- max(0, x - tau[j] D g).
+ * subset_seq, tau, update_pc are HOST arrays of n_subsets entries.  state->k
+ * advances by n_subsets; a fresh state starts at k = 0 (a snapshot iteration)
+ * and D must hold a preconditioner before the first iteration that does not
+ * update it.  PET_E_STATE for k < 0.  x is updated in place.  objective_out (device double,
+ * nullable) receives the objective at the final x (one extra forward pass). */
+pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *state, float *x, const int32_t *subset_seq,
+                          const float *tau, const uint8_t *update_pc, double *objective_out,
+                          void *stream);
+
+/* Instrumentation --------------------------------------------------------
+ * Work of the line kernels on `subset` (-1: all), exactly as they traverse it:
+ * out[0] = Joseph samples, out[1] = sample-TOF-bin pairs with nonzero weight
+ * support (= samples without TOF).  out: device doubles[2]. */
+pet_status pet_work_counts(pet_geom g, int subset, double *out, void *stream);
+
+/* Time every line-kernel launch of a handle with a HIP event pair recorded on
+ * the launch stream (enable != 0), and read the accumulated time and count of
+ * one kernel (PET_KERNEL_*) since the last read; reading synchronises on the
+ * recorded events and resets that kernel's record. */
+enum { PET_KERNEL_FWD = 0, PET_KERNEL_BACK = 1, PET_KERNEL_GRAD = 2, PET_KERNEL_EM = 3, PET_KERNEL_OBJ = 4 };
+pet_status pet_profile_enable(pet_geom g, int enable);
+pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms, int64_t *launches);
+
+const char *pet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -16,9 +16,13 @@
  *   length l = v_m |u| / |u_m|.
  *
  *   TOF: a sample at signed distance t = (lambda - 1/2)|u| from the LOR centre
- *   contributes to TOF bin b (centre t_b, width w) with weight
- *   1/2 [erf((t_b + w/2 - t)/(sqrt2 sigma)) - erf((t_b - w/2 - t)/(sqrt2 sigma))]
- *   when |t - t_b| <= nsig * sigma (no truncation when nsig <= 0).
+ *   contributes to TOF bin b (centre t_b, width w) with the Gaussian kernel
+ *   (standard deviation sigma) truncated to |t' - t| <= nsig sigma and
+ *   integrated over the bin:
+ *     1/2 [E(t_b + w/2 - t) - E(t_b - w/2 - t)],  E(u) = erf(clamp(u / (sqrt2 sigma), -c, c)),
+ *   c = nsig / sqrt2 (no clamp when nsig <= 0).  The weight is continuous in t
+ *   and the weights of a sample whose truncation window lies inside the bins
+ *   sum to erf(nsig / sqrt2).
  *
  * The adjoint scatters exactly the same (voxel, weight) pairs.
  *
@@ -31,6 +35,17 @@
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* erf of u / (sqrt2 sigma), with the argument clamped to +-nsig/sqrt2. */
+static double clamped_erf(double u, double sigma, double nsig) {
+    double z = u / (sqrt(2.0) * sigma);
+    if (nsig > 0) {
+        double c = nsig / sqrt(2.0);
+        if (z > c) z = c;
+        if (z < -c) z = -c;
+    }
+    return erf(z);
+}
 
 static int principal_axis(const double u[3], const double v[3]) {
     int m = 0;
@@ -78,12 +93,8 @@ static void joseph_lor(int mode, const double *p1, const double *p2, const int n
             double t = (lam - 0.5) * len;
             for (int b = 0; b < ntof; ++b) {
                 double tb = (b - 0.5 * (ntof - 1)) * tof_bin;
-                if (nsig > 0 && fabs(t - tb) > nsig * sigma) {
-                    tw[b] = 0.0;
-                    continue;
-                }
-                tw[b] = 0.5 * (erf((tb + 0.5 * tof_bin - t) / (sqrt(2.0) * sigma)) -
-                               erf((tb - 0.5 * tof_bin - t) / (sqrt(2.0) * sigma)));
+                tw[b] = 0.5 * (clamped_erf(tb + 0.5 * tof_bin - t, sigma, nsig) -
+                               clamped_erf(tb - 0.5 * tof_bin - t, sigma, nsig));
             }
         }
         if (mode == 1)

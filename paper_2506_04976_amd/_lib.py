@@ -1,0 +1,321 @@
+"""ctypes binding of libpetmi.so (include/pet.h): same entry-point names, torch
+tensors marshalled to device pointers and torch's current HIP stream.
+
+Every step of the reconstruction runs in the library's HIP kernels; this module
+only checks and converts arguments.  It refuses to run without the compiled
+library or without a GPU (there is no CPU fallback).
+"""
+
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpetmi.so")
+
+PET_SCANNER_PARALLEL2D = 0
+PET_SCANNER_CYLINDER = 1
+PET_BACK_AUTO = 0
+PET_BACK_SCATTER = 1
+PET_Y_F32, PET_Y_U16, PET_Y_U8 = 0, 1, 2
+
+_STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "PET_E_HIP",
+           5: "PET_E_NUMERIC", 6: "PET_E_STATE"}
+
+EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
+           "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
+           "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
+PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
+
+
+class PetError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GeomDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("vx", ctypes.c_double), ("vy", ctypes.c_double), ("vz", ctypes.c_double),
+                ("n_views", ctypes.c_int), ("n_rad", ctypes.c_int), ("radius_mm", ctypes.c_double),
+                ("n_crystals", ctypes.c_int), ("n_rings", ctypes.c_int), ("ring_pitch_mm", ctypes.c_double),
+                ("max_ring_diff", ctypes.c_int), ("rad_spacing_mm", ctypes.c_double),
+                ("half_length_mm", ctypes.c_double), ("n_tof", ctypes.c_int), ("tof_bin_mm", ctypes.c_double),
+                ("tof_sigma_mm", ctypes.c_double), ("tof_nsigma", ctypes.c_double), ("n_subsets", ctypes.c_int)]
+
+
+class SvrgState(ctypes.Structure):
+    _fields_ = [("ghat_i", ctypes.c_void_p), ("ghat", ctypes.c_void_p), ("x_snap", ctypes.c_void_p),
+                ("D", ctypes.c_void_p), ("sens", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("y_dtype", ctypes.c_int), ("add", ctypes.c_void_p), ("mult", ctypes.c_void_p),
+                ("kappa", ctypes.c_void_p), ("w", ctypes.c_float * 27), ("beta", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("eps", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("delta", ctypes.c_float), ("omega", ctypes.c_int), ("k", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpetmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(paper_2506_04976_amd/build.py); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, F, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+        L.pet_geom_create.argtypes = [ctypes.POINTER(GeomDesc), ctypes.POINTER(P)]
+        L.pet_geom_destroy.argtypes = [P]
+        L.pet_geom_info.argtypes = [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64)]
+        L.pet_fwd.argtypes = [P, I, P, P, P, P, P]
+        L.pet_back.argtypes = [P, I, P, P, P, I, I, P]
+        L.pet_subset_grad.argtypes = [P, I, P, P, I, P, P, P, P, P]
+        L.pet_rdp_grad_hessdiag.argtypes = [P, P, P, ctypes.POINTER(F), F, F, F, P, P, P, P]
+        L.pet_precond.argtypes = [P, P, P, P, F, F, P, P]
+        L.pet_osem_epoch.argtypes = [P, P, P, I, P, P, ctypes.POINTER(ctypes.c_int32), P, P]
+        L.pet_objective.argtypes = [P, P, P, I, P, P, P, ctypes.POINTER(F), F, F, F, P, P]
+        L.pet_svrg_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), P, P]
+        L.pet_work_counts.argtypes = [P, I, P, P]
+        L.pet_profile_enable.argtypes = [P, I]
+        L.pet_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
+        for name in EXPORTS[:-1]:
+            getattr(L, name).restype = ctypes.c_int
+        L.pet_last_error.restype = ctypes.c_char_p
+        L.pet_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise PetError(status, lib().pet_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def y_dtype_code(t):
+    return {torch.float32: PET_Y_F32, torch.int16: PET_Y_U16, torch.uint16: PET_Y_U16,
+            torch.uint8: PET_Y_U8}[t.dtype]
+
+
+def desc_from_config(cfg):
+    d = GeomDesc()
+    d.kind = PET_SCANNER_CYLINDER if cfg["kind"] == "cylinder" else PET_SCANNER_PARALLEL2D
+    for k in ("nx", "ny", "nz", "n_views", "n_rad", "n_tof", "n_subsets"):
+        setattr(d, k, int(cfg[k]))
+    d.vx, d.vy, d.vz = float(cfg["vx"]), float(cfg["vy"]), float(cfg["vz"])
+    if cfg["kind"] == "cylinder":
+        d.radius_mm = float(cfg["radius"])
+        d.n_crystals = int(cfg["n_crystals"])
+        d.n_rings = int(cfg["n_rings"])
+        d.ring_pitch_mm = float(cfg["ring_pitch"])
+        d.max_ring_diff = int(cfg["max_ring_diff"])
+    else:
+        d.rad_spacing_mm = float(cfg["rad_spacing"])
+        d.half_length_mm = float(cfg["half_length"])
+    d.tof_bin_mm = float(cfg.get("tof_bin", 0.0))
+    d.tof_sigma_mm = float(cfg.get("tof_sigma", 0.0))
+    d.tof_nsigma = float(cfg.get("tof_nsigma", 0.0))
+    return d
+
+
+def rdp_weights27(vx, vy, vz):
+    """Neighbour weights w = vx / distance, index (dz+1)*9 + (dy+1)*3 + (dx+1)."""
+    w = [0.0] * 27
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dz or dy or dx:
+                    w[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1] = vx / math.sqrt((dz * vz) ** 2 + (dy * vy) ** 2 + (dx * vx) ** 2)
+    return w
+
+
+def _w27(w):
+    return (ctypes.c_float * 27)(*[float(v) for v in w])
+
+
+class Geometry:
+    """Owns a pet_geom handle."""
+
+    def __init__(self, cfg):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP GPU available: the PET library has no CPU path")
+        self.cfg = dict(cfg)
+        self.desc = desc_from_config(cfg)
+        h = ctypes.c_void_p()
+        _check(lib().pet_geom_create(ctypes.byref(self.desc), ctypes.byref(h)))
+        self.handle = h
+        nb, nl, nv = self.info(-1)
+        self.n_bins, self.n_lors, self.n_vox = nb, nl, nv
+        self.n_subsets = int(cfg["n_subsets"])
+        self.shape = (int(cfg["nz"]), int(cfg["ny"]), int(cfg["nx"]))
+
+    def info(self, subset):
+        nb, nl, nv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().pet_geom_info(self.handle, subset, ctypes.byref(nb), ctypes.byref(nl), ctypes.byref(nv)))
+        return nb.value, nl.value, nv.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pet_geom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- entry points (same names as the C ABI) ---------------------------------
+
+def pet_fwd(geom, subset, x, mult, add, out, stream=None):
+    _check(lib().pet_fwd(geom.handle, subset, _ptr(x, torch.float32, geom.n_vox, "x"),
+                         _ptr(mult, torch.float32, geom.n_lors, "mult"), _ptr(add, torch.float32, geom.n_bins, "add"),
+                         _ptr(out, torch.float32, geom.n_bins, "out"), _stream(stream)))
+    return out
+
+
+def pet_back(geom, subset, sino, mult, x_out, accumulate=False, algo=PET_BACK_AUTO, stream=None):
+    _check(lib().pet_back(geom.handle, subset, _ptr(sino, torch.float32, geom.n_bins, "sino"),
+                          _ptr(mult, torch.float32, geom.n_lors, "mult"), _ptr(x_out, torch.float32, geom.n_vox, "x_out"),
+                          int(bool(accumulate)), algo, _stream(stream)))
+    return x_out
+
+
+def pet_subset_grad(geom, subset, x, y, add, mult, grad_out, kl_out=None, stream=None):
+    _check(lib().pet_subset_grad(geom.handle, subset, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                 _ptr(y, None, geom.n_bins, "y"), y_dtype_code(y),
+                                 _ptr(add, torch.float32, geom.n_bins, "add"), _ptr(mult, torch.float32, geom.n_lors, "mult"),
+                                 _ptr(grad_out, torch.float32, geom.n_vox, "grad_out"),
+                                 _ptr(kl_out, torch.float64, 1, "kl_out"), _stream(stream)))
+    return grad_out
+
+
+def pet_rdp_grad_hessdiag(geom, x, kappa, w27, beta, gamma, eps, grad_out=None, hessdiag_out=None, value_out=None,
+                          stream=None):
+    _check(lib().pet_rdp_grad_hessdiag(geom.handle, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                       _ptr(kappa, torch.float32, geom.n_vox, "kappa"), _w27(w27), beta, gamma, eps,
+                                       _ptr(grad_out, torch.float32, geom.n_vox, "grad_out"),
+                                       _ptr(hessdiag_out, torch.float32, geom.n_vox, "hessdiag_out"),
+                                       _ptr(value_out, torch.float64, 1, "value_out"), _stream(stream)))
+
+
+def pet_precond(geom, x, sens, hessdiag, alpha, delta, D_out, stream=None):
+    _check(lib().pet_precond(geom.handle, _ptr(x, torch.float32, geom.n_vox, "x"),
+                             _ptr(sens, torch.float32, geom.n_vox, "sens"),
+                             _ptr(hessdiag, torch.float32, geom.n_vox, "hessdiag"), alpha, delta,
+                             _ptr(D_out, torch.float32, geom.n_vox, "D_out"), _stream(stream)))
+    return D_out
+
+
+def pet_osem_epoch(geom, x, y, add, mult, order, xmax_out=None, stream=None):
+    order = [int(v) for v in order]
+    if len(order) != geom.n_subsets:
+        raise ValueError("order must list every subset once per epoch")
+    arr = (ctypes.c_int32 * len(order))(*order)
+    _check(lib().pet_osem_epoch(geom.handle, _ptr(x, torch.float32, geom.n_vox, "x"), _ptr(y, None, geom.n_bins, "y"),
+                                y_dtype_code(y), _ptr(add, torch.float32, geom.n_bins, "add"),
+                                _ptr(mult, torch.float32, geom.n_lors, "mult"), arr,
+                                _ptr(xmax_out, torch.float32, 1, "xmax_out"), _stream(stream)))
+    return x
+
+
+def pet_objective(geom, x, y, add, mult, kappa, w27, beta, gamma, eps, out, stream=None):
+    _check(lib().pet_objective(geom.handle, _ptr(x, torch.float32, geom.n_vox, "x"), _ptr(y, None, geom.n_bins, "y"),
+                               y_dtype_code(y), _ptr(add, torch.float32, geom.n_bins, "add"),
+                               _ptr(mult, torch.float32, geom.n_lors, "mult"),
+                               _ptr(kappa, torch.float32, geom.n_vox, "kappa"), _w27(w27), beta, gamma, eps,
+                               _ptr(out, torch.float64, 1, "out"), _stream(stream)))
+    return out
+
+
+def pet_svrg_epoch(geom, state, x, subset_seq, tau, update_pc, objective_out=None, stream=None):
+    """state: SvrgStateBuffers; subset_seq/tau/update_pc: host sequences of n_subsets entries."""
+    n = geom.n_subsets
+    if not (len(subset_seq) == len(tau) == len(update_pc) == n):
+        raise ValueError("subset_seq, tau and update_pc need n_subsets entries each")
+    seq = (ctypes.c_int32 * n)(*[int(v) for v in subset_seq])
+    taus = (ctypes.c_float * n)(*[float(v) for v in tau])
+    upd = (ctypes.c_uint8 * n)(*[1 if v else 0 for v in update_pc])
+    _check(lib().pet_svrg_epoch(geom.handle, ctypes.byref(state.c), _ptr(x, torch.float32, geom.n_vox, "x"), seq,
+                                taus, upd, _ptr(objective_out, torch.float64, 1, "objective_out"), _stream(stream)))
+    return x
+
+
+def pet_work_counts(geom, subset, out, stream=None):
+    """out: CUDA float64 tensor of 2 elements -> (samples, sample-bin pairs)."""
+    _check(lib().pet_work_counts(geom.handle, subset, _ptr(out, torch.float64, 2, "out"), _stream(stream)))
+    return out
+
+
+def pet_profile_enable(geom, enable=True):
+    _check(lib().pet_profile_enable(geom.handle, 1 if enable else 0))
+
+
+def pet_profile_read(geom, kernel):
+    """(total milliseconds, launches) of one line kernel since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().pet_profile_read(geom.handle, kernel, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+class SvrgStateBuffers:
+    """Device buffers + the C state struct of preconditioned SVRG."""
+
+    def __init__(self, geom, y, add, mult, sens, beta, gamma, eps, alpha=1.0, delta=0.0, w27=None, kappa=None,
+                 omega=2):
+        dev = y.device
+        n, nv = geom.n_subsets, geom.n_vox
+        self.ghat_i = torch.zeros((n, nv), dtype=torch.float32, device=dev)
+        self.ghat = torch.zeros(nv, dtype=torch.float64, device=dev)
+        self.x_snap = torch.zeros(nv, dtype=torch.float32, device=dev)
+        self.D = torch.zeros(nv, dtype=torch.float32, device=dev)
+        self.refs = (y, add, mult, sens, kappa)
+        if w27 is None:
+            w27 = rdp_weights27(geom.cfg["vx"], geom.cfg["vy"], geom.cfg["vz"])
+        c = SvrgState()
+        c.ghat_i = self.ghat_i.data_ptr()
+        c.ghat = self.ghat.data_ptr()
+        c.x_snap = self.x_snap.data_ptr()
+        c.D = self.D.data_ptr()
+        c.sens = _ptr(sens, torch.float32, nv, "sens").value
+        c.y = _ptr(y, None, geom.n_bins, "y").value
+        c.y_dtype = y_dtype_code(y)
+        c.add = _ptr(add, torch.float32, geom.n_bins, "add").value if add is not None else None
+        c.mult = _ptr(mult, torch.float32, geom.n_lors, "mult").value if mult is not None else None
+        c.kappa = _ptr(kappa, torch.float32, nv, "kappa").value if kappa is not None else None
+        for i, v in enumerate(w27):
+            c.w[i] = float(v)
+        c.beta, c.gamma, c.eps, c.alpha, c.delta = float(beta), float(gamma), float(eps), float(alpha), float(delta)
+        c.omega = int(omega)
+        c.k = 0
+        self.c = c
+
+    @property
+    def k(self):
+        return self.c.k

@@ -1,0 +1,318 @@
+// Host-side geometry (FP64) for the gfx950 PET library: LOR endpoints from the
+// scanner description, per-line Joseph sampling parameters, per-plane axial
+// parameters, TOF interval table and TOF weight table, plus the scratch arena.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "pet_internal.h"
+
+using namespace pet;
+
+namespace {
+
+struct Plane {
+    int r1, r2, seg;
+};
+
+std::vector<Plane> make_planes(const pet_geom_desc &d) {
+    std::vector<Plane> out;
+    if (d.kind == PET_SCANNER_PARALLEL2D) {
+        out.push_back({0, 0, 0});
+        return out;
+    }
+    std::vector<int> segs{0};
+    for (int k = 1; k <= d.max_ring_diff; ++k) {
+        segs.push_back(-k);
+        segs.push_back(k);
+    }
+    for (size_t si = 0; si < segs.size(); ++si) {
+        int dd = segs[si];
+        for (int r1 = std::max(0, -dd); r1 < std::min(d.n_rings, d.n_rings - dd); ++r1)
+            out.push_back({r1, r1 + dd, (int)si});
+    }
+    return out;
+}
+
+// TOF weight of a point at distance dist from a bin centre: the Gaussian kernel
+// truncated to +-nsig sigma around the point, integrated over the bin
+// (half-width half).  Continuous in dist; zero beyond half + nsig sigma.
+double tof_weight(double dist, double half, double sigma, double nsig) {
+    double s = std::sqrt(2.0) * sigma, c = nsig / std::sqrt(2.0);
+    auto E = [&](double u) { return std::erf(std::max(-c, std::min(c, u / s))); };
+    return 0.5 * (E(half - dist) - E(-half - dist));
+}
+
+pet_status validate(const pet_geom_desc &d) {
+    if (d.kind != PET_SCANNER_PARALLEL2D && d.kind != PET_SCANNER_CYLINDER)
+        return fail(PET_E_ARG, "pet_geom_create: unknown scanner kind");
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1 || !(d.vx > 0) || !(d.vy > 0) || !(d.vz > 0))
+        return fail(PET_E_ARG, "pet_geom_create: image sizes and voxel sizes must be positive");
+    if (d.nx > 32000 || d.ny > 32000 || d.nz > 32000)
+        return fail(PET_E_ARG, "pet_geom_create: image dimension too large");
+    if (d.n_views < 1 || d.n_rad < 1) return fail(PET_E_ARG, "pet_geom_create: n_views and n_rad must be >= 1");
+    if (d.n_subsets < 1 || d.n_subsets > d.n_views)
+        return fail(PET_E_ARG, "pet_geom_create: need 1 <= n_subsets <= n_views");
+    if (d.n_tof < 1 || d.n_tof > NT_MAX) return fail(PET_E_ARG, "pet_geom_create: n_tof must be in [1, 16]");
+    if (d.n_tof > 1 && (!(d.tof_bin_mm > 0) || !(d.tof_sigma_mm > 0) || !(d.tof_nsigma > 0)))
+        return fail(PET_E_ARG, "pet_geom_create: TOF needs tof_bin_mm, tof_sigma_mm, tof_nsigma > 0");
+    if (d.kind == PET_SCANNER_CYLINDER) {
+        if (!(d.radius_mm > 0) || d.n_crystals != 2 * d.n_views || d.n_rings < 1 || !(d.ring_pitch_mm > 0) ||
+            d.max_ring_diff < 0 || d.max_ring_diff >= d.n_rings)
+            return fail(PET_E_ARG, "pet_geom_create: inconsistent cylinder description "
+                                   "(need radius > 0, n_crystals = 2 n_views, 0 <= max_ring_diff < n_rings)");
+        if (d.n_rad > d.n_crystals) return fail(PET_E_ARG, "pet_geom_create: n_rad > n_crystals");
+    } else {
+        if (d.nz != 1) return fail(PET_E_ARG, "pet_geom_create: 2D parallel-beam geometry needs nz = 1");
+        if (!(d.rad_spacing_mm > 0) || !(d.half_length_mm > 0))
+            return fail(PET_E_ARG, "pet_geom_create: parallel-beam needs rad_spacing_mm, half_length_mm > 0");
+    }
+    return PET_OK;
+}
+
+}  // namespace
+
+extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) {
+    if (!desc || !out) return fail(PET_E_ARG, "pet_geom_create: null argument");
+    const pet_geom_desc &d = *desc;
+    pet_status st = validate(d);
+    if (st != PET_OK) return st;
+
+    pet_geom_s *g = new (std::nothrow) pet_geom_s();
+    if (!g) return fail(PET_E_OOM, "pet_geom_create: host allocation failed");
+    g->d = d;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(PET_E_HIP, "pet_geom_create: no HIP device");
+    }
+    std::vector<Plane> planes = make_planes(d);
+    g->n_planes = (int)planes.size();
+    g->n_vox = (int64_t)d.nx * d.ny * d.nz;
+    for (auto &p : planes) g->seg_of_plane.push_back(p.seg);
+
+    const int N[3] = {d.nx, d.ny, d.nz};
+    const double V[3] = {d.vx, d.vy, d.vz};
+    double O[3];
+    for (int a = 0; a < 3; ++a) O[a] = -0.5 * (N[a] - 1) * V[a];
+
+    // axial table
+    std::vector<double> z1(planes.size()), z2(planes.size());
+    double max_dz = 0.0;
+    for (size_t p = 0; p < planes.size(); ++p) {
+        if (d.kind == PET_SCANNER_CYLINDER) {
+            z1[p] = (planes[p].r1 - 0.5 * (d.n_rings - 1)) * d.ring_pitch_mm;
+            z2[p] = (planes[p].r2 - 0.5 * (d.n_rings - 1)) * d.ring_pitch_mm;
+        } else {
+            z1[p] = z2[p] = 0.0;
+        }
+        max_dz = std::max(max_dz, std::fabs(z2[p] - z1[p]));
+    }
+    std::vector<PlaneP> hplanes(planes.size());
+    for (size_t p = 0; p < planes.size(); ++p) {
+        hplanes[p].zb = (float)((z1[p] - O[2]) / V[2]);
+        hplanes[p].zs = (float)((z2[p] - z1[p]) / V[2]);
+        hplanes[p].dz2 = (float)((z2[p] - z1[p]) * (z2[p] - z1[p]));
+        hplanes[p].seg = planes[p].seg;
+    }
+
+    // line table
+    const int nl = d.n_views * d.n_rad;
+    std::vector<LineP> hlines(nl);
+    int rows_max = 0;
+    for (int v = 0; v < d.n_views; ++v) {
+        double phi = M_PI * v / d.n_views;
+        double nx_ = std::cos(phi), ny_ = std::sin(phi), tx = -std::sin(phi), ty = std::cos(phi);
+        for (int k = 0; k < d.n_rad; ++k) {
+            double s, h;
+            if (d.kind == PET_SCANNER_CYLINDER) {
+                s = d.radius_mm * std::sin(M_PI * (k - 0.5 * (d.n_rad - 1)) / d.n_crystals);
+                h = std::sqrt(d.radius_mm * d.radius_mm - s * s);
+            } else {
+                s = (k - 0.5 * (d.n_rad - 1)) * d.rad_spacing_mm;
+                h = d.half_length_mm;
+            }
+            double p1[2] = {s * nx_ - h * tx, s * ny_ - h * ty};
+            double u[2] = {2 * h * tx, 2 * h * ty};
+            double rx = std::fabs(u[0]) / V[0], ry = std::fabs(u[1]) / V[1];
+            int m = (ry > rx * (1.0 + 1e-9)) ? 1 : 0;
+            double best = std::max(rx, ry);
+            if (max_dz / V[2] > best * (1.0 + 1e-9)) {
+                delete g;
+                return fail(PET_E_ARG, "pet_geom_create: some LOR has z as principal axis (unsupported)");
+            }
+            int a = 1 - m;
+            LineP L{};
+            double lam0 = (O[m] - p1[m]) / u[m];
+            double dlam = V[m] / u[m];
+            double xa0 = (p1[a] + lam0 * u[a] - O[a]) / V[a];
+            double dxa = dlam * u[a] / V[a];
+            double lo_c, hi_c;
+            if (dxa == 0.0) {
+                bool in = xa0 >= -1.5 && xa0 <= N[a] + 0.5;
+                lo_c = in ? 0 : 1;
+                hi_c = in ? N[m] - 1 : 0;
+            } else {
+                double ia = (-1.5 - xa0) / dxa, ib = (N[a] + 0.5 - xa0) / dxa;
+                lo_c = std::ceil(std::min(ia, ib));
+                hi_c = std::floor(std::max(ia, ib));
+            }
+            // clamp in floating point before converting (near-axis-aligned lines
+            // that miss the grid give bounds far outside the int range)
+            lo_c = std::max(0.0, lo_c);
+            hi_c = std::min((double)N[m] - 1, hi_c);
+            int i_lo = 1, i_hi = 0;
+            if (lo_c <= hi_c) {
+                i_lo = (int)lo_c;
+                i_hi = (int)hi_c;
+                double l_a = lam0 + i_lo * dlam, l_b = lam0 + i_hi * dlam;
+                if (std::min(l_a, l_b) < 0.0 || std::max(l_a, l_b) > 1.0) {
+                    delete g;
+                    return fail(PET_E_ARG, "pet_geom_create: LOR endpoints lie inside the padded image box");
+                }
+                rows_max = std::max(rows_max, i_hi - i_lo + 1);
+            }
+            L.lam0 = (float)lam0;
+            L.dlam = (float)dlam;
+            L.xa0 = (float)xa0;
+            L.dxa = (float)dxa;
+            L.vm_um = (float)(V[m] / std::fabs(u[m]));
+            L.lt2 = (float)(u[0] * u[0] + u[1] * u[1]);
+            L.i_lo = (int16_t)i_lo;
+            L.i_hi = (int16_t)i_hi;
+            L.axis = m;
+            hlines[(size_t)v * d.n_rad + k] = L;
+        }
+    }
+
+    // subsets: views v = i (mod n)
+    g->subset_views.resize(d.n_subsets);
+    for (int v = 0; v < d.n_views; ++v) g->subset_views[v % d.n_subsets].push_back(v);
+    g->max_views = (int)g->subset_views[0].size();
+    g->views_stride = d.n_views;
+    std::vector<int> hviews((size_t)(d.n_subsets + 1) * d.n_views, 0);
+    for (int i = 0; i < d.n_subsets; ++i)
+        for (size_t j = 0; j < g->subset_views[i].size(); ++j) hviews[(size_t)i * d.n_views + j] = g->subset_views[i][j];
+    for (int v = 0; v < d.n_views; ++v) hviews[(size_t)d.n_subsets * d.n_views + v] = v;
+
+    // TOF tables
+    TofTable &T = g->tof;
+    T.n_tof = d.n_tof;
+    std::vector<float> hlut;
+    if (d.n_tof > 1) {
+        double cut = 0.5 * d.tof_bin_mm + d.tof_nsigma * d.tof_sigma_mm;  // support of a bin's weight
+        std::vector<double> tb(d.n_tof), edges;
+        for (int b = 0; b < d.n_tof; ++b) {
+            tb[b] = (b - 0.5 * (d.n_tof - 1)) * d.tof_bin_mm;
+            T.tb[b] = (float)tb[b];
+            edges.push_back(tb[b] - cut);
+            edges.push_back(tb[b] + cut);
+        }
+        std::sort(edges.begin(), edges.end());
+        std::vector<double> ue;
+        for (double e : edges)
+            if (ue.empty() || e - ue.back() > 1e-9 * (1.0 + std::fabs(e))) ue.push_back(e);
+        T.n_int = (int)ue.size() - 1;
+        for (size_t e = 0; e < ue.size(); ++e) T.edge[e] = (float)ue[e];
+        for (int s = 0; s < T.n_int; ++s) {
+            double mid = 0.5 * (ue[s] + ue[s + 1]);
+            int bf = -1, bl = -1;
+            for (int b = 0; b < d.n_tof; ++b)
+                if (std::fabs(mid - tb[b]) <= cut) {
+                    if (bf < 0) bf = b;
+                    bl = b;
+                }
+            if (bf < 0) {
+                bf = 0;
+                bl = -1;
+            }
+            T.bf[s] = bf;
+            T.na[s] = bl - bf + 1;
+            if (T.na[s] > 8) {
+                delete g;
+                return fail(PET_E_ARG, "pet_geom_create: more than 8 TOF bins overlap at one point");
+            }
+        }
+        hlut.resize(LUT_N + 1);
+        for (int j = 0; j <= LUT_N; ++j)
+            hlut[j] = (float)tof_weight(cut * j / LUT_N, 0.5 * d.tof_bin_mm, d.tof_sigma_mm, d.tof_nsigma);
+        T.lut_inv_h = (float)(LUT_N / cut);
+    } else {
+        T.n_int = 0;
+    }
+
+    // LDS need of the line kernels: image sheet + gradient sheet (+ TOF table)
+    int rz = d.nz + 2 * PADZ;
+    g->lds_bytes = (size_t)2 * rows_max * rz * sizeof(float) + (d.n_tof > 1 ? (LUT_N + 1) * sizeof(float) : 0);
+    int max_lds = 0;
+    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device);
+    if (max_lds > 0 && g->lds_bytes > (size_t)max_lds) {
+        delete g;
+        return fail(PET_E_ARG, "pet_geom_create: image too large for the LDS sheets of the line kernels (" +
+                                   std::to_string(g->lds_bytes) + " > " + std::to_string(max_lds) + " bytes)");
+    }
+
+    // device allocations
+    auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes == 0 ? 16 : bytes) == hipSuccess; };
+    g->t0_elems = (size_t)d.nx * (d.ny + 2 * PADA) * rz;
+    g->t1_elems = (size_t)d.ny * (d.nx + 2 * PADA) * rz;
+    g->n_partial = std::max<size_t>(2 * (size_t)nl, (size_t)(g->n_vox + 255) / 256) + 64;
+    bool ok = alloc((void **)&g->lines, sizeof(LineP) * nl) && alloc((void **)&g->planes, sizeof(PlaneP) * planes.size()) &&
+              alloc((void **)&g->lut, sizeof(float) * (LUT_N + 1)) &&
+              alloc((void **)&g->views_dev, sizeof(int) * hviews.size()) &&
+              alloc((void **)&g->T0, sizeof(float) * g->t0_elems) && alloc((void **)&g->T1, sizeof(float) * g->t1_elems) &&
+              alloc((void **)&g->G0, sizeof(float) * g->t0_elems) && alloc((void **)&g->G1, sizeof(float) * g->t1_elems) &&
+              alloc((void **)&g->g, sizeof(float) * g->n_vox) && alloc((void **)&g->xtmp, sizeof(float) * g->n_vox) &&
+              alloc((void **)&g->grad, sizeof(float) * g->n_vox) && alloc((void **)&g->hess, sizeof(float) * g->n_vox) &&
+              alloc((void **)&g->num, sizeof(float) * g->n_vox) && alloc((void **)&g->sensi, sizeof(float) * g->n_vox) &&
+              alloc((void **)&g->partial, sizeof(double) * g->n_partial) && alloc((void **)&g->dscratch, sizeof(double) * 16) &&
+              alloc((void **)&g->fscratch, sizeof(float) * 16);
+    if (!ok) {
+        pet_geom_destroy(g);
+        return fail(PET_E_OOM, "pet_geom_create: device allocation failed");
+    }
+    hipError_t e = hipMemcpy(g->lines, hlines.data(), sizeof(LineP) * nl, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->planes, hplanes.data(), sizeof(PlaneP) * planes.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->views_dev, hviews.data(), sizeof(int) * hviews.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hlut.empty()) e = hipMemcpy(g->lut, hlut.data(), sizeof(float) * hlut.size(), hipMemcpyHostToDevice);
+    // padded sheet borders must be zero once; interiors are rewritten per use
+    if (e == hipSuccess) e = hipMemset(g->T0, 0, sizeof(float) * g->t0_elems);
+    if (e == hipSuccess) e = hipMemset(g->T1, 0, sizeof(float) * g->t1_elems);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        pet_geom_destroy(g);
+        return hip_check(e, "pet_geom_create");
+    }
+    *out = g;
+    return PET_OK;
+}
+
+extern "C" pet_status pet_geom_destroy(pet_geom g) {
+    if (!g) return PET_OK;
+    hipDeviceSynchronize();
+    for (auto &v : g->prof_events)
+        for (auto &e : v) g->prof_pool.push_back(e);
+    for (auto &e : g->prof_pool) {
+        hipEventDestroy(e.first);
+        hipEventDestroy(e.second);
+    }
+    void *ptrs[] = {g->lines, g->planes, g->lut, g->views_dev, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
+                    g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    delete g;
+    return PET_OK;
+}
+
+extern "C" pet_status pet_geom_info(pet_geom g, int subset, int64_t *n_bins, int64_t *n_lors, int64_t *n_vox) {
+    if (!g) return fail(PET_E_ARG, "pet_geom_info: null handle");
+    if (subset < -1 || subset >= g->d.n_subsets) return fail(PET_E_ARG, "pet_geom_info: subset out of range");
+    int64_t nv = subset < 0 ? g->d.n_views : (int64_t)g->subset_views[subset].size();
+    int64_t lors = nv * g->d.n_rad * g->n_planes;
+    if (n_lors) *n_lors = lors;
+    if (n_bins) *n_bins = lors * g->d.n_tof;
+    if (n_vox) *n_vox = g->n_vox;
+    return PET_OK;
+}

@@ -1,0 +1,354 @@
+// Image-space kernels for gfx950: transposed sheet images for the line
+// kernels, the relative-difference-prior stencil fused with the prior-aware
+// preconditioner and the preconditioned SVRG step, snapshot accumulation in
+// FP64, the OSEM multiplicative update and deterministic FP64 reductions.
+#include "pet_internal.h"
+
+namespace pet {
+namespace {
+
+constexpr int IMG_BLOCK = 256;
+
+// x [iz][iy][ix] -> T0 [ix][iy + PADA][iz + PADZ] and T1 [iy][ix + PADA][iz + PADZ]
+// (interiors only; the zero borders are set once at creation).
+__global__ void k_to_sheets(const float *__restrict__ x, float *__restrict__ T0, float *__restrict__ T1,
+                            int nx, int ny, int nz, int rz) {
+    int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int ix = v % nx;
+        int iy = (v / nx) % ny;
+        int iz = v / ((int64_t)nx * ny);
+        float val = x[v];
+        T0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + iz + PADZ] = val;
+        T1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + iz + PADZ] = val;
+    }
+}
+
+__global__ void k_fill(float *__restrict__ p, int64_t n, float val) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
+}
+
+__device__ __forceinline__ float sheet_value(const float *G0, const float *G1, int ix, int iy, int iz, int nx,
+                                             int ny, int rz) {
+    return G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + iz + PADZ] +
+           G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + iz + PADZ];
+}
+
+__global__ void k_from_sheets(const float *__restrict__ G0, const float *__restrict__ G1, float *__restrict__ out,
+                              int nx, int ny, int nz, int rz, int accumulate) {
+    int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int ix = v % nx;
+        int iy = (v / nx) % ny;
+        int iz = v / ((int64_t)nx * ny);
+        float s = sheet_value(G0, G1, ix, iy, iz, nx, ny, rz);
+        out[v] = accumulate ? out[v] + s : s;
+    }
+}
+
+struct W27 {
+    float w[27];
+};
+
+enum RdpFlags {
+    R_GRAD_OUT = 1,   // write beta * grad S
+    R_HESS_OUT = 2,   // write beta * diag Hess S
+    R_VALUE = 4,      // per-block FP64 partial sums of beta * S
+    R_PRECOND = 8,    // write D = (x + delta) / (sens + alpha beta H (x + delta))
+    R_UPDATE = 16,    // SVRG step with clip into x_out
+    R_SNAPSHOT = 32,  // estimator is ghat + beta grad S (snapshot iteration)
+};
+
+struct RdpArgs {
+    const float *x, *kappa;
+    W27 w;
+    float beta, gamma, eps;
+    int nx, ny, nz;
+    float *grad, *hess;
+    double *partial;
+    // preconditioner
+    const float *sens;
+    float alpha, delta;
+    float *D;
+    // update
+    const float *gi, *ghat_i;
+    const double *ghat;
+    float n_sub, tau;
+    float *x_out;
+};
+
+// One thread per voxel.  RDP (eq. (rdp)) with gradient and Hessian diagonal as
+// in Appendix A: d = x_i - x_j, s = x_i + x_j, phi = s + gamma |d| + eps,
+//   dS/dx_i += w k_i k_j d (2 phi - (d + gamma |d|)) / phi^2
+//   d2S/dx_i^2 += 2 w k_i k_j (s - d + eps)^2 / phi^3
+//   S += 1/2 w k_i k_j d^2 / phi   (each ordered pair once, halved).
+template <int F>
+__global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
+    const int64_t n = (int64_t)a.nx * a.ny * a.nz;
+    const int64_t v = blockIdx.x * (int64_t)IMG_BLOCK + threadIdx.x;
+    double val = 0.0;
+    if (v < n) {
+        const int ix = v % a.nx;
+        const int iy = (v / a.nx) % a.ny;
+        const int iz = v / ((int64_t)a.nx * a.ny);
+        const float xi = a.x[v];
+        const float ki = a.kappa ? a.kappa[v] : 1.f;
+        float g = 0.f, h = 0.f, sv = 0.f;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int jz = iz + dz;
+            if (jz < 0 || jz >= a.nz) continue;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int jy = iy + dy;
+                if (jy < 0 || jy >= a.ny) continue;
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    const int jx = ix + dx;
+                    if (jx < 0 || jx >= a.nx) continue;
+                    const int64_t u = ((int64_t)jz * a.ny + jy) * a.nx + jx;
+                    const float xj = a.x[u];
+                    const float wk = a.w.w[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] * ki * (a.kappa ? a.kappa[u] : 1.f);
+                    const float d = xi - xj;
+                    const float ad = fabsf(d);
+                    const float phi = xi + xj + a.gamma * ad + a.eps;
+                    const float rphi = 1.f / phi;
+                    g = fmaf(wk * d * (2.f * phi - (d + a.gamma * ad)), rphi * rphi, g);
+                    if (F & (R_HESS_OUT | R_PRECOND)) {
+                        const float c = 2.f * xj + a.eps;  // s - d + eps
+                        h = fmaf(2.f * wk * c * c, rphi * rphi * rphi, h);
+                    }
+                    if (F & R_VALUE) sv = fmaf(wk * d * d, rphi, sv);
+                }
+            }
+        }
+        const float bg = a.beta * g;
+        const float bh = a.beta * h;
+        if (F & R_GRAD_OUT) a.grad[v] = bg;
+        if (F & R_HESS_OUT) a.hess[v] = bh;
+        if (F & R_VALUE) val = 0.5 * (double)a.beta * (double)sv;
+        float Dv = 0.f;
+        if (F & R_PRECOND) {
+            const float xd = xi + a.delta;
+            const float den = a.sens[v] + a.alpha * bh * xd;
+            Dv = den != 0.f ? xd / den : 0.f;
+            a.D[v] = Dv;
+        } else if (F & R_UPDATE) {
+            Dv = a.D[v];
+        }
+        if (F & R_UPDATE) {
+            float est;
+            if (F & R_SNAPSHOT) {
+                est = (float)a.ghat[v] + bg;
+            } else {
+                est = fmaf(a.n_sub, a.gi[v] - a.ghat_i[v], (float)a.ghat[v]) + bg;
+            }
+            a.x_out[v] = fmaxf(0.f, fmaf(-a.tau * Dv, est, xi));
+        }
+    }
+    if (F & R_VALUE) {
+        __shared__ double red[IMG_BLOCK / 64];
+        for (int off = 32; off > 0; off >>= 1) val += __shfl_down(val, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = val;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < IMG_BLOCK / 64; ++w) s += red[w];
+            a.partial[blockIdx.x] = s;
+        }
+    }
+}
+
+__global__ void k_precond(const float *__restrict__ x, const float *__restrict__ sens, const float *__restrict__ hess,
+                          float alpha, float delta, float *__restrict__ D, int64_t n) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const float xd = x[v] + delta;
+        const float den = sens[v] + alpha * hess[v] * xd;
+        D[v] = den != 0.f ? xd / den : 0.f;
+    }
+}
+
+// ghat_i = g (data gradient of subset i at the snapshot); ghat (+)= g in FP64.
+__global__ void k_snapshot_accum(const float *__restrict__ G0, const float *__restrict__ G1, float *__restrict__ ghat_i,
+                                 double *__restrict__ ghat, float *__restrict__ gcopy, int nx, int ny, int nz, int rz,
+                                 int first) {
+    int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int ix = v % nx;
+        int iy = (v / nx) % ny;
+        int iz = v / ((int64_t)nx * ny);
+        float s = sheet_value(G0, G1, ix, iy, iz, nx, ny, rz);
+        ghat_i[v] = s;
+        if (gcopy) gcopy[v] = s;
+        ghat[v] = first ? (double)s : ghat[v] + (double)s;
+    }
+}
+
+__global__ void k_osem_update(float *__restrict__ x, const float *__restrict__ num, const float *__restrict__ sens,
+                              int64_t n) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        float s = sens[v];
+        if (s > 0.f) x[v] = x[v] * num[v] / s;
+    }
+}
+
+// Single-block deterministic reductions.
+__global__ void k_reduce_sum(const double *__restrict__ p, int n, double *__restrict__ out, int accumulate) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += p[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = accumulate ? *out + red[0] : red[0];
+}
+
+__global__ void k_max(const float *__restrict__ x, int64_t n, float *__restrict__ out) {
+    __shared__ float red[1024];
+    float m = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, x[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_copy(float *__restrict__ d, const float *__restrict__ s, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+inline dim3 grid_for(int64_t n) {
+    int64_t b = (n + IMG_BLOCK - 1) / IMG_BLOCK;
+    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 65536));
+}
+
+template <int F>
+hipError_t rdp_launch(const RdpArgs &a, int64_t n, hipStream_t s) {
+    dim3 grid((unsigned)((n + IMG_BLOCK - 1) / IMG_BLOCK));
+    hipLaunchKernelGGL((k_rdp<F>), grid, dim3(IMG_BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_to_sheets(const pet_geom_s *g, const float *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, g->T0, g->T1, g->d.nx, g->d.ny,
+                       g->d.nz, g->d.nz + 2 * PADZ);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_sheets(const pet_geom_s *g, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t0_elems), dim3(IMG_BLOCK), 0, s, g->G0, (int64_t)g->t0_elems, 0.f);
+    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t1_elems), dim3(IMG_BLOCK), 0, s, g->G1, (int64_t)g->t1_elems, 0.f);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_sheets(const pet_geom_s *g, float *out, int accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, out, g->d.nx, g->d.ny,
+                       g->d.nz, g->d.nz + 2 * PADZ, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_rdp(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
+                      float gamma, float eps, float *grad, float *hess, double *partial, hipStream_t s) {
+    RdpArgs a{};
+    a.x = x;
+    a.kappa = kappa;
+    for (int i = 0; i < 27; ++i) a.w.w[i] = w27[i];
+    a.beta = beta;
+    a.gamma = gamma;
+    a.eps = eps;
+    a.nx = g->d.nx;
+    a.ny = g->d.ny;
+    a.nz = g->d.nz;
+    a.grad = grad;
+    a.hess = hess;
+    a.partial = partial;
+    int f = (grad ? 1 : 0) | (hess ? 2 : 0) | (partial ? 4 : 0);
+    switch (f) {
+        case 1: return rdp_launch<R_GRAD_OUT>(a, g->n_vox, s);
+        case 2: return rdp_launch<R_HESS_OUT>(a, g->n_vox, s);
+        case 3: return rdp_launch<R_GRAD_OUT | R_HESS_OUT>(a, g->n_vox, s);
+        case 4: return rdp_launch<R_VALUE>(a, g->n_vox, s);
+        case 5: return rdp_launch<R_GRAD_OUT | R_VALUE>(a, g->n_vox, s);
+        case 6: return rdp_launch<R_HESS_OUT | R_VALUE>(a, g->n_vox, s);
+        case 7: return rdp_launch<R_GRAD_OUT | R_HESS_OUT | R_VALUE>(a, g->n_vox, s);
+        default: return hipSuccess;
+    }
+}
+
+int rdp_blocks(const pet_geom_s *g) { return (int)((g->n_vox + IMG_BLOCK - 1) / IMG_BLOCK); }
+
+hipError_t launch_precond(const pet_geom_s *g, const float *x, const float *sens, const float *hess, float alpha,
+                          float delta, float *D, hipStream_t s) {
+    hipLaunchKernelGGL(k_precond, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, sens, hess, alpha, delta, D, g->n_vox);
+    return hipGetLastError();
+}
+
+hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
+                            float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
+                            float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
+                            float n_sub, float tau, float *x_out, hipStream_t s) {
+    RdpArgs a{};
+    a.x = x;
+    a.kappa = kappa;
+    for (int i = 0; i < 27; ++i) a.w.w[i] = w27[i];
+    a.beta = beta;
+    a.gamma = gamma;
+    a.eps = eps;
+    a.nx = g->d.nx;
+    a.ny = g->d.ny;
+    a.nz = g->d.nz;
+    a.sens = sens;
+    a.alpha = alpha;
+    a.delta = delta;
+    a.D = D;
+    a.gi = gi;
+    a.ghat_i = ghat_i;
+    a.ghat = ghat;
+    a.n_sub = n_sub;
+    a.tau = tau;
+    a.x_out = x_out;
+    if (update_pc) {
+        if (snapshot) return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
+        return rdp_launch<R_PRECOND | R_UPDATE>(a, g->n_vox, s);
+    }
+    if (snapshot) return rdp_launch<R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
+    return rdp_launch<R_UPDATE>(a, g->n_vox, s);
+}
+
+hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_snapshot_accum, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, ghat_i, ghat, gcopy,
+                       g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_sum(const double *partial, int n, double *out, int accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(1024), 0, s, partial, n, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s) {
+    hipLaunchKernelGGL(k_osem_update, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, num, sens, g->n_vox);
+    return hipGetLastError();
+}
+
+hipError_t launch_max(const pet_geom_s *g, const float *x, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, s, x, g->n_vox, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, grid_for(n), dim3(IMG_BLOCK), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace pet

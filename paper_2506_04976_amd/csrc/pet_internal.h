@@ -1,0 +1,140 @@
+// Internal declarations of the gfx950 PET library: device geometry tables,
+// kernel argument blocks and launch helpers shared by the host entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/pet.h"
+
+namespace pet {
+
+// Padding (voxels) of the transposed "sheet" images on each side of the
+// transaxial interpolation axis and of z.  Samples may sit up to 1.5 voxels
+// outside the grid (conservative sample ranges); padded zeros make them exact.
+constexpr int PADA = 2;
+constexpr int PADZ = 2;
+constexpr int NT_MAX = 16;     // TOF bins supported
+constexpr int NINT_MAX = 2 * NT_MAX + 1;
+constexpr int LUT_N = 4096;    // TOF weight table: W(|d|) on [0, bin/2 + nsig sigma]
+constexpr int LINE_BLOCK = 256;
+
+// One transaxial line (view, radial): sample i along the principal axis m sits
+// at lambda(i) = lam0 + i dlam on the LOR; its coordinate along the other
+// transaxial axis, in voxel units, is xa0 + i dxa.  Samples outside
+// [i_lo, i_hi] cannot touch the grid (i_lo > i_hi: line misses the image).
+struct LineP {
+    float lam0, dlam, xa0, dxa;
+    float vm_um;  // v_m / |u_m|: step length = vm_um * |u|
+    float lt2;    // squared transaxial length of u
+    int16_t i_lo, i_hi;
+    int32_t axis; // principal axis: 0 = x, 1 = y
+};
+static_assert(sizeof(LineP) == 32, "LineP layout");
+
+// One plane (ring pair): z index coordinate of a sample is zb + lambda zs.
+struct PlaneP {
+    float zb, zs, dz2;
+    int32_t seg;
+};
+
+// TOF interval table.  The t axis (signed distance from the LOR centre) is cut
+// at every support edge t_b -/+ (bin/2 + nsig sigma) of a bin's weight; inside
+// interval s the bins with nonzero weight are bf[s] .. bf[s] + na[s] - 1.
+struct TofTable {
+    int n_tof;
+    int n_int;
+    float edge[NINT_MAX + 1];
+    int bf[NINT_MAX];
+    int na[NINT_MAX];
+    float tb[NT_MAX];
+    float lut_inv_h;  // LUT index = |t - t_b| * lut_inv_h
+};
+
+enum Mode { M_FWD = 0, M_BACK = 1, M_GRAD = 2, M_EM = 3, M_OBJ = 4, M_COUNT = 5, M_NMODES = 6 };
+
+struct ProjArgs {
+    const LineP *lines;
+    const PlaneP *planes;
+    const float *lut;
+    const int *views;
+    int n_rad, n_planes, nx, ny, nz, rz;
+    // transposed padded images: T[0] principal x: [nx][ny+4][nz+4]; T[1] principal y: [ny][nx+4][nz+4]
+    const float *T0, *T1;
+    float *G0, *G1;
+    const void *y;
+    int y_dtype;
+    const float *add, *mult, *sino;
+    float *out;
+    double *partial;  // one double per block (KL sum), or null
+    TofTable tof;
+};
+
+}  // namespace pet
+
+struct pet_geom_s {
+    pet_geom_desc d;
+    int device;
+    int n_planes;
+    int64_t n_vox;
+    int max_views;                      // views per subset (max)
+    std::vector<std::vector<int>> subset_views;
+    std::vector<int> seg_of_plane;
+    // device tables
+    pet::LineP *lines = nullptr;
+    pet::PlaneP *planes = nullptr;
+    float *lut = nullptr;
+    int *views_dev = nullptr;           // [n_subsets + 1][max(max_views, n_views)]; last row: all views
+    int views_stride = 0;
+    pet::TofTable tof{};
+    size_t lds_bytes = 0;
+    // scratch arena
+    float *T0 = nullptr, *T1 = nullptr, *G0 = nullptr, *G1 = nullptr;
+    size_t t0_elems = 0, t1_elems = 0;
+    float *g = nullptr, *xtmp = nullptr, *grad = nullptr, *hess = nullptr, *num = nullptr, *sensi = nullptr;
+    double *partial = nullptr;
+    size_t n_partial = 0;
+    double *dscratch = nullptr;         // a few device doubles
+    float *fscratch = nullptr;          // a few device floats
+    // optional HIP-event timing of the line kernels, per mode
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[pet::M_NMODES];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
+};
+
+namespace pet {
+
+// error state (api.cpp)
+pet_status fail(pet_status s, const std::string &msg);
+pet_status hip_check(hipError_t e, const char *what);
+
+// projector launches (proj.hip)
+hipError_t launch_line_kernel(pet_geom_s *g, int mode, int subset, const ProjArgs &a, hipStream_t s);
+int n_line_blocks(const pet_geom_s *g, int subset);
+
+// image kernels (image.hip)
+hipError_t launch_to_sheets(const pet_geom_s *g, const float *x, hipStream_t s);
+hipError_t launch_zero_sheets(const pet_geom_s *g, hipStream_t s);
+hipError_t launch_from_sheets(const pet_geom_s *g, float *out, int accumulate, hipStream_t s);
+hipError_t launch_rdp(const pet_geom_s *g, const float *x, const float *kappa, const float *w27,
+                      float beta, float gamma, float eps, float *grad, float *hess, double *partial,
+                      hipStream_t s);
+hipError_t launch_precond(const pet_geom_s *g, const float *x, const float *sens, const float *hess,
+                          float alpha, float delta, float *D, hipStream_t s);
+hipError_t launch_reduce_sum(const double *partial, int n, double *out, int accumulate, hipStream_t s);
+hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s);
+hipError_t launch_max(const pet_geom_s *g, const float *x, float *out, hipStream_t s);
+hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
+                            float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
+                            float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
+                            float n_sub, float tau, float *x_out, hipStream_t s);
+hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
+                                 hipStream_t s);
+int rdp_blocks(const pet_geom_s *g);
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
+
+}  // namespace pet

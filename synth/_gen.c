@@ -41,13 +41,20 @@ static int ellipsoid_hit(const double *sh, const double p1[3], const double u[3]
 
 static double G(double z) { return z * erf(z) + exp(-z * z) / sqrt(M_PI); }
 
-/* Integral over t in [A, B] of the bin-integrated Gaussian TOF kernel of bin
- * centre tb and half-width h. */
-static double tof_seg(double A, double B, double tb, double h, double sigma) {
+/* F(u) = integral from 0 to u of erf(clamp(v / s, -c, c)) dv (even in u);
+ * c <= 0 means no clamp. */
+static double F(double u, double s, double c) {
+    double v = fabs(u);
+    if (c <= 0 || v <= c * s) return s * (G(v / s) - 1.0 / sqrt(M_PI));
+    return s * (G(c) - 1.0 / sqrt(M_PI)) + erf(c) * (v - c * s);
+}
+
+/* Integral over t in [A, B] of the TOF weight of bin centre tb and half-width
+ * h: the Gaussian kernel truncated to +-nsig sigma, integrated over the bin. */
+static double tof_seg(double A, double B, double tb, double h, double sigma, double nsig) {
     if (B <= A) return 0.0;
-    double s = sqrt(2.0) * sigma;
-    return 0.5 * s * (G((tb + h - A) / s) - G((tb + h - B) / s)
-                      - G((tb - h - A) / s) + G((tb - h - B) / s));
+    double s = sqrt(2.0) * sigma, c = nsig > 0 ? nsig / sqrt(2.0) : 0.0;
+    return 0.5 * (F(tb + h - A, s, c) - F(tb + h - B, s, c) - F(tb - h - A, s, c) + F(tb - h - B, s, c));
 }
 
 /* Line integrals of the phantom for lines x planes (x TOF bins).
@@ -80,12 +87,12 @@ void gen_project(long n_lines, const double *p1xy, const double *p2xy, long n_pl
                 } else {
                     for (int b = 0; b < n_tof; ++b) {
                         double A = t0, B = t1;
-                        if (nsig > 0) {
-                            double lo = tb[b] - nsig * sigma, hi = tb[b] + nsig * sigma;
+                        if (nsig > 0) {  /* the weight vanishes beyond h + nsig sigma */
+                            double lo = tb[b] - 0.5 * tof_bin - nsig * sigma, hi = tb[b] + 0.5 * tof_bin + nsig * sigma;
                             if (A < lo) A = lo;
                             if (B > hi) B = hi;
                         }
-                        acc[b] += sh[7] * tof_seg(A, B, tb[b], 0.5 * tof_bin, sigma);
+                        acc[b] += sh[7] * tof_seg(A, B, tb[b], 0.5 * tof_bin, sigma, nsig);
                     }
                 }
             }

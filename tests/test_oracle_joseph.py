@@ -159,38 +159,41 @@ def test_tof_partition_of_unity_untruncated(oracle_built):
     assert np.allclose(tof.sum(1), nontof, rtol=1e-12, atol=1e-12 * nontof.max())
 
 
-def test_tof_truncated_weight_sum_range(oracle_built):
-    # 13 bins of 40 mm, sigma 25.48 mm, truncated at 3 sigma from the bin centre:
-    # the weights of a sample near the LOR centre sum to a value in [0.980, 0.999).
-    cfg = dict(_grid(3, 3, 1, 2.0, 2.0, 2.0), n_tof=13, tof_bin=40.0,
-               tof_sigma=60.0 * configs.FWHM_TO_SIGMA, tof_nsigma=3.0)
+def test_tof_truncated_weights_sum_to_erf(oracle_built):
+    # The truncated Gaussian (+-3 sigma around the event) integrated over bins
+    # that cover its whole window telescopes to the kernel's mass inside the
+    # window: sum_b w_b = erf(3 / sqrt 2) exactly, wherever the event sits.
+    sig = 60.0 * configs.FWHM_TO_SIGMA
+    cfg = dict(_grid(3, 3, 1, 2.0, 2.0, 2.0), n_tof=13, tof_bin=40.0, tof_sigma=sig, tof_nsigma=3.0)
     x = np.zeros((1, 3, 3))
     x[0, 1, 1] = 1.0
-    sums = []
-    for off in np.linspace(-120, 120, 97):
-        p1 = np.array([[-300.0 - off, 0.0, 0.0]])
-        p2 = np.array([[300.0 - off, 0.0, 0.0]])
+    for off in np.linspace(-150, 150, 61):
+        p1 = np.array([[-400.0 - off, 0.0, 0.0]])
+        p2 = np.array([[400.0 - off, 0.0, 0.0]])
         tof = projector.fwd(cfg, x, p1, p2, tof=True)[0]
         nontof = projector.fwd(cfg, x, p1, p2, tof=False)[0, 0]
-        sums.append(tof.sum() / nontof)
-    sums = np.array(sums)
-    assert sums.min() > 0.980 and sums.max() < 0.999
+        assert tof.sum() / nontof == pytest.approx(math.erf(3 / math.sqrt(2)), rel=1e-13)
 
 
-def test_tof_kernel_peak_and_symmetry(oracle_built):
+def test_tof_kernel_centre_bin_and_support(oracle_built):
     # A source at the LOR centre: bins symmetric about the centre bin; the centre
-    # bin weight is erf(20 / (sqrt(2) sigma)) (bin-integrated Gaussian).
+    # bin holds erf(20 / (sqrt(2) sigma)) (window +-76.4 mm covers the bin);
+    # a bin whose nearest edge is farther than 3 sigma (centre 120 mm away,
+    # edge at 100 mm) gets nothing; the bins 80 mm away keep their overlap with
+    # the window, [60, 76.4] mm.
     sig = 60.0 * configs.FWHM_TO_SIGMA
     cfg = dict(_grid(3, 3, 1, 2.0, 2.0, 2.0), n_tof=13, tof_bin=40.0, tof_sigma=sig, tof_nsigma=3.0)
     x = np.zeros((1, 3, 3))
     x[0, 1, 1] = 1.0
     p1 = np.array([[-300.0, 0.0, 0.0]])
     p2 = np.array([[300.0, 0.0, 0.0]])
-    tof = projector.fwd(cfg, x, p1, p2, tof=True)[0]
+    tof = projector.fwd(cfg, x, p1, p2, tof=True)[0] / 2.0  # step length 2 mm
     assert np.allclose(tof, tof[::-1], rtol=1e-13)
-    assert tof[6] == pytest.approx(2.0 * math.erf(20 / (math.sqrt(2) * sig)), rel=1e-13)
-    assert tof[6 - 2] == 0.0 and tof[6 + 2] == 0.0  # 80 mm > 3 sigma (76.4 mm)
-    assert tof[5] > 0
+    assert tof[6] == pytest.approx(math.erf(20 / (math.sqrt(2) * sig)), rel=1e-13)
+    assert tof[3] == 0.0 and tof[9] == 0.0
+    gauss_mass_60_to_cut = 0.5 * (math.erf(3 / math.sqrt(2)) - math.erf(60 / (math.sqrt(2) * sig)))
+    assert tof[4] == pytest.approx(gauss_mass_60_to_cut, rel=1e-13)
+    assert tof.sum() == pytest.approx(math.erf(3 / math.sqrt(2)), rel=1e-13)
 
 
 def test_parallel_beam_mass_at_grid_angles(oracle_built):
