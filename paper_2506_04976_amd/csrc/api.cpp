@@ -36,8 +36,12 @@ ProjArgs base_args(pet_geom g, int subset) {
     ProjArgs a{};
     a.lines = g->lines;
     a.planes = g->planes;
-    a.lut = g->lut;
     a.views = views_of(g, subset);
+    a.segs = g->segs;
+    a.n_seg = g->n_seg;
+    a.rows_max = g->rows_max;
+    a.ws = g->tof_ws;
+    a.tstride = g->tof_tstride;
     a.n_rad = g->d.n_rad;
     a.n_planes = g->n_planes;
     a.nx = g->d.nx;

@@ -37,15 +37,6 @@ std::vector<Plane> make_planes(const pet_geom_desc &d) {
     return out;
 }
 
-// TOF weight of a point at distance dist from a bin centre: the Gaussian kernel
-// truncated to +-nsig sigma around the point, integrated over the bin
-// (half-width half).  Continuous in dist; zero beyond half + nsig sigma.
-double tof_weight(double dist, double half, double sigma, double nsig) {
-    double s = std::sqrt(2.0) * sigma, c = nsig / std::sqrt(2.0);
-    auto E = [&](double u) { return std::erf(std::max(-c, std::min(c, u / s))); };
-    return 0.5 * (E(half - dist) - E(-half - dist));
-}
-
 pet_status validate(const pet_geom_desc &d) {
     if (d.kind != PET_SCANNER_PARALLEL2D && d.kind != PET_SCANNER_CYLINDER)
         return fail(PET_E_ARG, "pet_geom_create: unknown scanner kind");
@@ -200,7 +191,6 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     // TOF tables
     TofTable &T = g->tof;
     T.n_tof = d.n_tof;
-    std::vector<float> hlut;
     if (d.n_tof > 1) {
         double cut = 0.5 * d.tof_bin_mm + d.tof_nsigma * d.tof_sigma_mm;  // support of a bin's weight
         std::vector<double> tb(d.n_tof), edges;
@@ -235,20 +225,56 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
                 return fail(PET_E_ARG, "pet_geom_create: more than 8 TOF bins overlap at one point");
             }
         }
-        hlut.resize(LUT_N + 1);
-        for (int j = 0; j <= LUT_N; ++j)
-            hlut[j] = (float)tof_weight(cut * j / LUT_N, 0.5 * d.tof_bin_mm, d.tof_sigma_mm, d.tof_nsigma);
-        T.lut_inv_h = (float)(LUT_N / cut);
+        T.half_bin = (float)(0.5 * d.tof_bin_mm);
+        T.inv_sqrt2_sigma = (float)(1.0 / (std::sqrt(2.0) * d.tof_sigma_mm));
+        T.erf_clamp = (float)(d.tof_nsigma / std::sqrt(2.0));
     } else {
         T.n_int = 0;
     }
 
-    // LDS need of the line kernels: image sheet + gradient sheet (+ TOF table)
+    // segments (contiguous plane ranges of equal ring difference)
+    std::vector<SegP> hsegs;
+    for (size_t p = 0; p < planes.size(); ++p) {
+        if (hsegs.empty() || planes[p].seg != planes[p - 1].seg) hsegs.push_back({(int)p, 0, hplanes[p].dz2, 0});
+        hsegs.back().np++;
+    }
+    g->n_seg = (int)hsegs.size();
+    g->rows_max = rows_max;
+    if (d.n_tof > 1) {
+        for (auto &sg : hsegs)
+            if (sg.np > 64) {
+                delete g;
+                return fail(PET_E_ARG, "pet_geom_create: TOF needs at most 64 planes per segment (one wave)");
+            }
+        int ws = 1;
+        for (int s = 0; s < T.n_int; ++s) ws = std::max(ws, T.na[s]);
+        g->tof_ws = ws;
+        int rounds = (g->n_seg + TOF_MAX_WAVES - 1) / TOF_MAX_WAVES;
+        g->tof_waves = (g->n_seg + rounds - 1) / rounds;
+    }
+
+    // LDS need of the line kernels: image sheet (float) + gradient sheet
+    // (double) + per-wave TOF tables (weights [rows][4] + [rows][ws - 4] +
+    // interval cuts).  Fewer TOF waves are used if the tables do not fit.
     int rz = d.nz + 2 * PADZ;
-    g->lds_bytes = (size_t)2 * rows_max * rz * sizeof(float) + (d.n_tof > 1 ? (LUT_N + 1) * sizeof(float) : 0);
+    size_t sheet = ((size_t)rows_max * rz + 3) & ~(size_t)3;
     int max_lds = 0;
     hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device);
-    if (max_lds > 0 && g->lds_bytes > (size_t)max_lds) {
+    if (max_lds <= 0) max_lds = 64 * 1024;
+    size_t need = 3 * sheet * sizeof(float);
+    if (d.n_tof > 1) {
+        int e1 = g->tof_ws > 4 ? g->tof_ws - 4 : 0;
+        size_t per_wave = (((size_t)rows_max * (4 + e1) + CUTS_PAD + 3) & ~(size_t)3) * sizeof(float);
+        if (need + per_wave <= (size_t)max_lds) {
+            int fit = (int)(((size_t)max_lds - need) / per_wave);
+            if (fit < g->tof_waves) g->tof_waves = fit;
+        } else {
+            g->tof_waves = 1;
+        }
+        need += (size_t)g->tof_waves * per_wave;
+    }
+    g->lds_bytes = need;
+    if (g->lds_bytes > (size_t)max_lds) {
         delete g;
         return fail(PET_E_ARG, "pet_geom_create: image too large for the LDS sheets of the line kernels (" +
                                    std::to_string(g->lds_bytes) + " > " + std::to_string(max_lds) + " bytes)");
@@ -260,7 +286,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     g->t1_elems = (size_t)d.ny * (d.nx + 2 * PADA) * rz;
     g->n_partial = std::max<size_t>(2 * (size_t)nl, (size_t)(g->n_vox + 255) / 256) + 64;
     bool ok = alloc((void **)&g->lines, sizeof(LineP) * nl) && alloc((void **)&g->planes, sizeof(PlaneP) * planes.size()) &&
-              alloc((void **)&g->lut, sizeof(float) * (LUT_N + 1)) &&
+              alloc((void **)&g->segs, sizeof(SegP) * hsegs.size()) &&
               alloc((void **)&g->views_dev, sizeof(int) * hviews.size()) &&
               alloc((void **)&g->T0, sizeof(float) * g->t0_elems) && alloc((void **)&g->T1, sizeof(float) * g->t1_elems) &&
               alloc((void **)&g->G0, sizeof(float) * g->t0_elems) && alloc((void **)&g->G1, sizeof(float) * g->t1_elems) &&
@@ -275,8 +301,8 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     }
     hipError_t e = hipMemcpy(g->lines, hlines.data(), sizeof(LineP) * nl, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->planes, hplanes.data(), sizeof(PlaneP) * planes.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->segs, hsegs.data(), sizeof(SegP) * hsegs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->views_dev, hviews.data(), sizeof(int) * hviews.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !hlut.empty()) e = hipMemcpy(g->lut, hlut.data(), sizeof(float) * hlut.size(), hipMemcpyHostToDevice);
     // padded sheet borders must be zero once; interiors are rewritten per use
     if (e == hipSuccess) e = hipMemset(g->T0, 0, sizeof(float) * g->t0_elems);
     if (e == hipSuccess) e = hipMemset(g->T1, 0, sizeof(float) * g->t1_elems);
@@ -298,7 +324,7 @@ extern "C" pet_status pet_geom_destroy(pet_geom g) {
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);
     }
-    void *ptrs[] = {g->lines, g->planes, g->lut, g->views_dev, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
+    void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
                     g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch};
     for (void *p : ptrs)
         if (p) hipFree(p);

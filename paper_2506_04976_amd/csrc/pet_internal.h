@@ -20,8 +20,10 @@ constexpr int PADA = 2;
 constexpr int PADZ = 2;
 constexpr int NT_MAX = 16;     // TOF bins supported
 constexpr int NINT_MAX = 2 * NT_MAX + 1;
-constexpr int LUT_N = 4096;    // TOF weight table: W(|d|) on [0, bin/2 + nsig sigma]
-constexpr int LINE_BLOCK = 256;
+constexpr int NT_BLOCK = 768;   // non-TOF line kernel: threads per workgroup
+constexpr int TOF_MAX_WAVES = 16;  // TOF line kernel: at most 16 segment waves
+constexpr int WS_MAX = 8;       // TOF bins overlapping one point
+constexpr int CUTS_PAD = 36;    // per-wave TOF interval cut indices (>= NINT_MAX + 1, multiple of 4)
 
 // One transaxial line (view, radial): sample i along the principal axis m sits
 // at lambda(i) = lam0 + i dlam on the LOR; its coordinate along the other
@@ -42,6 +44,14 @@ struct PlaneP {
     int32_t seg;
 };
 
+// One segment (ring difference): planes p0 .. p0 + np - 1, all with the same
+// squared axial extent dz2 (so the same |u| on a given line).
+struct SegP {
+    int32_t p0, np;
+    float dz2;
+    int32_t pad;
+};
+
 // TOF interval table.  The t axis (signed distance from the LOR centre) is cut
 // at every support edge t_b -/+ (bin/2 + nsig sigma) of a bin's weight; inside
 // interval s the bins with nonzero weight are bf[s] .. bf[s] + na[s] - 1.
@@ -52,7 +62,9 @@ struct TofTable {
     int bf[NINT_MAX];
     int na[NINT_MAX];
     float tb[NT_MAX];
-    float lut_inv_h;  // LUT index = |t - t_b| * lut_inv_h
+    float half_bin;         // tof_bin / 2
+    float inv_sqrt2_sigma;  // 1 / (sqrt2 sigma)
+    float erf_clamp;        // nsig / sqrt2: truncation of the Gaussian kernel
 };
 
 enum Mode { M_FWD = 0, M_BACK = 1, M_GRAD = 2, M_EM = 3, M_OBJ = 4, M_COUNT = 5, M_NMODES = 6 };
@@ -60,9 +72,10 @@ enum Mode { M_FWD = 0, M_BACK = 1, M_GRAD = 2, M_EM = 3, M_OBJ = 4, M_COUNT = 5,
 struct ProjArgs {
     const LineP *lines;
     const PlaneP *planes;
-    const float *lut;
     const int *views;
+    const SegP *segs;
     int n_rad, n_planes, nx, ny, nz, rz;
+    int n_seg, rows_max, ws, tstride;  // TOF: segments, sheet rows (max), bins per point, table row stride
     // transposed padded images: T[0] principal x: [nx][ny+4][nz+4]; T[1] principal y: [ny][nx+4][nz+4]
     const float *T0, *T1;
     float *G0, *G1;
@@ -87,7 +100,8 @@ struct pet_geom_s {
     // device tables
     pet::LineP *lines = nullptr;
     pet::PlaneP *planes = nullptr;
-    float *lut = nullptr;
+    pet::SegP *segs = nullptr;
+    int n_seg = 0, rows_max = 0, tof_ws = 0, tof_tstride = 0, tof_waves = 0;
     int *views_dev = nullptr;           // [n_subsets + 1][max(max_views, n_views)]; last row: all views
     int views_stride = 0;
     pet::TofTable tof{};

@@ -1,5 +1,5 @@
 // Joseph projector kernels for gfx950 (forward, adjoint, fused subset gradient,
-// EM ratio, KL objective), line-driven with LDS sheets.
+// EM ratio, KL objective, work counts), line-driven with LDS sheets.
 //
 // Separability used here: every LOR of a transaxial line (view, radial) has the
 // same principal axis m, the same sample positions lambda(i) along m and the
@@ -8,12 +8,15 @@
 //   1. it interpolates the image once along the transaxial axis into an LDS
 //      "sheet" X[i][z] (rows i along m, z padded), reading a z-contiguous
 //      transposed copy of the image so the loads are coalesced;
-//   2. each thread takes planes (ring pairs) of the line and walks the samples
-//      with one linear interpolation in z from LDS per sample (TOF: weighted
-//      into the TOF bins through an interval table and a weight table in LDS);
+//   2. threads take the planes (ring pairs) of the line and walk the samples
+//      with one linear interpolation in z from LDS per sample;
 //   3. the adjoint accumulates Z[i][z] in LDS with LDS atomics and finally
 //      spreads the sheet back over the two transaxial neighbours with global
 //      atomics into a z-contiguous transposed gradient image.
+// TOF: all planes of one ring-difference segment share |u|, hence the signed
+// distance t(i) of every sample and its TOF weights.  One wave takes one
+// segment (one plane per lane), fills a table with the weights of the line's
+// samples (increasing-t order) once, and the lanes read it by broadcast.
 // The arithmetic is Joseph's: sample value = bilinear interpolation of the
 // image in the two non-principal axes, line integral = step length * sum.
 #include "pet_internal.h"
@@ -34,15 +37,7 @@ __device__ __forceinline__ double kl_term(float ybar, float yv) {
     return s;
 }
 
-__device__ __forceinline__ float tof_w(const float *lut, float d, float inv_h) {
-    float u = fminf(fabsf(d) * inv_h, (float)LUT_N);
-    int j = min((int)u, LUT_N - 1);
-    float f = u - (float)j;
-    float l0 = lut[j], l1 = lut[j + 1];
-    return fmaf(f, l1 - l0, l0);
-}
-
-// Number of samples (in increasing-t order) with t < e.
+// Number of samples of [is, ie] (in increasing-t order) with t < e.
 __device__ __forceinline__ int cut_count(float e, float len, float lam0, float dlam, int is, int ie) {
     float lam_e = e / len + 0.5f;
     float r = (lam_e - lam0) / dlam;
@@ -58,284 +53,32 @@ __device__ __forceinline__ int cut_count(float e, float len, float lam0, float d
     return c;
 }
 
-struct LorGeo {
-    float lam0, dlam, zb, zs, len;
-    int is, ie, ilo, rz;
-};
-
-// Forward TOF accumulation over the samples q in [c0, c1) of one interval with
-// NA active bins starting at bin bf.
-template <int NA>
-__device__ __forceinline__ void tof_fwd_run(const LorGeo &G, const float *X, const float *lut, float inv_h,
-                                            const float *tbj, int c0, int c1, float *win) {
-    for (int q = c0; q < c1; ++q) {
-        int i = G.dlam > 0.f ? G.is + q : G.ie - q;
-        float lam = fmaf((float)i, G.dlam, G.lam0);
-        float xz = fmaf(lam, G.zs, G.zb);
-        float jf = floorf(xz);
-        float f = xz - jf;
-        int r = (i - G.ilo) * G.rz + (int)jf + PADZ;
-        float x0 = X[r], x1 = X[r + 1];
-        float v = fmaf(f, x1 - x0, x0);
-        float t = (lam - 0.5f) * G.len;
-#pragma unroll
-        for (int j = 0; j < NA; ++j) win[j] = fmaf(v, tof_w(lut, t - tbj[j], inv_h), win[j]);
+// Sample range [is, ie] of a LOR restricted to samples whose z coordinate can
+// touch the grid (xi_z in [-1.5, nz + 0.5]).
+__device__ __forceinline__ void z_clip(const LineP &L, const PlaneP &P, int nz, int &is, int &ie) {
+    is = L.i_lo;
+    ie = L.i_hi;
+    if (P.zs != 0.f) {
+        float la = (-1.5f - P.zb) / P.zs, lb = ((float)nz + 0.5f - P.zb) / P.zs;
+        float ia = (fminf(la, lb) - L.lam0) / L.dlam, ib = (fmaxf(la, lb) - L.lam0) / L.dlam;
+        float lo = ceilf(fminf(ia, ib)), hi = floorf(fmaxf(ia, ib));
+        if (lo > (float)is) is = lo > (float)ie ? ie + 1 : (int)lo;
+        if (hi < (float)ie) ie = hi < (float)is ? is - 1 : (int)hi;
+    } else if (P.zb < -1.5f || P.zb > (float)nz + 0.5f) {
+        ie = is - 1;
     }
 }
 
-template <int NA>
-__device__ __forceinline__ void tof_back_run(const LorGeo &G, float *Z, const float *lut, float inv_h,
-                                             const float *tbj, int c0, int c1, const float *win) {
-    for (int q = c0; q < c1; ++q) {
-        int i = G.dlam > 0.f ? G.is + q : G.ie - q;
-        float lam = fmaf((float)i, G.dlam, G.lam0);
-        float xz = fmaf(lam, G.zs, G.zb);
-        float jf = floorf(xz);
-        float f = xz - jf;
-        int r = (i - G.ilo) * G.rz + (int)jf + PADZ;
-        float t = (lam - 0.5f) * G.len;
-        float Q = 0.f;
-#pragma unroll
-        for (int j = 0; j < NA; ++j) Q = fmaf(win[j], tof_w(lut, t - tbj[j], inv_h), Q);
-        float a1 = Q * f;
-        atomicAdd(&Z[r], Q - a1);
-        atomicAdd(&Z[r + 1], a1);
-    }
-}
-
-template <int W>
-__device__ __forceinline__ void tof_dispatch_fwd(int na, const LorGeo &G, const float *X, const float *lut,
-                                                 float inv_h, const float *tbj, int c0, int c1, float *win) {
-    switch (na) {
-        case 1: tof_fwd_run<1>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-        case 2: tof_fwd_run<2>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-        case 3: tof_fwd_run<3>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-        case 4: tof_fwd_run<4>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-        default:
-            if constexpr (W > 4) {
-                switch (na) {
-                    case 5: tof_fwd_run<5>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-                    case 6: tof_fwd_run<6>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-                    case 7: tof_fwd_run<7>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-                    default: tof_fwd_run<8>(G, X, lut, inv_h, tbj, c0, c1, win); break;
-                }
-            }
-    }
-}
-
-template <int W>
-__device__ __forceinline__ void tof_dispatch_back(int na, const LorGeo &G, float *Z, const float *lut,
-                                                  float inv_h, const float *tbj, int c0, int c1, const float *win) {
-    switch (na) {
-        case 1: tof_back_run<1>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-        case 2: tof_back_run<2>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-        case 3: tof_back_run<3>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-        case 4: tof_back_run<4>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-        default:
-            if constexpr (W > 4) {
-                switch (na) {
-                    case 5: tof_back_run<5>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-                    case 6: tof_back_run<6>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-                    case 7: tof_back_run<7>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-                    default: tof_back_run<8>(G, Z, lut, inv_h, tbj, c0, c1, win); break;
-                }
-            }
-    }
-}
-
-// W = 0: non-TOF; W = 4 / 8: TOF with at most W bins overlapping any point.
-template <int W, int MODE>
-__global__ void __launch_bounds__(LINE_BLOCK) k_line(ProjArgs a) {
-    extern __shared__ float smem[];
-    constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
-    constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM;
-    constexpr int NTA = W == 0 ? 1 : NT_MAX;
-    const int tid = threadIdx.x;
-    const int jv = blockIdx.x / a.n_rad;
-    const int k = blockIdx.x - jv * a.n_rad;
-    const int line = a.views[jv] * a.n_rad + k;
-    const LineP L = a.lines[line];
-    const int nrow = L.i_hi - L.i_lo + 1;  // <= 0: line misses the image
+// Block prologue: image sheet X (transaxial interpolation of the transposed
+// image) and / or zeroed gradient sheet Z.  Z accumulates in FP64: LDS FP64
+// atomic adds run at full rate on gfx950, FP32 ones do not.
+template <bool NEED_X, bool NEED_Z>
+__device__ __forceinline__ void build_sheets(const ProjArgs &a, const LineP &L, int nrow, float *X, double *Z) {
     const int rz = a.rz;
-    const int nt = W == 0 ? 1 : a.tof.n_tof;
-    const int n_other = L.axis ? a.nx : a.ny;  // size of the transaxial interpolation axis
-    const size_t other_stride = (size_t)(n_other + 2 * PADA) * rz;
-
-    float *X = smem;
-    float *Z = smem + (NEED_X ? max(nrow, 0) * rz : 0);
-    float *lut = Z + (NEED_Z ? max(nrow, 0) * rz : 0);
-
-    if (nrow > 0 && MODE != M_COUNT) {
-        if (W > 0)
-            for (int e = tid; e <= LUT_N; e += LINE_BLOCK) lut[e] = a.lut[e];
-        const float *T = L.axis ? a.T1 : a.T0;
-        for (int e = tid; e < nrow * rz; e += LINE_BLOCK) {
-            int r = e / rz;
-            int zp = e - r * rz;
-            if (NEED_X) {
-                int i = L.i_lo + r;
-                float xa = fmaf((float)i, L.dxa, L.xa0);
-                float jf = floorf(xa);
-                float f = xa - jf;
-                size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
-                float t0 = T[base], t1 = T[base + rz];
-                X[e] = fmaf(f, t1 - t0, t0);
-            }
-            if (NEED_Z) Z[e] = 0.f;
-        }
-    }
-    __syncthreads();
-
-    double kl = 0.0, cnt_pairs = 0.0;
-    for (int p = tid; p < a.n_planes; p += LINE_BLOCK) {
-        const PlaneP P = a.planes[p];
-        const int64_t lor = (int64_t)line * a.n_planes + p;
-        LorGeo G;
-        G.lam0 = L.lam0;
-        G.dlam = L.dlam;
-        G.zb = P.zb;
-        G.zs = P.zs;
-        G.len = sqrtf(L.lt2 + P.dz2);
-        G.ilo = L.i_lo;
-        G.rz = rz;
-        G.is = L.i_lo;
-        G.ie = L.i_hi;
-        const float ell = L.vm_um * G.len;
-        if (nrow > 0) {
-            // restrict to samples whose z coordinate can touch the grid
-            if (P.zs != 0.f) {
-                float la = (-1.5f - P.zb) / P.zs, lb = ((float)a.nz + 0.5f - P.zb) / P.zs;
-                float ia = (fminf(la, lb) - L.lam0) / L.dlam, ib = (fmaxf(la, lb) - L.lam0) / L.dlam;
-                float lo = ceilf(fminf(ia, ib)), hi = floorf(fmaxf(ia, ib));
-                if (lo > (float)G.is) G.is = lo > (float)G.ie ? G.ie + 1 : (int)lo;
-                if (hi < (float)G.ie) G.ie = hi < (float)G.is ? G.is - 1 : (int)hi;
-            } else if (P.zb < -1.5f || P.zb > (float)a.nz + 0.5f) {
-                G.ie = G.is - 1;
-            }
-        } else {
-            G.ie = G.is - 1;
-        }
-
-        float acc[NTA];
-#pragma unroll
-        for (int b = 0; b < NTA; ++b) acc[b] = 0.f;
-
-        if constexpr (MODE == M_COUNT) {
-            // the work of this LOR exactly as the other modes traverse it:
-            // samples, and sample-bin pairs (TOF; equal to samples without TOF)
-            if (G.ie >= G.is) {
-                const double ns = (double)(G.ie - G.is + 1);
-                double np = ns;
-                if constexpr (W > 0) {
-                    np = 0.0;
-                    for (int s = 0; s < a.tof.n_int; ++s) {
-                        const int na = a.tof.na[s];
-                        if (na <= 0) continue;
-                        const int c0 = cut_count(a.tof.edge[s], G.len, G.lam0, G.dlam, G.is, G.ie);
-                        const int c1 = cut_count(a.tof.edge[s + 1], G.len, G.lam0, G.dlam, G.is, G.ie);
-                        if (c1 > c0) np += (double)na * (c1 - c0);
-                    }
-                }
-                kl += ns;
-                cnt_pairs += np;
-            }
-            continue;
-        }
-
-        // ---- forward projection ----
-        if (NEED_X && G.ie >= G.is) {
-            if constexpr (W == 0) {
-                float s = 0.f;
-                for (int i = G.is; i <= G.ie; ++i) {
-                    float lam = fmaf((float)i, G.dlam, G.lam0);
-                    float xz = fmaf(lam, G.zs, G.zb);
-                    float jf = floorf(xz);
-                    float f = xz - jf;
-                    int r = (i - G.ilo) * rz + (int)jf + PADZ;
-                    float x0 = X[r], x1 = X[r + 1];
-                    s += fmaf(f, x1 - x0, x0);
-                }
-                acc[0] = s;
-            } else {
-                for (int s = 0; s < a.tof.n_int; ++s) {
-                    const int na = a.tof.na[s];
-                    if (na <= 0) continue;
-                    const int c0 = cut_count(a.tof.edge[s], G.len, G.lam0, G.dlam, G.is, G.ie);
-                    const int c1 = cut_count(a.tof.edge[s + 1], G.len, G.lam0, G.dlam, G.is, G.ie);
-                    const int bf = a.tof.bf[s];
-                    float tbj[W], win[W];
-#pragma unroll
-                    for (int j = 0; j < W; ++j) {
-                        tbj[j] = a.tof.tb[min(bf + j, NT_MAX - 1)];
-                        win[j] = 0.f;
-                    }
-                    if (c1 > c0) tof_dispatch_fwd<W>(na, G, X, lut, a.tof.lut_inv_h, tbj, c0, c1, win);
-#pragma unroll
-                    for (int j = 0; j < W; ++j)
-                        if (j < na) acc[bf + j] += win[j];
-                }
-            }
-        }
-
-        // ---- ratio / output ----
-        const float m = a.mult ? a.mult[lor] : 1.f;
-        for (int b = 0; b < nt; ++b) {
-            const int64_t idx = lor * nt + b;
-            if constexpr (MODE == M_BACK) {
-                acc[b] = (a.sino ? a.sino[idx] : 1.f) * m * ell;
-            } else {
-                float ybar = fmaf(m, acc[b] * ell, a.add ? a.add[idx] : 0.f);
-                if constexpr (MODE == M_FWD) {
-                    a.out[idx] = ybar;
-                } else {
-                    float yv = load_y(a.y, a.y_dtype, idx);
-                    if (a.partial) kl += kl_term(ybar, yv);
-                    if constexpr (MODE == M_GRAD) acc[b] = m * (1.f - yv / ybar) * ell;
-                    if constexpr (MODE == M_EM) acc[b] = m * (yv / ybar) * ell;
-                }
-            }
-        }
-
-        // ---- adjoint into the LDS gradient sheet ----
-        if (NEED_Z && G.ie >= G.is) {
-            if constexpr (W == 0) {
-                const float Q = acc[0];
-                for (int i = G.is; i <= G.ie; ++i) {
-                    float lam = fmaf((float)i, G.dlam, G.lam0);
-                    float xz = fmaf(lam, G.zs, G.zb);
-                    float jf = floorf(xz);
-                    float f = xz - jf;
-                    int r = (i - G.ilo) * rz + (int)jf + PADZ;
-                    float a1 = Q * f;
-                    atomicAdd(&Z[r], Q - a1);
-                    atomicAdd(&Z[r + 1], a1);
-                }
-            } else {
-                for (int s = 0; s < a.tof.n_int; ++s) {
-                    const int na = a.tof.na[s];
-                    if (na <= 0) continue;
-                    const int c0 = cut_count(a.tof.edge[s], G.len, G.lam0, G.dlam, G.is, G.ie);
-                    const int c1 = cut_count(a.tof.edge[s + 1], G.len, G.lam0, G.dlam, G.is, G.ie);
-                    const int bf = a.tof.bf[s];
-                    float tbj[W], win[W];
-#pragma unroll
-                    for (int j = 0; j < W; ++j) {
-                        tbj[j] = a.tof.tb[min(bf + j, NT_MAX - 1)];
-                        win[j] = (j < na) ? acc[min(bf + j, NTA - 1)] : 0.f;
-                    }
-                    if (c1 > c0) tof_dispatch_back<W>(na, G, Z, lut, a.tof.lut_inv_h, tbj, c0, c1, win);
-                }
-            }
-        }
-    }
-
-    // ---- spread the gradient sheet over the two transaxial neighbours ----
-    if (NEED_Z && nrow > 0) {
-        __syncthreads();
-        float *Gout = L.axis ? a.G1 : a.G0;
-        for (int e = tid; e < nrow * rz; e += LINE_BLOCK) {
-            float val = Z[e];
-            if (val == 0.f) continue;
+    const float *T = L.axis ? a.T1 : a.T0;
+    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
+        if (NEED_X) {
             int r = e / rz;
             int zp = e - r * rz;
             int i = L.i_lo + r;
@@ -343,64 +86,430 @@ __global__ void __launch_bounds__(LINE_BLOCK) k_line(ProjArgs a) {
             float jf = floorf(xa);
             float f = xa - jf;
             size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
-            float a1 = val * f;
-            atomicAdd(&Gout[base], val - a1);
-            atomicAdd(&Gout[base + rz], a1);
+            float t0 = T[base], t1 = T[base + rz];
+            X[e] = fmaf(f, t1 - t0, t0);
+        }
+        if (NEED_Z) Z[e] = 0.0;
+    }
+}
+
+// Block epilogue: spread the gradient sheet over the two transaxial neighbours.
+__device__ __forceinline__ void scatter_sheet(const ProjArgs &a, const LineP &L, int nrow, const double *Z) {
+    const int rz = a.rz;
+    float *Gout = L.axis ? a.G1 : a.G0;
+    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
+        float val = (float)Z[e];
+        if (val == 0.f) continue;
+        int r = e / rz;
+        int zp = e - r * rz;
+        int i = L.i_lo + r;
+        float xa = fmaf((float)i, L.dxa, L.xa0);
+        float jf = floorf(xa);
+        float f = xa - jf;
+        size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
+        float a1 = val * f;
+        atomicAdd(&Gout[base], val - a1);
+        atomicAdd(&Gout[base + rz], a1);
+    }
+}
+
+// Block sums of two doubles into partial[blockIdx.x] (and, for the work counts,
+// partial[gridDim.x + blockIdx.x]).
+__device__ __forceinline__ void block_sums(double v0, double v1, double *partial, bool two) {
+    __shared__ double red[2][TOF_MAX_WAVES];
+    for (int off = 32; off > 0; off >>= 1) {
+        v0 += __shfl_down(v0, off, 64);
+        v1 += __shfl_down(v1, off, 64);
+    }
+    const int nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = v0;
+        red[1][threadIdx.x >> 6] = v1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            s0 += red[0][w];
+            s1 += red[1][w];
+        }
+        partial[blockIdx.x] = s0;
+        if (two) partial[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Non-TOF: threads over planes (dense), one line per workgroup.
+template <int MODE>
+__global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
+    extern __shared__ float4 smem4[];
+    float *smem = reinterpret_cast<float *>(smem4);
+    constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
+    constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM;
+    const int jv = blockIdx.x / a.n_rad;
+    const int k = blockIdx.x - jv * a.n_rad;
+    const int line = a.views[jv] * a.n_rad + k;
+    const LineP L = a.lines[line];
+    const int nrow = L.i_hi - L.i_lo + 1;
+    const int rz = a.rz;
+    const int sheet = (a.rows_max * rz + 3) & ~3;
+    float *X = smem;
+    double *Z = reinterpret_cast<double *>(smem + (NEED_X ? sheet : 0));
+    if (nrow > 0 && MODE != M_COUNT) build_sheets<NEED_X, NEED_Z>(a, L, nrow, X, Z);
+    __syncthreads();
+
+    double kl = 0.0;
+    for (int p = threadIdx.x; p < a.n_planes; p += blockDim.x) {
+        const PlaneP P = a.planes[p];
+        const int64_t lor = (int64_t)line * a.n_planes + p;
+        const float len = sqrtf(L.lt2 + P.dz2);
+        const float ell = L.vm_um * len;
+        int is = 0, ie = -1;
+        if (nrow > 0) z_clip(L, P, a.nz, is, ie);
+        if constexpr (MODE == M_COUNT) {
+            if (ie >= is) kl += (double)(ie - is + 1);
+            continue;
+        }
+        float s = 0.f;
+        if (NEED_X) {
+            for (int i = is; i <= ie; ++i) {
+                float lam = fmaf((float)i, L.dlam, L.lam0);
+                float xz = fmaf(lam, P.zs, P.zb);
+                float jf = floorf(xz);
+                float f = xz - jf;
+                int r = (i - L.i_lo) * rz + (int)jf + PADZ;
+                float x0 = X[r], x1 = X[r + 1];
+                s += fmaf(f, x1 - x0, x0);
+            }
+        }
+        const float m = a.mult ? a.mult[lor] : 1.f;
+        float Q = 0.f;
+        if constexpr (MODE == M_BACK) {
+            Q = (a.sino ? a.sino[lor] : 1.f) * m * ell;
+        } else {
+            float ybar = fmaf(m, s * ell, a.add ? a.add[lor] : 0.f);
+            if constexpr (MODE == M_FWD) {
+                a.out[lor] = ybar;
+                continue;
+            } else {
+                float yv = load_y(a.y, a.y_dtype, lor);
+                if (a.partial) kl += kl_term(ybar, yv);
+                if constexpr (MODE == M_GRAD) Q = m * (1.f - yv / ybar) * ell;
+                if constexpr (MODE == M_EM) Q = m * (yv / ybar) * ell;
+            }
+        }
+        if constexpr (NEED_Z) {
+            for (int i = is; i <= ie; ++i) {
+                float lam = fmaf((float)i, L.dlam, L.lam0);
+                float xz = fmaf(lam, P.zs, P.zb);
+                float jf = floorf(xz);
+                float f = xz - jf;
+                int r = (i - L.i_lo) * rz + (int)jf + PADZ;
+                float a1 = Q * f;
+                atomicAdd(&Z[r], (double)(Q - a1));
+                atomicAdd(&Z[r + 1], (double)a1);
+            }
         }
     }
-
-    // ---- FP64 block sums: KL terms (or sample / pair counts) ----
-    if (MODE != M_FWD && MODE != M_BACK && a.partial) {
-        __shared__ double red[2][LINE_BLOCK / 64];
-        for (int off = 32; off > 0; off >>= 1) {
-            kl += __shfl_down(kl, off, 64);
-            cnt_pairs += __shfl_down(cnt_pairs, off, 64);
-        }
-        if ((tid & 63) == 0) {
-            red[0][tid >> 6] = kl;
-            red[1][tid >> 6] = cnt_pairs;
-        }
+    if (NEED_Z && nrow > 0) {
         __syncthreads();
-        if (tid == 0) {
-            double s0 = 0.0, s1 = 0.0;
-            for (int w = 0; w < LINE_BLOCK / 64; ++w) {
-                s0 += red[0][w];
-                s1 += red[1][w];
-            }
-            a.partial[blockIdx.x] = s0;
-            if (MODE == M_COUNT) a.partial[gridDim.x + blockIdx.x] = s1;
+        scatter_sheet(a, L, nrow, Z);
+    }
+    if (MODE != M_FWD && MODE != M_BACK && a.partial) block_sums(kl, kl, a.partial, MODE == M_COUNT);
+}
+
+// ---------------------------------------------------------------------------
+// TOF: one wave per segment, one plane per lane, shared per-segment table.
+//
+// Per wave the LDS holds, for the segment being processed:
+//   cuts[s]  (s = 0 .. n_int)   first sample (t order) at or beyond edge s;
+//   w4[q], w1[q]                the TOF weights of the bins active at sample q
+//                               (first four in a float4, the rest after).
+// Samples q are numbered in increasing t along the LOR; the sample index,
+// lambda and the sheet row follow from q and are the same for all lanes.
+
+// erf of u / (sqrt2 sigma) with the argument clamped to the truncation window.
+__device__ __forceinline__ float clamped_erf(float u, float inv_s, float c) {
+    return erff(fminf(fmaxf(u * inv_s, -c), c));
+}
+
+__device__ __forceinline__ void fill_table(const ProjArgs &a, const LineP &L, float len, int *cuts, float *w4,
+                                           float *w1) {
+    const int lane = threadIdx.x & 63;
+    const int nq = L.i_hi - L.i_lo + 1;
+    const int e1 = a.ws > 4 ? a.ws - 4 : 0;
+    for (int e = lane; e <= a.tof.n_int; e += 64) cuts[e] = cut_count(a.tof.edge[e], len, L.lam0, L.dlam, L.i_lo, L.i_hi);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const float inv_s = a.tof.inv_sqrt2_sigma, c = a.tof.erf_clamp, h = a.tof.half_bin;
+    for (int q = lane; q < nq; q += 64) {
+        // interval holding q: cuts[s] <= q < cuts[s + 1]
+        int s = 0;
+        while (s < a.tof.n_int - 1 && cuts[s + 1] <= q) ++s;
+        const int na = (cuts[s] <= q && q < cuts[s + 1]) ? a.tof.na[s] : 0;
+        if (na <= 0) continue;
+        const int i = L.dlam > 0.f ? L.i_lo + q : L.i_hi - q;
+        const float lam = fmaf((float)i, L.dlam, L.lam0);
+        const float t = (lam - 0.5f) * len;
+        // weights of bins bf .. bf + na - 1 from shared bin edges
+        const float t0 = a.tof.tb[a.tof.bf[s]] - h - t;
+        float e_prev = clamped_erf(t0, inv_s, c);
+        float w[WS_MAX];
+        for (int j = 0; j < WS_MAX; ++j) w[j] = 0.f;
+        for (int j = 0; j < na; ++j) {
+            const float e_next = clamped_erf(t0 + (float)(j + 1) * (2.f * h), inv_s, c);
+            w[j] = 0.5f * (e_next - e_prev);
+            e_prev = e_next;
+        }
+        reinterpret_cast<float4 *>(w4)[q] = make_float4(w[0], w[1], w[2], w[3]);
+        for (int j = 0; j < e1; ++j) w1[q * e1 + j] = w[4 + j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Weights of sample q (all lanes read the same row: broadcast reads).
+template <int NA>
+__device__ __forceinline__ void read_w(const float *w4, const float *w1, int e1, int q, float (&w)[NA]) {
+    const float4 v = reinterpret_cast<const float4 *>(w4)[q];
+    if (NA > 0) w[0] = v.x;
+    if (NA > 1) w[1] = v.y;
+    if (NA > 2) w[2] = v.z;
+    if (NA > 3) w[3] = v.w;
+#pragma unroll
+    for (int j = 4; j < NA; ++j) w[j] = w1[q * e1 + (j - 4)];
+}
+
+// Forward accumulation over the samples q in [c0, c1) (wave-uniform) of one
+// TOF interval with NA active bins; a lane only adds the samples of its own
+// z-valid range [qlo, qhi].
+template <int NA>
+__device__ __forceinline__ void tof_fwd_run(const LineP &L, const PlaneP &P, const float *X, const float *w4,
+                                            const float *w1, int e1, int rz, int c0, int c1, int qlo, int qhi,
+                                            float *win) {
+    for (int q = c0; q < c1; ++q) {
+        float w[NA];
+        read_w<NA>(w4, w1, e1, q, w);
+        const int i = L.dlam > 0.f ? L.i_lo + q : L.i_hi - q;
+        if (q >= qlo && q <= qhi) {
+            const float lam = fmaf((float)i, L.dlam, L.lam0);
+            const float xz = fmaf(lam, P.zs, P.zb);
+            const float jf = floorf(xz);
+            const float f = xz - jf;
+            const int ri = (i - L.i_lo) * rz + (int)jf + PADZ;
+            const float x0 = X[ri], x1 = X[ri + 1];
+            const float v = fmaf(f, x1 - x0, x0);
+#pragma unroll
+            for (int j = 0; j < NA; ++j) win[j] = fmaf(v, w[j], win[j]);
         }
     }
 }
 
-template <int W>
-hipError_t launch_w(int mode, dim3 grid, size_t lds, const ProjArgs &a, hipStream_t s) {
-    switch (mode) {
-        case M_FWD: hipLaunchKernelGGL((k_line<W, M_FWD>), grid, dim3(LINE_BLOCK), lds, s, a); break;
-        case M_BACK: hipLaunchKernelGGL((k_line<W, M_BACK>), grid, dim3(LINE_BLOCK), lds, s, a); break;
-        case M_GRAD: hipLaunchKernelGGL((k_line<W, M_GRAD>), grid, dim3(LINE_BLOCK), lds, s, a); break;
-        case M_EM: hipLaunchKernelGGL((k_line<W, M_EM>), grid, dim3(LINE_BLOCK), lds, s, a); break;
-        case M_OBJ: hipLaunchKernelGGL((k_line<W, M_OBJ>), grid, dim3(LINE_BLOCK), lds, s, a); break;
-        case M_COUNT: hipLaunchKernelGGL((k_line<W, M_COUNT>), grid, dim3(LINE_BLOCK), 0, s, a); break;
-        default: return hipErrorInvalidValue;
+template <int NA>
+__device__ __forceinline__ void tof_back_run(const LineP &L, const PlaneP &P, double *Z, const float *w4,
+                                             const float *w1, int e1, int rz, int c0, int c1, int qlo, int qhi,
+                                             const float *win) {
+    for (int q = c0; q < c1; ++q) {
+        float w[NA];
+        read_w<NA>(w4, w1, e1, q, w);
+        const int i = L.dlam > 0.f ? L.i_lo + q : L.i_hi - q;
+        if (q >= qlo && q <= qhi) {
+            float Q = 0.f;
+#pragma unroll
+            for (int j = 0; j < NA; ++j) Q = fmaf(win[j], w[j], Q);
+            const float lam = fmaf((float)i, L.dlam, L.lam0);
+            const float xz = fmaf(lam, P.zs, P.zb);
+            const float jf = floorf(xz);
+            const float f = xz - jf;
+            const int ri = (i - L.i_lo) * rz + (int)jf + PADZ;
+            const float a1 = Q * f;
+            atomicAdd(&Z[ri], (double)(Q - a1));
+            atomicAdd(&Z[ri + 1], (double)a1);
+        }
     }
+}
+
+#define PET_NA_SWITCH(FN, ...)              \
+    switch (na) {                           \
+        case 1: FN<1>(__VA_ARGS__); break;  \
+        case 2: FN<2>(__VA_ARGS__); break;  \
+        case 3: FN<3>(__VA_ARGS__); break;  \
+        case 4: FN<4>(__VA_ARGS__); break;  \
+        case 5: FN<5>(__VA_ARGS__); break;  \
+        case 6: FN<6>(__VA_ARGS__); break;  \
+        case 7: FN<7>(__VA_ARGS__); break;  \
+        default: FN<8>(__VA_ARGS__); break; \
+    }
+
+template <int MODE>
+__global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
+    extern __shared__ float4 smem4[];
+    float *smem = reinterpret_cast<float *>(smem4);
+    constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
+    constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int jv = blockIdx.x / a.n_rad;
+    const int k = blockIdx.x - jv * a.n_rad;
+    const int line = a.views[jv] * a.n_rad + k;
+    const LineP L = a.lines[line];
+    const int nrow = L.i_hi - L.i_lo + 1;
+    const int rz = a.rz;
+    const int nt = a.tof.n_tof;
+    // LDS: X sheet (float) | Z sheet (double) | per wave: w4 [rows][4], w1 [rows][e1], cuts
+    const int sheet = (a.rows_max * rz + 3) & ~3;
+    const int e1 = a.ws > 4 ? a.ws - 4 : 0;
+    const int per_wave = a.rows_max * (4 + e1) + CUTS_PAD;
+    float *X = smem;
+    double *Z = reinterpret_cast<double *>(smem + (NEED_X ? sheet : 0));
+    float *wave_mem = smem + (NEED_X ? sheet : 0) + (NEED_Z ? 2 * sheet : 0) + wave * ((per_wave + 3) & ~3);
+    float *w4 = wave_mem;
+    float *w1 = wave_mem + 4 * a.rows_max;
+    int *cuts = (int *)(w1 + a.rows_max * e1);
+    if (nrow > 0 && MODE != M_COUNT) build_sheets<NEED_X, NEED_Z>(a, L, nrow, X, Z);
+    __syncthreads();
+
+    double kl = 0.0, pairs = 0.0;
+    for (int sg = wave; sg < a.n_seg; sg += nwaves) {
+        const SegP S = a.segs[sg];
+        const bool has = lane < S.np;
+        const int p = S.p0 + (has ? lane : 0);
+        const PlaneP P = a.planes[p];
+        const int64_t lor = (int64_t)line * a.n_planes + p;
+        const float len = sqrtf(L.lt2 + S.dz2);
+        const float ell = L.vm_um * len;
+        int is = 0, ie = -1;
+        if (nrow > 0 && has) z_clip(L, P, a.nz, is, ie);
+        // this lane's samples in t order: q in [qlo, qhi]
+        const int qlo = L.dlam > 0.f ? is - L.i_lo : L.i_hi - ie;
+        const int qhi = L.dlam > 0.f ? ie - L.i_lo : L.i_hi - is;
+
+        if constexpr (MODE == M_COUNT) {
+            if (nrow > 0 && ie >= is) {
+                kl += (double)(ie - is + 1);
+                for (int s = 0; s < a.tof.n_int; ++s) {
+                    const int na = a.tof.na[s];
+                    if (na <= 0) continue;
+                    const int c0 = max(cut_count(a.tof.edge[s], len, L.lam0, L.dlam, L.i_lo, L.i_hi), qlo);
+                    const int c1 = min(cut_count(a.tof.edge[s + 1], len, L.lam0, L.dlam, L.i_lo, L.i_hi), qhi + 1);
+                    if (c1 > c0) pairs += (double)na * (c1 - c0);
+                }
+            }
+        } else {
+            if (nrow > 0) fill_table(a, L, len, cuts, w4, w1);
+            float acc[NT_MAX];
+#pragma unroll
+            for (int b = 0; b < NT_MAX; ++b) acc[b] = 0.f;
+
+            // ---- forward projection ----
+            if (NEED_X && nrow > 0) {
+                for (int s = 0; s < a.tof.n_int; ++s) {
+                    const int na = a.tof.na[s];
+                    if (na <= 0) continue;
+                    const int c0 = __builtin_amdgcn_readfirstlane(cuts[s]);
+                    const int c1 = __builtin_amdgcn_readfirstlane(cuts[s + 1]);
+                    const int bf = a.tof.bf[s];
+                    float win[WS_MAX];
+#pragma unroll
+                    for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
+                    if (c1 > c0) PET_NA_SWITCH(tof_fwd_run, L, P, X, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
+#pragma unroll
+                    for (int j = 0; j < WS_MAX; ++j)
+                        if (j < na) acc[bf + j] += win[j];
+                }
+            }
+
+            // ---- ratio / output ----
+            if (has) {
+                const float m = a.mult ? a.mult[lor] : 1.f;
+                for (int b = 0; b < nt; ++b) {
+                    const int64_t idx = lor * nt + b;
+                    if constexpr (MODE == M_BACK) {
+                        acc[b] = (a.sino ? a.sino[idx] : 1.f) * m * ell;
+                    } else {
+                        const float ybar = fmaf(m, acc[b] * ell, a.add ? a.add[idx] : 0.f);
+                        if constexpr (MODE == M_FWD) {
+                            a.out[idx] = ybar;
+                        } else {
+                            const float yv = load_y(a.y, a.y_dtype, idx);
+                            if (a.partial) kl += kl_term(ybar, yv);
+                            if constexpr (MODE == M_GRAD) acc[b] = m * (1.f - yv / ybar) * ell;
+                            if constexpr (MODE == M_EM) acc[b] = m * (yv / ybar) * ell;
+                        }
+                    }
+                }
+            }
+
+            // ---- adjoint into the LDS gradient sheet ----
+            if (NEED_Z && nrow > 0) {
+                for (int s = 0; s < a.tof.n_int; ++s) {
+                    const int na = a.tof.na[s];
+                    if (na <= 0) continue;
+                    const int c0 = __builtin_amdgcn_readfirstlane(cuts[s]);
+                    const int c1 = __builtin_amdgcn_readfirstlane(cuts[s + 1]);
+                    if (c1 <= c0 || max(c0, qlo) > min(c1 - 1, qhi)) continue;
+                    const int bf = a.tof.bf[s];
+                    float win[WS_MAX];
+#pragma unroll
+                    for (int j = 0; j < WS_MAX; ++j) win[j] = (j < na) ? acc[min(bf + j, NT_MAX - 1)] : 0.f;
+                    PET_NA_SWITCH(tof_back_run, L, P, Z, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
+                }
+            }
+            // the next segment overwrites this wave's table
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (NEED_Z && nrow > 0) {
+        __syncthreads();
+        scatter_sheet(a, L, nrow, Z);
+    }
+    if (MODE != M_FWD && MODE != M_BACK && a.partial) block_sums(kl, pairs, a.partial, MODE == M_COUNT);
+}
+
+template <int MODE>
+hipError_t launch_mode(const pet_geom_s *g, dim3 grid, const ProjArgs &a, hipStream_t s) {
+    const size_t lds = MODE == M_COUNT ? 0 : g->lds_bytes;
+    if (g->d.n_tof > 1)
+        hipLaunchKernelGGL((k_line_tof<MODE>), grid, dim3(64 * g->tof_waves), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_line_nt<MODE>), grid, dim3(NT_BLOCK), lds, s, a);
     return hipGetLastError();
 }
 
 // Raise the dynamic-LDS limit of the line kernels to what this geometry needs
 // (checked against the device limit at creation).  Only needed above the
 // default; a failure here is reported by the launch itself.
-template <int W>
 void set_lds_attr(size_t need) {
     static size_t granted = 64 * 1024;
     if (need <= granted) return;
-    hipError_t e = hipFuncSetAttribute((const void *)k_line<W, M_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_line<W, M_BACK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_line<W, M_GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_line<W, M_EM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_line<W, M_OBJ>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+    const void *fns[] = {(const void *)k_line_nt<M_FWD>,   (const void *)k_line_nt<M_BACK>,
+                         (const void *)k_line_nt<M_GRAD>,  (const void *)k_line_nt<M_EM>,
+                         (const void *)k_line_nt<M_OBJ>,   (const void *)k_line_tof<M_FWD>,
+                         (const void *)k_line_tof<M_BACK>, (const void *)k_line_tof<M_GRAD>,
+                         (const void *)k_line_tof<M_EM>,   (const void *)k_line_tof<M_OBJ>};
+    hipError_t e = hipSuccess;
+    for (const void *f : fns)
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
     if (e == hipSuccess) granted = need;
     (void)hipGetLastError();
+}
+
+hipError_t launch_line_kernel_impl(const pet_geom_s *g, int mode, dim3 grid, const ProjArgs &a, hipStream_t s) {
+    set_lds_attr(g->lds_bytes);
+    switch (mode) {
+        case M_FWD: return launch_mode<M_FWD>(g, grid, a, s);
+        case M_BACK: return launch_mode<M_BACK>(g, grid, a, s);
+        case M_GRAD: return launch_mode<M_GRAD>(g, grid, a, s);
+        case M_EM: return launch_mode<M_EM>(g, grid, a, s);
+        case M_OBJ: return launch_mode<M_OBJ>(g, grid, a, s);
+        case M_COUNT: return launch_mode<M_COUNT>(g, grid, a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -408,24 +517,6 @@ void set_lds_attr(size_t need) {
 int n_line_blocks(const pet_geom_s *g, int subset) {
     int nv = subset < 0 ? g->d.n_views : (int)g->subset_views[subset].size();
     return nv * g->d.n_rad;
-}
-
-static hipError_t launch_line_kernel_impl(const pet_geom_s *g, int mode, dim3 grid, const ProjArgs &a, hipStream_t s) {
-    int wmax = 0;
-    if (g->d.n_tof > 1) {
-        wmax = 1;
-        for (int i = 0; i < g->tof.n_int; ++i) wmax = std::max(wmax, g->tof.na[i]);
-    }
-    if (wmax == 0) {
-        set_lds_attr<0>(g->lds_bytes);
-        return launch_w<0>(mode, grid, g->lds_bytes, a, s);
-    }
-    if (wmax <= 4) {
-        set_lds_attr<4>(g->lds_bytes);
-        return launch_w<4>(mode, grid, g->lds_bytes, a, s);
-    }
-    set_lds_attr<8>(g->lds_bytes);
-    return launch_w<8>(mode, grid, g->lds_bytes, a, s);
 }
 
 hipError_t launch_line_kernel(pet_geom_s *g, int mode, int subset, const ProjArgs &a, hipStream_t s) {
