@@ -36,6 +36,11 @@ FLOP_PER_SAMPLE_NONTOF = 2.0  # accumulate forward + scale backward
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
 PEAK_HBM_GBPS = 8000.0
 
+# HBM bytes per launch of the fused TOF subset gradient, from calibrated
+# FETCH_SIZE / WRITE_SIZE counter runs, valid for the kernel source with this
+# hash only (reported as null otherwise).
+MEASURED_TRAFFIC = {"c2_tof": (753.5e6, "c5605dd53e2e257e")}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -83,6 +88,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed SVRG epochs before timing")
     ap.add_argument("--config", default="c2_tof")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run a device-to-device copy of this many MiB (a known-size reference kernel "
+                         "for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -131,6 +139,12 @@ def main():
         pm.pet_svrg_epoch(geom, st, x, orders[e], [1.0 / (1.0 + 0.02 * k / n) for k in ks],
                           [k in upd_iters for k in ks])
 
+    if args.copy_ref_mib > 0:
+        src = torch.ones(args.copy_ref_mib * 262144, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("[bench] OSEM done; warmup epochs ...")
     for e in range(args.warmup):
         epoch(e)
@@ -170,6 +184,11 @@ def main():
         flops += FLOP_PER_SAMPLE * s + (FLOP_PER_PAIR_TOF * p if tof else FLOP_PER_SAMPLE_NONTOF * s)
         nb, nl, _ = geom.info(i)
         hbm += nb * (y.element_size() + 4) + nl * 4 + 4 * geom.n_vox * 2
+    import hashlib
+    src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_2506_04976_amd", "csrc", "proj.hip"), "rb").read()).hexdigest()[:16]
+    traffic = None
+    if cfg["name"] in MEASURED_TRAFFIC and MEASURED_TRAFFIC[cfg["name"]][1] == src_hash:
+        traffic = MEASURED_TRAFFIC[cfg["name"]][0]
     grad_s = grad_ms / 1e3
     achieved = flops / grad_s / 1e12
     kernel_gbps = hbm / grad_s / 1e9
@@ -209,7 +228,7 @@ def main():
                    "bins": geom.n_bins, "voxels": geom.n_vox, "counts": cfg.get("counts"),
                    "y_dtype": str(keep["y"].dtype), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "k_line<TOF, M_GRAD> (fused forward projection, ratio, backprojection)",
                      "avg_launch_ms": grad_ms / grad_launches, "launches": grad_launches,
                      "algorithmic_hbm_gbps": kernel_gbps, "hbm_frac": kernel_gbps / PEAK_HBM_GBPS},
