@@ -20,6 +20,7 @@
 // The arithmetic is Joseph's: sample value = bilinear interpolation of the
 // image in the two non-principal axes, line integral = step length * sum.
 #include "pet_internal.h"
+#include <climits>
 
 namespace pet {
 namespace {
@@ -234,22 +235,37 @@ __device__ __forceinline__ float clamped_erf(float u, float inv_s, float c) {
     return erff(fminf(fmaxf(u * inv_s, -c), c));
 }
 
-__device__ __forceinline__ void fill_table(const ProjArgs &a, const LineP &L, float len, int *cuts, float *w4,
-                                           float *w1) {
+// Per-wave TOF weight table of one LOR (one segment of the line): lane s
+// computes the cut cuts[s] (rows before interval s in t order) and returns it;
+// each row q of a non-empty interval gets the weights of its na bins.
+__device__ __forceinline__ int fill_table(const ProjArgs &a, const LineP &L, float len, int *cuts, float *w4,
+                                          float *w1) {
     const int lane = threadIdx.x & 63;
     const int nq = L.i_hi - L.i_lo + 1;
     const int e1 = a.ws > 4 ? a.ws - 4 : 0;
-    for (int e = lane; e <= a.tof.n_int; e += 64) cuts[e] = cut_count(a.tof.edge[e], len, L.lam0, L.dlam, L.i_lo, L.i_hi);
+    int *sid = reinterpret_cast<int *>(w4);  // interval of row q, parked in w4[q].x
+    int cut = 0;
+    if (lane <= a.tof.n_int) {
+        cut = cut_count(a.tof.edge[lane], len, L.lam0, L.dlam, L.i_lo, L.i_hi);
+        cuts[lane] = cut;
+    }
+    for (int q = lane; q < nq; q += 64) sid[4 * q] = -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // lane s marks the rows of interval s
+    if (lane < a.tof.n_int && a.tof.na[lane] > 0) {
+        const int hi = cuts[lane + 1];
+        for (int q = cut; q < hi; ++q) sid[4 * q] = lane;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const float inv_s = a.tof.inv_sqrt2_sigma, c = a.tof.erf_clamp, h = a.tof.half_bin;
     for (int q = lane; q < nq; q += 64) {
-        // interval holding q: cuts[s] <= q < cuts[s + 1]
-        int s = 0;
-        while (s < a.tof.n_int - 1 && cuts[s + 1] <= q) ++s;
-        const int na = (cuts[s] <= q && q < cuts[s + 1]) ? a.tof.na[s] : 0;
-        if (na <= 0) continue;
+        const int s = sid[4 * q];
+        if (s < 0) continue;
+        const int na = a.tof.na[s];
         const int i = L.dlam > 0.f ? L.i_lo + q : L.i_hi - q;
         const float lam = fmaf((float)i, L.dlam, L.lam0);
         const float t = (lam - 0.5f) * len;
@@ -269,6 +285,7 @@ __device__ __forceinline__ void fill_table(const ProjArgs &a, const LineP &L, fl
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return cut;
 }
 
 // Weights of sample q (all lanes read the same row: broadcast reads).
@@ -285,9 +302,10 @@ __device__ __forceinline__ void read_w(const float *w4, const float *w1, int e1,
 
 // Forward accumulation over the samples q in [c0, c1) (wave-uniform) of one
 // TOF interval with NA active bins; a lane only adds the samples of its own
-// z-valid range [qlo, qhi].
+// z-valid range [qlo, qhi]. The axial position of the sample in principal
+// plane i is zA * i + zB (voxel units).
 template <int NA>
-__device__ __forceinline__ void tof_fwd_run(const LineP &L, const PlaneP &P, const float *X, const float *w4,
+__device__ __forceinline__ void tof_fwd_run(const LineP &L, float zA, float zB, const float *X, const float *w4,
                                             const float *w1, int e1, int rz, int c0, int c1, int qlo, int qhi,
                                             float *win) {
     for (int q = c0; q < c1; ++q) {
@@ -295,8 +313,7 @@ __device__ __forceinline__ void tof_fwd_run(const LineP &L, const PlaneP &P, con
         read_w<NA>(w4, w1, e1, q, w);
         const int i = L.dlam > 0.f ? L.i_lo + q : L.i_hi - q;
         if (q >= qlo && q <= qhi) {
-            const float lam = fmaf((float)i, L.dlam, L.lam0);
-            const float xz = fmaf(lam, P.zs, P.zb);
+            const float xz = fmaf((float)i, zA, zB);
             const float jf = floorf(xz);
             const float f = xz - jf;
             const int ri = (i - L.i_lo) * rz + (int)jf + PADZ;
@@ -309,7 +326,7 @@ __device__ __forceinline__ void tof_fwd_run(const LineP &L, const PlaneP &P, con
 }
 
 template <int NA>
-__device__ __forceinline__ void tof_back_run(const LineP &L, const PlaneP &P, double *Z, const float *w4,
+__device__ __forceinline__ void tof_back_run(const LineP &L, float zA, float zB, double *Z, const float *w4,
                                              const float *w1, int e1, int rz, int c0, int c1, int qlo, int qhi,
                                              const float *win) {
     for (int q = c0; q < c1; ++q) {
@@ -320,8 +337,7 @@ __device__ __forceinline__ void tof_back_run(const LineP &L, const PlaneP &P, do
             float Q = 0.f;
 #pragma unroll
             for (int j = 0; j < NA; ++j) Q = fmaf(win[j], w[j], Q);
-            const float lam = fmaf((float)i, L.dlam, L.lam0);
-            const float xz = fmaf(lam, P.zs, P.zb);
+            const float xz = fmaf((float)i, zA, zB);
             const float jf = floorf(xz);
             const float f = xz - jf;
             const int ri = (i - L.i_lo) * rz + (int)jf + PADZ;
@@ -373,6 +389,10 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
     if (nrow > 0 && MODE != M_COUNT) build_sheets<NEED_X, NEED_Z>(a, L, nrow, X, Z);
     __syncthreads();
 
+    // lane s holds the bin count and first bin of interval s
+    const int na_l = lane < a.tof.n_int ? a.tof.na[lane] : 0;
+    const int bf_l = lane < a.tof.n_int ? a.tof.bf[lane] : 0;
+
     double kl = 0.0, pairs = 0.0;
     for (int sg = wave; sg < a.n_seg; sg += nwaves) {
         const SegP S = a.segs[sg];
@@ -400,23 +420,35 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
                 }
             }
         } else {
-            if (nrow > 0) fill_table(a, L, len, cuts, w4, w1);
+            const int cut = nrow > 0 ? fill_table(a, L, len, cuts, w4, w1) : 0;
+            // axial sample position of row i: xz = zA * i + zB
+            const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb);
+            const int cut_next = __shfl_down(cut, 1, 64);
+            // intervals with bins whose rows meet some lane's sample range
+            int qa = qlo <= qhi ? qlo : INT_MAX, qb = qlo <= qhi ? qhi : -1;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                qa = min(qa, __shfl_xor(qa, o, 64));
+                qb = max(qb, __shfl_xor(qb, o, 64));
+            }
+            const bool live = nrow > 0 && na_l > 0 && max(cut, qa) < min(cut_next, qb + 1);
+            const uint64_t live_mask = __ballot(live);
             float acc[NT_MAX];
 #pragma unroll
             for (int b = 0; b < NT_MAX; ++b) acc[b] = 0.f;
 
             // ---- forward projection ----
-            if (NEED_X && nrow > 0) {
-                for (int s = 0; s < a.tof.n_int; ++s) {
-                    const int na = a.tof.na[s];
-                    if (na <= 0) continue;
-                    const int c0 = __builtin_amdgcn_readfirstlane(cuts[s]);
-                    const int c1 = __builtin_amdgcn_readfirstlane(cuts[s + 1]);
-                    const int bf = a.tof.bf[s];
+            if (NEED_X) {
+                for (uint64_t m = live_mask; m; m &= m - 1) {
+                    const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
+                    const int na = __builtin_amdgcn_readlane(na_l, s);
+                    const int c0 = __builtin_amdgcn_readlane(cut, s);
+                    const int c1 = __builtin_amdgcn_readlane(cut_next, s);
+                    const int bf = __builtin_amdgcn_readlane(bf_l, s);
                     float win[WS_MAX];
 #pragma unroll
                     for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
-                    if (c1 > c0) PET_NA_SWITCH(tof_fwd_run, L, P, X, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
+                    if (c1 > c0) PET_NA_SWITCH(tof_fwd_run, L, zA, zB, X, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
 #pragma unroll
                     for (int j = 0; j < WS_MAX; ++j)
                         if (j < na) acc[bf + j] += win[j];
@@ -437,26 +469,25 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
                         } else {
                             const float yv = load_y(a.y, a.y_dtype, idx);
                             if (a.partial) kl += kl_term(ybar, yv);
-                            if constexpr (MODE == M_GRAD) acc[b] = m * (1.f - yv / ybar) * ell;
-                            if constexpr (MODE == M_EM) acc[b] = m * (yv / ybar) * ell;
+                            if constexpr (MODE == M_GRAD) acc[b] = m * fmaf(-yv, __builtin_amdgcn_rcpf(ybar), 1.f) * ell;
+                            if constexpr (MODE == M_EM) acc[b] = m * (yv * __builtin_amdgcn_rcpf(ybar)) * ell;
                         }
                     }
                 }
             }
 
             // ---- adjoint into the LDS gradient sheet ----
-            if (NEED_Z && nrow > 0) {
-                for (int s = 0; s < a.tof.n_int; ++s) {
-                    const int na = a.tof.na[s];
-                    if (na <= 0) continue;
-                    const int c0 = __builtin_amdgcn_readfirstlane(cuts[s]);
-                    const int c1 = __builtin_amdgcn_readfirstlane(cuts[s + 1]);
-                    if (c1 <= c0 || max(c0, qlo) > min(c1 - 1, qhi)) continue;
-                    const int bf = a.tof.bf[s];
+            if (NEED_Z) {
+                for (uint64_t m = live_mask; m; m &= m - 1) {
+                    const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
+                    const int na = __builtin_amdgcn_readlane(na_l, s);
+                    const int c0 = __builtin_amdgcn_readlane(cut, s);
+                    const int c1 = __builtin_amdgcn_readlane(cut_next, s);
+                    const int bf = __builtin_amdgcn_readlane(bf_l, s);
                     float win[WS_MAX];
 #pragma unroll
                     for (int j = 0; j < WS_MAX; ++j) win[j] = (j < na) ? acc[min(bf + j, NT_MAX - 1)] : 0.f;
-                    PET_NA_SWITCH(tof_back_run, L, P, Z, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
+                    PET_NA_SWITCH(tof_back_run, L, zA, zB, Z, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
                 }
             }
             // the next segment overwrites this wave's table
