@@ -31,6 +31,22 @@ __device__ __forceinline__ float load_y(const void *y, int dt, int64_t idx) {
     return ((const float *)y)[idx];
 }
 
+// The nt values src[base .. base + nt) of one LOR, all loads issued before the
+// first use (zero above nt).
+template <typename T>
+__device__ __forceinline__ void load_row(const T *src, int64_t base, int nt, float (&v)[NT_MAX]) {
+#pragma unroll
+    for (int b = 0; b < NT_MAX; ++b) v[b] = b < nt ? (float)src[base + b] : 0.f;
+}
+__device__ __forceinline__ void load_y_row(const void *y, int dt, int64_t base, int nt, float (&v)[NT_MAX]) {
+    if (dt == PET_Y_U8)
+        load_row((const uint8_t *)y, base, nt, v);
+    else if (dt == PET_Y_U16)
+        load_row((const uint16_t *)y, base, nt, v);
+    else
+        load_row((const float *)y, base, nt, v);
+}
+
 // Poisson deviance term d(ybar, y) of the KL data fidelity, FP64.
 __device__ __forceinline__ double kl_term(float ybar, float yv) {
     double s = ybar, t = yv;
@@ -56,12 +72,18 @@ __device__ __forceinline__ int cut_count(float e, float len, float lam0, float d
 
 // Sample range [is, ie] of a LOR restricted to samples whose z coordinate can
 // touch the grid (xi_z in [-1.5, nz + 0.5]).
+template <bool FAST = false>
 __device__ __forceinline__ void z_clip(const LineP &L, const PlaneP &P, int nz, int &is, int &ie) {
     is = L.i_lo;
     ie = L.i_hi;
     if (P.zs != 0.f) {
-        float la = (-1.5f - P.zb) / P.zs, lb = ((float)nz + 0.5f - P.zb) / P.zs;
-        float ia = (fminf(la, lb) - L.lam0) / L.dlam, ib = (fmaxf(la, lb) - L.lam0) / L.dlam;
+        // FAST: reciprocals instead of divisions, for callers that clamp the
+        // axial position themselves (the range is then only a work bound)
+        const float rzs = FAST ? __builtin_amdgcn_rcpf(P.zs) : 0.f, rdl = FAST ? __builtin_amdgcn_rcpf(L.dlam) : 0.f;
+        float la = FAST ? (-1.5f - P.zb) * rzs : (-1.5f - P.zb) / P.zs;
+        float lb = FAST ? ((float)nz + 0.5f - P.zb) * rzs : ((float)nz + 0.5f - P.zb) / P.zs;
+        float ia = FAST ? (fminf(la, lb) - L.lam0) * rdl : (fminf(la, lb) - L.lam0) / L.dlam;
+        float ib = FAST ? (fmaxf(la, lb) - L.lam0) * rdl : (fmaxf(la, lb) - L.lam0) / L.dlam;
         float lo = ceilf(fminf(ia, ib)), hi = floorf(fmaxf(ia, ib));
         if (lo > (float)is) is = lo > (float)ie ? ie + 1 : (int)lo;
         if (hi < (float)ie) ie = hi < (float)is ? is - 1 : (int)hi;
@@ -300,51 +322,76 @@ __device__ __forceinline__ void read_w(const float *w4, const float *w1, int e1,
     for (int j = 4; j < NA; ++j) w[j] = w1[q * e1 + (j - 4)];
 }
 
-// Forward accumulation over the samples q in [c0, c1) (wave-uniform) of one
-// TOF interval with NA active bins; a lane only adds the samples of its own
-// z-valid range [qlo, qhi]. The axial position of the sample in principal
+// Sample loops of one TOF interval: n rows walked in t order from row pointer
+// xr / zr (row of the first sample, z padding skipped), principal-plane index
+// fi stepping by dfi and row stride drz. The weights of a row are the same
+// for every lane (broadcast LDS reads); the axial position of a sample in
 // plane i is zA * i + zB (voxel units).
 template <int NA>
-__device__ __forceinline__ void tof_fwd_run(const LineP &L, float zA, float zB, const float *X, const float *w4,
-                                            const float *w1, int e1, int rz, int c0, int c1, int qlo, int qhi,
-                                            float *win) {
-    for (int q = c0; q < c1; ++q) {
-        float w[NA];
-        read_w<NA>(w4, w1, e1, q, w);
-        const int i = L.dlam > 0.f ? L.i_lo + q : L.i_hi - q;
-        if (q >= qlo && q <= qhi) {
-            const float xz = fmaf((float)i, zA, zB);
-            const float jf = floorf(xz);
-            const float f = xz - jf;
-            const int ri = (i - L.i_lo) * rz + (int)jf + PADZ;
-            const float x0 = X[ri], x1 = X[ri + 1];
-            const float v = fmaf(f, x1 - x0, x0);
+__device__ __forceinline__ void read_wq(const float *wq, const float *w1q, float (&w)[NA]) {
+    const float4 v = *reinterpret_cast<const float4 *>(wq);
+    if (NA > 0) w[0] = v.x;
+    if (NA > 1) w[1] = v.y;
+    if (NA > 2) w[2] = v.z;
+    if (NA > 3) w[3] = v.w;
 #pragma unroll
-            for (int j = 0; j < NA; ++j) win[j] = fmaf(v, w[j], win[j]);
-        }
+    for (int j = 4; j < NA; ++j) w[j] = w1q[j - 4];
+}
+
+// Forward: no lane predicate. The axial position is clamped to [-2, nz]; a
+// sample outside the z-valid range [-1.5, nz + 0.5] then interpolates between
+// two cells of the zero padding and adds exactly zero, as does a lane without
+// a plane (zA = 0, zB = -2).
+template <int NA>
+__device__ __forceinline__ void tof_fwd_run(float zA, float zB, float zmax, const float *xr, int drz, float fi,
+                                            float dfi, const float *wq, const float *w1q, int e1, int n,
+                                            float *win) {
+#pragma unroll 2
+    for (; n > 0; --n) {
+        float w[NA];
+        read_wq<NA>(wq, w1q, w);
+        const float xz = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), -2.f, zmax);
+        const float jf = floorf(xz);
+        const float f = xz - jf;
+        const int j = (int)jf;
+        const float x0 = xr[j], x1 = xr[j + 1];
+        const float v = fmaf(f, x1 - x0, x0);
+#pragma unroll
+        for (int b = 0; b < NA; ++b) win[b] = fmaf(v, w[b], win[b]);
+        xr += drz;
+        fi += dfi;
+        wq += 4;
+        w1q += e1;
     }
 }
 
+// Adjoint: a lane adds its samples k = q - qlo in [0, span] only.
 template <int NA>
-__device__ __forceinline__ void tof_back_run(const LineP &L, float zA, float zB, double *Z, const float *w4,
-                                             const float *w1, int e1, int rz, int c0, int c1, int qlo, int qhi,
+__device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, double *zr, int drz, float fi, float dfi,
+                                             const float *wq, const float *w1q, int e1, int n, int k, unsigned span,
                                              const float *win) {
-    for (int q = c0; q < c1; ++q) {
+#pragma unroll 2
+    for (; n > 0; --n) {
         float w[NA];
-        read_w<NA>(w4, w1, e1, q, w);
-        const int i = L.dlam > 0.f ? L.i_lo + q : L.i_hi - q;
-        if (q >= qlo && q <= qhi) {
-            float Q = 0.f;
+        read_wq<NA>(wq, w1q, w);
+        float Q = 0.f;
 #pragma unroll
-            for (int j = 0; j < NA; ++j) Q = fmaf(win[j], w[j], Q);
-            const float xz = fmaf((float)i, zA, zB);
+        for (int b = 0; b < NA; ++b) Q = fmaf(win[b], w[b], Q);
+        if ((unsigned)k <= span) {
+            // (the clamp only guards the LDS bounds; valid samples lie inside)
+            const float xz = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), -2.f, zmax);
             const float jf = floorf(xz);
             const float f = xz - jf;
-            const int ri = (i - L.i_lo) * rz + (int)jf + PADZ;
             const float a1 = Q * f;
-            atomicAdd(&Z[ri], (double)(Q - a1));
-            atomicAdd(&Z[ri + 1], (double)a1);
+            const int j = (int)jf;
+            atomicAdd(&zr[j], (double)(Q - a1));
+            atomicAdd(&zr[j + 1], (double)a1);
         }
+        zr += drz;
+        fi += dfi;
+        wq += 4;
+        w1q += e1;
+        ++k;
     }
 }
 
@@ -403,7 +450,7 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
         const float len = sqrtf(L.lt2 + S.dz2);
         const float ell = L.vm_um * len;
         int is = 0, ie = -1;
-        if (nrow > 0 && has) z_clip(L, P, a.nz, is, ie);
+        if (nrow > 0 && has) z_clip<true>(L, P, a.nz, is, ie);
         // this lane's samples in t order: q in [qlo, qhi]
         const int qlo = L.dlam > 0.f ? is - L.i_lo : L.i_hi - ie;
         const int qhi = L.dlam > 0.f ? ie - L.i_lo : L.i_hi - is;
@@ -423,6 +470,13 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
             const int cut = nrow > 0 ? fill_table(a, L, len, cuts, w4, w1) : 0;
             // axial sample position of row i: xz = zA * i + zB
             const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb);
+            const float zAf = has ? zA : 0.f, zBf = has ? zB : -2.f, zmax = (float)a.nz;
+            const int drz = L.dlam > 0.f ? rz : -rz;
+            const float dfi = L.dlam > 0.f ? 1.f : -1.f;
+            // back-projection predicate: k = q - qlo_b in [0, span]; a lane with
+            // no samples gets a base far below every row
+            const unsigned span = qlo <= qhi ? (unsigned)(qhi - qlo) : 0u;
+            const int qlo_b = qlo <= qhi ? qlo : -(1 << 30);
             const int cut_next = __shfl_down(cut, 1, 64);
             // intervals with bins whose rows meet some lane's sample range
             int qa = qlo <= qhi ? qlo : INT_MAX, qb = qlo <= qhi ? qhi : -1;
@@ -448,7 +502,9 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
                     float win[WS_MAX];
 #pragma unroll
                     for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
-                    if (c1 > c0) PET_NA_SWITCH(tof_fwd_run, L, zA, zB, X, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
+                    const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                    PET_NA_SWITCH(tof_fwd_run, zAf, zBf, zmax, X + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
+                                  w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, win)
 #pragma unroll
                     for (int j = 0; j < WS_MAX; ++j)
                         if (j < na) acc[bf + j] += win[j];
@@ -458,19 +514,28 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
             // ---- ratio / output ----
             if (has) {
                 const float m = a.mult ? a.mult[lor] : 1.f;
-                for (int b = 0; b < nt; ++b) {
-                    const int64_t idx = lor * nt + b;
-                    if constexpr (MODE == M_BACK) {
-                        acc[b] = (a.sino ? a.sino[idx] : 1.f) * m * ell;
-                    } else {
-                        const float ybar = fmaf(m, acc[b] * ell, a.add ? a.add[idx] : 0.f);
+                const int64_t base = lor * nt;
+                if constexpr (MODE == M_BACK) {
+                    float sv[NT_MAX];
+                    if (a.sino) load_row(a.sino, base, nt, sv);
+#pragma unroll
+                    for (int b = 0; b < NT_MAX; ++b) acc[b] = (a.sino ? sv[b] : 1.f) * m * ell;
+                } else {
+                    float ad[NT_MAX], yv[NT_MAX];
+#pragma unroll
+                    for (int b = 0; b < NT_MAX; ++b) ad[b] = 0.f;
+                    if (a.add) load_row(a.add, base, nt, ad);
+                    if constexpr (MODE != M_FWD) load_y_row(a.y, a.y_dtype, base, nt, yv);
+#pragma unroll
+                    for (int b = 0; b < NT_MAX; ++b) {
+                        if (b >= nt) continue;
+                        const float ybar = fmaf(m, acc[b] * ell, ad[b]);
                         if constexpr (MODE == M_FWD) {
-                            a.out[idx] = ybar;
+                            a.out[base + b] = ybar;
                         } else {
-                            const float yv = load_y(a.y, a.y_dtype, idx);
-                            if (a.partial) kl += kl_term(ybar, yv);
-                            if constexpr (MODE == M_GRAD) acc[b] = m * fmaf(-yv, __builtin_amdgcn_rcpf(ybar), 1.f) * ell;
-                            if constexpr (MODE == M_EM) acc[b] = m * (yv * __builtin_amdgcn_rcpf(ybar)) * ell;
+                            if (a.partial) kl += kl_term(ybar, yv[b]);
+                            if constexpr (MODE == M_GRAD) acc[b] = m * fmaf(-yv[b], __builtin_amdgcn_rcpf(ybar), 1.f) * ell;
+                            if constexpr (MODE == M_EM) acc[b] = m * (yv[b] * __builtin_amdgcn_rcpf(ybar)) * ell;
                         }
                     }
                 }
@@ -487,7 +552,9 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
                     float win[WS_MAX];
 #pragma unroll
                     for (int j = 0; j < WS_MAX; ++j) win[j] = (j < na) ? acc[min(bf + j, NT_MAX - 1)] : 0.f;
-                    PET_NA_SWITCH(tof_back_run, L, zA, zB, Z, w4, w1, e1, rz, c0, c1, qlo, qhi, win)
+                    const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                    PET_NA_SWITCH(tof_back_run, zA, zB, zmax, Z + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
+                                  w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, c0 - qlo_b, span, win)
                 }
             }
             // the next segment overwrites this wave's table
