@@ -202,3 +202,22 @@ def make_dataset(cfg, chunk_views=16):
                 break
             code = 1 if mx <= 65535 else 2
     return dict(x_true=x_true, mult=a, r_lor=r_lor, r=r, y=y, y_dtype_code=code, scale=scale)
+
+
+def nrmse_region(cfg, scale):
+    """Evaluation region and reference level of the convergence NRMSE: the
+    voxels whose centres lie inside the phantom's first (outermost) shape, and
+    that shape's own value in the scaled phantom (background disc in 2D, grey
+    shell in 3D).  Returns (mask [nz][ny][nx] bool, level)."""
+    cx, cy, cz, ax, ay, az, rot, inc, _ = shapes(cfg)[0]
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    x = (np.arange(nx) - (nx - 1) / 2.0) * cfg["vx"]
+    y = (np.arange(ny) - (ny - 1) / 2.0) * cfg["vy"]
+    z = (np.arange(nz) - (nz - 1) / 2.0) * cfg["vz"]
+    zz, yy, xx = np.meshgrid(z, y, x, indexing="ij")
+    c, s = math.cos(rot), math.sin(rot)
+    u = (xx - cx) * c + (yy - cy) * s
+    v = -(xx - cx) * s + (yy - cy) * c
+    w = zz - cz
+    mask = (u / ax) ** 2 + (v / ay) ** 2 + (w / az) ** 2 <= 1.0
+    return mask, float(inc * scale)
