@@ -192,6 +192,82 @@ pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *state, float *x, const int
                           const float *tau, const uint8_t *update_pc, double *objective_out,
                           void *stream);
 
+/* Reverse mode (unrolled reconstruction) -----------------------------------
+ * Derivatives for differentiating through pet_svrg_epoch (Algorithm 1 with the
+ * clipped step of eq. (sgm)); the second derivatives of the data term follow
+ * from eq. (template) with d(s, t) of Section 2, those of the prior from
+ * Appendix A.
+ *
+ * Data-term Hessian-vector product of one subset (-1: all):
+ * hv_out (+)= P^T [mult^2 y / ybar^2 (mult P v)] with ybar = mult P x + add
+ * (bins with y = 0 contribute 0).  ybar_work: caller-owned device scratch of
+ * n_bins floats; the subset's bins receive ybar.  accumulate = 0 overwrites. */
+pet_status pet_subset_hvp(pet_geom g, int subset, const float *x, const float *v, const void *y,
+                          int y_dtype, const float *add, const float *mult, float *ybar_work,
+                          float *hv_out, int accumulate, void *stream);
+
+/* Prior Hessian-vector product: hv_out (+)= beta H_S(x) v with
+ * H_ii = 2 sum_j w k_i k_j (2 x_j + eps)^2 / psi^3 and
+ * H_ij = -2 w k_i k_j (2 x_i + eps)(2 x_j + eps) / psi^3 (neighbours j),
+ * psi = x_i + x_j + gamma |x_i - x_j| + eps.  gdot_out (device double,
+ * nullable) ACCUMULATES sum_i dS/dx_i v_i (unscaled by beta). */
+pet_status pet_rdp_hvp(pet_geom g, const float *x, const float *kappa, const float w[27], float beta,
+                       float gamma, float eps, const float *v, float *hv_out, int accumulate,
+                       double *gdot_out, void *stream);
+
+/* Vector-Jacobian product of the prior-aware preconditioner
+ * D(x, beta) = (x + delta) / (sens + alpha beta h_S(x) (x + delta)) (h_S the
+ * unscaled prior Hessian diagonal; D = 0 where the denominator is 0):
+ * xbar += (dD/dx)^T Dbar (a 27-point stencil, since h_S couples neighbours),
+ * betabar (device double) += <dD/dbeta, Dbar>. */
+pet_status pet_precond_vjp(pet_geom g, const float *x, const float *sens, const float *kappa,
+                           const float w[27], float beta, float gamma, float eps, float alpha,
+                           float delta, const float *Dbar, float *xbar, double *betabar, void *stream);
+
+/* Buffers of pet_svrg_epoch_vjp, all caller-owned device memory.
+ *   x_start     the iterate at the epoch's first iteration (forward checkpoint)
+ *   x_snap_src  the iterate of the snapshot iteration whose table the epoch
+ *               uses, when the epoch does not start with a snapshot (else NULL)
+ *   D_start     the preconditioner in effect before the epoch, when its first
+ *               iteration does not update it (else NULL)
+ *   xbar        in: dL/dx after the epoch; out: dL/dx_start
+ *   Dbar, gbar_i [n_subsets][n_vox], gbar: adjoints of the preconditioner and
+ *               of the snapshot table and sum in effect; carried from one
+ *               epoch's call to the previous epoch's (start them at 0)
+ *   betabar     device double, accumulates dL/dbeta
+ *   xs [(n_subsets + 1) n_vox], est [n_subsets n_vox], ybar_work [n_bins],
+ *   v [2 n_vox]: workspace. */
+typedef struct {
+    const float *x_start;
+    const float *x_snap_src;
+    const float *D_start;
+    float *xbar;
+    float *Dbar;
+    float *gbar_i;
+    float *gbar;
+    double *betabar;
+    float *xs;
+    float *est;
+    float *ybar_work;
+    float *v;
+} pet_svrg_vjp_bufs;
+
+/* Reverse of one pet_svrg_epoch for a scalar loss L: with state->k at the
+ * epoch's first iteration and the same subset_seq / tau / update_pc (host
+ * arrays), recomputes the epoch from the checkpoint (keeping its iterates and
+ * estimators), then sweeps the iterations backwards:
+ *   u = xbar [x_next > 0];  Dbar += -tau u est;  v = -tau D u;  xbar = u
+ *     + beta H_S(x) v + (n H_i(x) v, gbar_i -= n v, gbar += v)        regular
+ *     + beta H_S(x) v + sum_q H_q(x) (gbar_q + gbar + v), gbar* = 0   snapshot
+ *     + (dD/dx)^T Dbar, Dbar = 0                                    D update
+ *   betabar += <grad S(x), v> (+ <dD/dbeta, Dbar> at a D update).
+ * Preconditioner updates and snapshots must fall on the epoch's first
+ * iteration (PET_E_ARG otherwise).  The state's ghat_i, ghat and D are
+ * overwritten (recompute scratch); state->k is not advanced. */
+pet_status pet_svrg_epoch_vjp(pet_geom g, const pet_svrg_state *state, pet_svrg_vjp_bufs *bufs,
+                              const int32_t *subset_seq, const float *tau, const uint8_t *update_pc,
+                              void *stream);
+
 /* Instrumentation --------------------------------------------------------
  * Work of the line kernels on `subset` (-1: all), exactly as they traverse it:
  * out[0] = Joseph samples, out[1] = sample-TOF-bin pairs with nonzero weight
@@ -202,7 +278,8 @@ pet_status pet_work_counts(pet_geom g, int subset, double *out, void *stream);
  * the launch stream (enable != 0), and read the accumulated time and count of
  * one kernel (PET_KERNEL_*) since the last read; reading synchronises on the
  * recorded events and resets that kernel's record. */
-enum { PET_KERNEL_FWD = 0, PET_KERNEL_BACK = 1, PET_KERNEL_GRAD = 2, PET_KERNEL_EM = 3, PET_KERNEL_OBJ = 4 };
+enum { PET_KERNEL_FWD = 0, PET_KERNEL_BACK = 1, PET_KERNEL_GRAD = 2, PET_KERNEL_EM = 3, PET_KERNEL_OBJ = 4,
+       PET_KERNEL_HVP = 6 };
 pet_status pet_profile_enable(pet_geom g, int enable);
 pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms, int64_t *launches);
 

@@ -119,10 +119,15 @@ class Unrolled:
         p = self.prob
         return self.data_grad(x, i) + beta / self.n * prior_grad(x, p.w, p.gamma, p.eps, self.kappa)
 
-    def svrg(self, x0, log_beta, n_epochs, orders, taus, update_iters, omega=2):
+    def svrg(self, x0, log_beta, n_epochs, orders, taus, update_iters, omega=2, clip_masks=None, record=None):
         """Final image after n_epochs epochs of Algorithm 1 (clipped step);
         orders[e][j] is the subset of iteration j of epoch e, taus[e][j] its
-        step size, update_iters the iterations that recompute D."""
+        step size, update_iters the iterations that recompute D.
+
+        clip_masks (one boolean image per iteration) replaces the clip by the
+        fixed selection u * mask: the map restricted to one smooth piece, whose
+        derivative at the run that recorded the masks (record: a list that
+        receives [u > 0] per iteration) equals the clipped map's."""
         p = self.prob
         n = self.n
         beta = torch.exp(log_beta)
@@ -142,7 +147,12 @@ class Unrolled:
                 i = int(orders[e][j])
                 g = n * (self.grad_J(x, i, beta) - ghat_i[i]) + ghat
             u = x - float(taus[e][j]) * D * g
-            x = torch.where(u > 0, u, torch.zeros_like(u))
+            if record is not None:
+                record.append((u > 0).detach().clone())
+            if clip_masks is not None:
+                x = u * clip_masks[k]
+            else:
+                x = torch.where(u > 0, u, torch.zeros_like(u))
         return x
 
 
@@ -158,12 +168,13 @@ def loss_and_grads(prob, x0, log_beta, x_target, n_epochs, orders, taus, update_
     return float(L.detach()), x0t.grad.numpy().copy(), float(lb.grad), xf.detach().numpy()
 
 
-def loss(prob, x0, log_beta, x_target, n_epochs, orders, taus, update_iters, omega=2):
-    """L only (no graph), for finite differences."""
+def loss(prob, x0, log_beta, x_target, n_epochs, orders, taus, update_iters, omega=2, clip_masks=None, record=None):
+    """L only (no graph), for finite differences; clip_masks / record as in
+    Unrolled.svrg."""
     u = Unrolled(prob)
     with torch.no_grad():
         x0t = torch.from_numpy(np.asarray(x0, np.float64).reshape(prob.shape).copy())
         xf = u.svrg(x0t, torch.tensor(float(log_beta), dtype=torch.float64), n_epochs, orders, taus, update_iters,
-                    omega)
+                    omega, clip_masks, record)
         tgt = torch.from_numpy(np.asarray(x_target, np.float64).reshape(prob.shape))
         return float(((xf - tgt) ** 2).sum())

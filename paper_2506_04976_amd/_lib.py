@@ -26,8 +26,10 @@ _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "P
 
 EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
+           "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
            "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
 PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
+PET_KERNEL_HVP = 6
 
 
 class PetError(RuntimeError):
@@ -55,6 +57,12 @@ class SvrgState(ctypes.Structure):
                 ("delta", ctypes.c_float), ("omega", ctypes.c_int), ("k", ctypes.c_int64)]
 
 
+class SvrgVjpBufs(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("x_start", "x_snap_src", "D_start", "xbar", "Dbar", "gbar_i", "gbar", "betabar", "xs", "est",
+                 "ybar_work", "v")]
+
+
 _lib = None
 
 
@@ -80,6 +88,12 @@ def lib():
         L.pet_objective.argtypes = [P, P, P, I, P, P, P, ctypes.POINTER(F), F, F, F, P, P]
         L.pet_svrg_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), P, P]
+        L.pet_subset_hvp.argtypes = [P, I, P, P, P, I, P, P, P, P, I, P]
+        L.pet_rdp_hvp.argtypes = [P, P, P, ctypes.POINTER(F), F, F, F, P, P, I, P, P]
+        L.pet_precond_vjp.argtypes = [P, P, P, P, ctypes.POINTER(F), F, F, F, F, F, P, P, P, P]
+        L.pet_svrg_epoch_vjp.argtypes = [P, ctypes.POINTER(SvrgState), ctypes.POINTER(SvrgVjpBufs),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(F),
+                                         ctypes.POINTER(ctypes.c_uint8), P]
         L.pet_work_counts.argtypes = [P, I, P, P]
         L.pet_profile_enable.argtypes = [P, I]
         L.pet_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
@@ -267,6 +281,47 @@ def pet_svrg_epoch(geom, state, x, subset_seq, tau, update_pc, objective_out=Non
     return x
 
 
+def pet_subset_hvp(geom, subset, x, v, y, add, mult, ybar_work, hv_out, accumulate=False, stream=None):
+    _check(lib().pet_subset_hvp(geom.handle, subset, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                _ptr(v, torch.float32, geom.n_vox, "v"), _ptr(y, None, geom.n_bins, "y"),
+                                y_dtype_code(y), _ptr(add, torch.float32, geom.n_bins, "add"),
+                                _ptr(mult, torch.float32, geom.n_lors, "mult"),
+                                _ptr(ybar_work, torch.float32, geom.n_bins, "ybar_work"),
+                                _ptr(hv_out, torch.float32, geom.n_vox, "hv_out"), 1 if accumulate else 0,
+                                _stream(stream)))
+    return hv_out
+
+
+def pet_rdp_hvp(geom, x, kappa, w27, beta, gamma, eps, v, hv_out, accumulate=False, gdot_out=None, stream=None):
+    _check(lib().pet_rdp_hvp(geom.handle, _ptr(x, torch.float32, geom.n_vox, "x"),
+                             _ptr(kappa, torch.float32, geom.n_vox, "kappa"), _w27(w27), beta, gamma, eps,
+                             _ptr(v, torch.float32, geom.n_vox, "v"), _ptr(hv_out, torch.float32, geom.n_vox, "hv_out"),
+                             1 if accumulate else 0, _ptr(gdot_out, torch.float64, 1, "gdot_out"), _stream(stream)))
+    return hv_out
+
+
+def pet_precond_vjp(geom, x, sens, kappa, w27, beta, gamma, eps, alpha, delta, Dbar, xbar, betabar, stream=None):
+    _check(lib().pet_precond_vjp(geom.handle, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                 _ptr(sens, torch.float32, geom.n_vox, "sens"),
+                                 _ptr(kappa, torch.float32, geom.n_vox, "kappa"), _w27(w27), beta, gamma, eps, alpha,
+                                 delta, _ptr(Dbar, torch.float32, geom.n_vox, "Dbar"),
+                                 _ptr(xbar, torch.float32, geom.n_vox, "xbar"),
+                                 _ptr(betabar, torch.float64, 1, "betabar"), _stream(stream)))
+    return xbar
+
+
+def pet_svrg_epoch_vjp(geom, state, bufs, subset_seq, tau, update_pc, stream=None):
+    """state: SvrgStateBuffers with k at the epoch's first iteration; bufs: VjpBuffers."""
+    n = geom.n_subsets
+    if not (len(subset_seq) == len(tau) == len(update_pc) == n):
+        raise ValueError("subset_seq, tau and update_pc need n_subsets entries each")
+    seq = (ctypes.c_int32 * n)(*[int(v) for v in subset_seq])
+    taus = (ctypes.c_float * n)(*[float(v) for v in tau])
+    upd = (ctypes.c_uint8 * n)(*[1 if v else 0 for v in update_pc])
+    _check(lib().pet_svrg_epoch_vjp(geom.handle, ctypes.byref(state.c), ctypes.byref(bufs.c), seq, taus, upd,
+                                    _stream(stream)))
+
+
 def pet_work_counts(geom, subset, out, stream=None):
     """out: CUDA float64 tensor of 2 elements -> (samples, sample-bin pairs)."""
     _check(lib().pet_work_counts(geom.handle, subset, _ptr(out, torch.float64, 2, "out"), _stream(stream)))
@@ -319,3 +374,32 @@ class SvrgStateBuffers:
     @property
     def k(self):
         return self.c.k
+
+
+class VjpBuffers:
+    """Device buffers + the C struct of pet_svrg_epoch_vjp (reverse carry and
+    workspace); the checkpoint pointers are set per call with set_checkpoint."""
+
+    def __init__(self, geom, device):
+        n, nv = geom.n_subsets, geom.n_vox
+        f32 = dict(dtype=torch.float32, device=device)
+        self.xbar = torch.zeros(nv, **f32)
+        self.Dbar = torch.zeros(nv, **f32)
+        self.gbar_i = torch.zeros((n, nv), **f32)
+        self.gbar = torch.zeros(nv, **f32)
+        self.betabar = torch.zeros(1, dtype=torch.float64, device=device)
+        self.xs = torch.zeros((n + 1, nv), **f32)
+        self.est = torch.zeros((n, nv), **f32)
+        self.ybar_work = torch.zeros(geom.n_bins, **f32)
+        self.v = torch.zeros((2, nv), **f32)
+        c = SvrgVjpBufs()
+        for name in ("xbar", "Dbar", "gbar_i", "gbar", "betabar", "xs", "est", "ybar_work", "v"):
+            setattr(c, name, getattr(self, name).data_ptr())
+        self.c = c
+        self.nv = nv
+
+    def set_checkpoint(self, x_start, x_snap_src=None, D_start=None):
+        self._ck = (x_start, x_snap_src, D_start)
+        self.c.x_start = _ptr(x_start, torch.float32, self.nv, "x_start").value
+        self.c.x_snap_src = _ptr(x_snap_src, torch.float32, self.nv, "x_snap_src").value if x_snap_src is not None else None
+        self.c.D_start = _ptr(D_start, torch.float32, self.nv, "D_start").value if D_start is not None else None

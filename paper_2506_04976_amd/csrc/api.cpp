@@ -91,6 +91,28 @@ hipError_t objective_impl(pet_geom g, const float *x, const void *y, int dt, con
     return e;
 }
 
+// H_subset(x) v = P^T [mult^2 y / ybar^2 (mult P v)] with ybar = mult P x + add
+// written to ybar_work (the subset's bins) on the way.
+hipError_t hvp_impl(pet_geom g, int subset, const float *x, const float *v, const void *y, int dt, const float *add,
+                    const float *mult, float *ybar_work, float *out, int accumulate, hipStream_t s) {
+    hipError_t e = launch_to_sheets(g, x, s);
+    ProjArgs a = base_args(g, subset);
+    a.add = add;
+    a.mult = mult;
+    a.out = ybar_work;
+    if (e == hipSuccess) e = launch_line_kernel(g, M_FWD, subset, a, s);
+    if (e == hipSuccess) e = launch_to_sheets(g, v, s);
+    if (e == hipSuccess) e = launch_zero_sheets(g, s);
+    ProjArgs b = base_args(g, subset);
+    b.y = y;
+    b.y_dtype = dt;
+    b.mult = mult;
+    b.ybar = ybar_work;
+    if (e == hipSuccess) e = launch_line_kernel(g, M_HVP, subset, b, s);
+    if (e == hipSuccess) e = launch_from_sheets(g, out, accumulate, s);
+    return e;
+}
+
 }  // namespace
 }  // namespace pet
 
@@ -232,7 +254,7 @@ extern "C" pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *st, float *x, c
             const int i = subset_seq[j];
             e = launch_svrg_step(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
                                  st->alpha, st->delta, st->D, snap, g->g, st->ghat_i + (size_t)i * nv, st->ghat,
-                                 (float)n, tau[j], g->xtmp, s);
+                                 (float)n, tau[j], g->xtmp, nullptr, s);
         }
         if (e == hipSuccess) e = launch_copy(x, g->xtmp, nv, s);
     }
@@ -265,7 +287,7 @@ extern "C" pet_status pet_profile_enable(pet_geom g, int enable) {
 
 extern "C" pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms, int64_t *launches) {
     if (!g || !total_ms || !launches) return fail(PET_E_ARG, "pet_profile_read: null argument");
-    if (kernel < 0 || kernel >= M_COUNT) return fail(PET_E_ARG, "pet_profile_read: unknown kernel");
+    if (kernel < 0 || kernel >= M_NMODES || kernel == M_COUNT) return fail(PET_E_ARG, "pet_profile_read: unknown kernel");
     double ms = 0.0;
     auto &v = g->prof_events[kernel];
     for (auto &ev : v) {
@@ -280,4 +302,134 @@ extern "C" pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms,
     *launches = (int64_t)v.size();
     v.clear();
     return PET_OK;
+}
+
+extern "C" pet_status pet_subset_hvp(pet_geom g, int subset, const float *x, const float *v, const void *y,
+                                     int y_dtype, const float *add, const float *mult, float *ybar_work,
+                                     float *hv_out, int accumulate, void *stream) {
+    if (!g || !x || !v || !y || !ybar_work || !hv_out) return fail(PET_E_ARG, "pet_subset_hvp: null argument");
+    if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_subset_hvp: subset out of range");
+    if (!valid_dtype(y_dtype)) return fail(PET_E_ARG, "pet_subset_hvp: bad y dtype");
+    return hip_check(hvp_impl(g, subset, x, v, y, y_dtype, add, mult, ybar_work, hv_out, accumulate,
+                              (hipStream_t)stream),
+                     "pet_subset_hvp");
+}
+
+extern "C" pet_status pet_rdp_hvp(pet_geom g, const float *x, const float *kappa, const float w[27], float beta,
+                                  float gamma, float eps, const float *v, float *hv_out, int accumulate,
+                                  double *gdot_out, void *stream) {
+    if (!g || !x || !w || !v || !hv_out) return fail(PET_E_ARG, "pet_rdp_hvp: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_rdp_hvp(g, x, kappa, w, beta, gamma, eps, v, hv_out, accumulate,
+                                  gdot_out ? g->partial : nullptr, s);
+    if (e == hipSuccess && gdot_out) e = launch_reduce_sum(g->partial, adj_blocks(g), gdot_out, 1, s);
+    return hip_check(e, "pet_rdp_hvp");
+}
+
+extern "C" pet_status pet_precond_vjp(pet_geom g, const float *x, const float *sens, const float *kappa,
+                                      const float w[27], float beta, float gamma, float eps, float alpha, float delta,
+                                      const float *Dbar, float *xbar, double *betabar, void *stream) {
+    if (!g || !x || !sens || !w || !Dbar || !xbar || !betabar) return fail(PET_E_ARG, "pet_precond_vjp: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_precond_vjp(g, x, kappa, w, beta, gamma, eps, sens, alpha, delta, Dbar, xbar, g->hess,
+                                      g->partial, s);
+    if (e == hipSuccess) e = launch_reduce_sum(g->partial, adj_blocks(g), betabar, 1, s);
+    return hip_check(e, "pet_precond_vjp");
+}
+
+extern "C" pet_status pet_svrg_epoch_vjp(pet_geom g, const pet_svrg_state *st, pet_svrg_vjp_bufs *b,
+                                         const int32_t *subset_seq, const float *tau, const uint8_t *update_pc,
+                                         void *stream) {
+    if (!g || !st || !b || !subset_seq || !tau || !update_pc) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: null argument");
+    if (!st->ghat_i || !st->ghat || !st->D || !st->sens || !st->y)
+        return fail(PET_E_ARG, "pet_svrg_epoch_vjp: incomplete state");
+    if (!b->x_start || !b->xbar || !b->Dbar || !b->gbar_i || !b->gbar || !b->betabar || !b->xs || !b->est ||
+        !b->ybar_work || !b->v)
+        return fail(PET_E_ARG, "pet_svrg_epoch_vjp: incomplete buffers");
+    if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: bad y dtype");
+    if (st->omega < 1 || st->k < 0) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: bad omega or iteration counter");
+    const int n = g->d.n_subsets;
+    const int64_t nv = g->n_vox;
+    const int64_t om = (int64_t)st->omega * n;
+    for (int j = 0; j < n; ++j) {
+        if (subset_seq[j] < 0 || subset_seq[j] >= n) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: subset_seq entry out of range");
+        if (j > 0 && update_pc[j]) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: preconditioner updates only at the epoch's first iteration");
+        if (j > 0 && (st->k + j) % om == 0) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: snapshots only at the epoch's first iteration");
+    }
+    const bool snap0 = st->k % om == 0;
+    if (!snap0 && !b->x_snap_src) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: x_snap_src needed (epoch without snapshot)");
+    if (!update_pc[0] && !b->D_start) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: D_start needed (no update at the epoch start)");
+    hipStream_t s = (hipStream_t)stream;
+    float *v = b->v, *tmp = b->v + nv;
+    auto xs = [&](int j) { return b->xs + (size_t)j * nv; };
+    hipError_t e = hipSuccess;
+
+    // ---- recompute the epoch, keeping every iterate and estimator ----
+    if (!snap0) {
+        e = launch_to_sheets(g, b->x_snap_src, s);
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            e = subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+            if (e == hipSuccess) e = launch_snapshot_accum(g, st->ghat_i + (size_t)i * nv, st->ghat, nullptr, i == 0, s);
+        }
+    }
+    if (e == hipSuccess && !update_pc[0]) e = launch_copy(st->D, b->D_start, nv, s);
+    if (e == hipSuccess) e = launch_copy(xs(0), b->x_start, nv, s);
+    for (int j = 0; j < n && e == hipSuccess; ++j) {
+        const bool snap = (st->k + j) % om == 0;
+        const int i = subset_seq[j];
+        e = launch_to_sheets(g, xs(j), s);
+        if (snap) {
+            for (int q = 0; q < n && e == hipSuccess; ++q) {
+                e = subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+                if (e == hipSuccess) e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s);
+            }
+        } else {
+            e = subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+            if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
+        }
+        if (e == hipSuccess)
+            e = launch_svrg_step(g, xs(j), st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
+                                 st->alpha, st->delta, st->D, snap, g->g, st->ghat_i + (size_t)i * nv, st->ghat,
+                                 (float)n, tau[j], xs(j + 1), b->est + (size_t)j * nv, s);
+    }
+
+    // ---- reverse sweep ----
+    for (int j = n - 1; j >= 0 && e == hipSuccess; --j) {
+        const bool snap = (st->k + j) % om == 0;
+        const int i = subset_seq[j];
+        // clip and step: xbar <- u, Dbar += -tau u est, v = -tau D u
+        e = launch_step_vjp(g, xs(j + 1), st->D, b->est + (size_t)j * nv, tau[j], b->xbar, b->Dbar, v, s);
+        // prior: xbar += beta H_S v, dL/dbeta += <grad S, v>
+        if (e == hipSuccess)
+            e = launch_rdp_hvp(g, xs(j), st->kappa, st->w, st->beta, st->gamma, st->eps, v, b->xbar, 1, g->partial, s);
+        if (e == hipSuccess) e = launch_reduce_sum(g->partial, adj_blocks(g), b->betabar, 1, s);
+        if (e != hipSuccess) break;
+        if (!snap) {
+            // est = n (g_i(x) - ghat_i) + ghat + ...: xbar += n H_i v, gbar_i -= n v, gbar += v
+            float *gbi = b->gbar_i + (size_t)i * nv;
+            e = launch_lincomb(tmp, (float)n, v, 0.f, nullptr, nv, s);
+            if (e == hipSuccess)
+                e = hvp_impl(g, i, xs(j), tmp, st->y, st->y_dtype, st->add, st->mult, b->ybar_work, b->xbar, 1, s);
+            if (e == hipSuccess) e = launch_lincomb(gbi, 1.f, gbi, -(float)n, v, nv, s);
+            if (e == hipSuccess) e = launch_lincomb(b->gbar, 1.f, b->gbar, 1.f, v, nv, s);
+        } else {
+            // est = ghat + ...: the snapshot table and sum were produced here from x_j
+            e = launch_lincomb(b->gbar, 1.f, b->gbar, 1.f, v, nv, s);
+            for (int q = 0; q < n && e == hipSuccess; ++q) {
+                float *gbq = b->gbar_i + (size_t)q * nv;
+                e = launch_lincomb(tmp, 1.f, gbq, 1.f, b->gbar, nv, s);
+                if (e == hipSuccess)
+                    e = hvp_impl(g, q, xs(j), tmp, st->y, st->y_dtype, st->add, st->mult, b->ybar_work, b->xbar, 1, s);
+                if (e == hipSuccess) e = launch_fill(gbq, nv, 0.f, s);
+            }
+            if (e == hipSuccess) e = launch_fill(b->gbar, nv, 0.f, s);
+        }
+        if (e == hipSuccess && update_pc[j]) {
+            e = launch_precond_vjp(g, xs(j), st->kappa, st->w, st->beta, st->gamma, st->eps, st->sens, st->alpha,
+                                   st->delta, b->Dbar, b->xbar, tmp, g->partial, s);
+            if (e == hipSuccess) e = launch_reduce_sum(g->partial, adj_blocks(g), b->betabar, 1, s);
+            if (e == hipSuccess) e = launch_fill(b->Dbar, nv, 0.f, s);
+        }
+    }
+    return hip_check(e, "pet_svrg_epoch_vjp");
 }

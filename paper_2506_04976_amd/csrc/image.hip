@@ -57,6 +57,7 @@ enum RdpFlags {
     R_PRECOND = 8,    // write D = (x + delta) / (sens + alpha beta H (x + delta))
     R_UPDATE = 16,    // SVRG step with clip into x_out
     R_SNAPSHOT = 32,  // estimator is ghat + beta grad S (snapshot iteration)
+    R_EST_OUT = 64,   // also write the estimator (for the reverse pass)
 };
 
 struct RdpArgs {
@@ -74,7 +75,7 @@ struct RdpArgs {
     const float *gi, *ghat_i;
     const double *ghat;
     float n_sub, tau;
-    float *x_out;
+    float *x_out, *est_out;
 };
 
 // One thread per voxel.  RDP (eq. (rdp)) with gradient and Hessian diagonal as
@@ -144,6 +145,7 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
             } else {
                 est = fmaf(a.n_sub, a.gi[v] - a.ghat_i[v], (float)a.ghat[v]) + bg;
             }
+            if (F & R_EST_OUT) a.est_out[v] = est;
             a.x_out[v] = fmaxf(0.f, fmaf(-a.tau * Dv, est, xi));
         }
     }
@@ -295,7 +297,7 @@ hipError_t launch_precond(const pet_geom_s *g, const float *x, const float *sens
 hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
                             float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
                             float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
-                            float n_sub, float tau, float *x_out, hipStream_t s) {
+                            float n_sub, float tau, float *x_out, float *est_out, hipStream_t s) {
     RdpArgs a{};
     a.x = x;
     a.kappa = kappa;
@@ -316,12 +318,18 @@ hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *ka
     a.n_sub = n_sub;
     a.tau = tau;
     a.x_out = x_out;
-    if (update_pc) {
-        if (snapshot) return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
-        return rdp_launch<R_PRECOND | R_UPDATE>(a, g->n_vox, s);
+    a.est_out = est_out;
+    const int f = (update_pc ? 4 : 0) | (snapshot ? 2 : 0) | (est_out ? 1 : 0);
+    switch (f) {
+        case 0: return rdp_launch<R_UPDATE>(a, g->n_vox, s);
+        case 1: return rdp_launch<R_UPDATE | R_EST_OUT>(a, g->n_vox, s);
+        case 2: return rdp_launch<R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
+        case 3: return rdp_launch<R_UPDATE | R_SNAPSHOT | R_EST_OUT>(a, g->n_vox, s);
+        case 4: return rdp_launch<R_PRECOND | R_UPDATE>(a, g->n_vox, s);
+        case 5: return rdp_launch<R_PRECOND | R_UPDATE | R_EST_OUT>(a, g->n_vox, s);
+        case 6: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
+        default: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT | R_EST_OUT>(a, g->n_vox, s);
     }
-    if (snapshot) return rdp_launch<R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
-    return rdp_launch<R_UPDATE>(a, g->n_vox, s);
 }
 
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
@@ -343,6 +351,11 @@ hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, c
 
 hipError_t launch_max(const pet_geom_s *g, const float *x, float *out, hipStream_t s) {
     hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, s, x, g->n_vox, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *dst, int64_t n, float val, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, grid_for(n), dim3(IMG_BLOCK), 0, s, dst, n, val);
     return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ struct TofTable {
     float erf_clamp;        // nsig / sqrt2: truncation of the Gaussian kernel
 };
 
-enum Mode { M_FWD = 0, M_BACK = 1, M_GRAD = 2, M_EM = 3, M_OBJ = 4, M_COUNT = 5, M_NMODES = 6 };
+enum Mode { M_FWD = 0, M_BACK = 1, M_GRAD = 2, M_EM = 3, M_OBJ = 4, M_COUNT = 5, M_HVP = 6, M_NMODES = 7 };
 
 struct ProjArgs {
     const LineP *lines;
@@ -82,6 +82,7 @@ struct ProjArgs {
     const void *y;
     int y_dtype;
     const float *add, *mult, *sino;
+    const float *ybar;  // M_HVP: mean data mult P x + add at the linearisation point
     float *out;
     double *partial;  // one double per block (KL sum), or null
     TofTable tof;
@@ -145,10 +146,22 @@ hipError_t launch_max(const pet_geom_s *g, const float *x, float *out, hipStream
 hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
                             float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
                             float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
-                            float n_sub, float tau, float *x_out, hipStream_t s);
+                            float n_sub, float tau, float *x_out, float *est_out, hipStream_t s);
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
                                  hipStream_t s);
 int rdp_blocks(const pet_geom_s *g);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
+hipError_t launch_fill(float *dst, int64_t n, float val, hipStream_t s);
+// reverse-mode kernels (adjoint.hip)
+int adj_blocks(const pet_geom_s *g);
+hipError_t launch_rdp_hvp(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
+                          float gamma, float eps, const float *v, float *out, int accumulate, double *partial,
+                          hipStream_t s);
+hipError_t launch_precond_vjp(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
+                              float gamma, float eps, const float *sens, float alpha, float delta,
+                              const float *Dbar, float *xbar, float *e_tmp, double *partial, hipStream_t s);
+hipError_t launch_step_vjp(const pet_geom_s *g, const float *x_next, const float *D, const float *est, float tau,
+                           float *xbar, float *Dbar, float *v, hipStream_t s);
+hipError_t launch_lincomb(float *out, float ca, const float *a, float cb, const float *b, int64_t n, hipStream_t s);
 
 }  // namespace pet

@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
     extern __shared__ float4 smem4[];
     float *smem = reinterpret_cast<float *>(smem4);
     constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
-    constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM;
+    constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM || MODE == M_HVP;
     const int jv = blockIdx.x / a.n_rad;
     const int k = blockIdx.x - jv * a.n_rad;
     const int line = a.views[jv] * a.n_rad + k;
@@ -210,6 +210,11 @@ __global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
         float Q = 0.f;
         if constexpr (MODE == M_BACK) {
             Q = (a.sino ? a.sino[lor] : 1.f) * m * ell;
+        } else if constexpr (MODE == M_HVP) {
+            // data-term Hessian: mult^2 y / ybar^2 (P v), then back
+            const float yv = load_y(a.y, a.y_dtype, lor);
+            const float yb = a.ybar[lor];
+            Q = yv != 0.f ? m * m * yv / (yb * yb) * (s * ell) * ell : 0.f;
         } else {
             float ybar = fmaf(m, s * ell, a.add ? a.add[lor] : 0.f);
             if constexpr (MODE == M_FWD) {
@@ -412,7 +417,7 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
     extern __shared__ float4 smem4[];
     float *smem = reinterpret_cast<float *>(smem4);
     constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
-    constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM;
+    constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM || MODE == M_HVP;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -520,6 +525,13 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
                     if (a.sino) load_row(a.sino, base, nt, sv);
 #pragma unroll
                     for (int b = 0; b < NT_MAX; ++b) acc[b] = (a.sino ? sv[b] : 1.f) * m * ell;
+                } else if constexpr (MODE == M_HVP) {
+                    float yb[NT_MAX], yv[NT_MAX];
+                    load_row(a.ybar, base, nt, yb);
+                    load_y_row(a.y, a.y_dtype, base, nt, yv);
+#pragma unroll
+                    for (int b = 0; b < NT_MAX; ++b)
+                        acc[b] = (b < nt && yv[b] != 0.f) ? m * m * yv[b] / (yb[b] * yb[b]) * (acc[b] * ell) * ell : 0.f;
                 } else {
                     float ad[NT_MAX], yv[NT_MAX];
 #pragma unroll
@@ -606,6 +618,7 @@ hipError_t launch_line_kernel_impl(const pet_geom_s *g, int mode, dim3 grid, con
         case M_EM: return launch_mode<M_EM>(g, grid, a, s);
         case M_OBJ: return launch_mode<M_OBJ>(g, grid, a, s);
         case M_COUNT: return launch_mode<M_COUNT>(g, grid, a, s);
+        case M_HVP: return launch_mode<M_HVP>(g, grid, a, s);
         default: return hipErrorInvalidValue;
     }
 }
