@@ -16,6 +16,7 @@ resident in HBM before timing starts.  One JSON line is printed.
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -183,6 +184,69 @@ def time_to_nrmse(args, cfg, geom, pm, epoch, y, r, a, beta, eps, delta, x0_host
             "region_voxels": int(nm), "level": level}
 
 
+def differentiable_leg(pm):
+    """Unrolled reconstruction of the differentiable workload (96x96x32 image,
+    120 views x 180 radial x 268 planes, 8 subsets, 10 epochs): plain SVRG
+    epochs/s against forward + reverse (torch.autograd through the unrolled
+    epochs with per-epoch checkpoints) epochs/s, same GPU, same schedule."""
+    import numpy as np
+    import torch
+    from synth import configs, data
+
+    cfg = configs.get("c3_diff")
+    dev = torch.device("cuda:0")
+    n, E = cfg["n_subsets"], cfg["epochs"]
+    d = data.make_dataset(cfg)
+    y = torch.from_numpy(d["y"].reshape(-1)).to(dev)
+    r = torch.from_numpy(d["r"].reshape(-1)).to(dev)
+    a = torch.from_numpy(d["mult"].reshape(-1)).to(dev)
+    tgt = torch.from_numpy(d["x_true"].reshape(-1)).to(dev)
+    geom = pm.Geometry(cfg)
+    sens = torch.empty(geom.n_vox, device=dev)
+    pm.pet_back(geom, -1, None, a, sens)
+    x0 = torch.ones(geom.n_vox, device=dev)
+    xmax = torch.zeros(1, device=dev)
+    pm.pet_osem_epoch(geom, x0, y, r, a, list(range(n)), xmax)
+    eps = delta = 1e-3 * float(xmax.cpu())
+    beta = configs.beta_value(cfg)
+    orders = data.subset_orders(cfg, E)
+    taus = [[1.0 / (1.0 + 0.02 * (e * n + j) / n) for j in range(n)] for e in range(E)]
+    upd = [[(e * n + j) in (0, n, 2 * n) for j in range(n)] for e in range(E)]
+    prob = pm.UnrolledProblem(geom, y, r, a, sens, gamma=cfg["gamma"], eps=eps, alpha=1.0, delta=delta,
+                              orders=orders, taus=taus, updates=upd)
+
+    def plain():
+        st = prob.state(beta)
+        x = x0.clone()
+        for e in range(E):
+            pm.pet_svrg_epoch(geom, st, x, orders[e], taus[e], upd[e])
+        return x
+
+    def diff():
+        xi = x0.clone().requires_grad_(True)
+        lb = torch.tensor(math.log(beta), dtype=torch.float64, device=dev, requires_grad=True)
+        xf = pm.unrolled_svrg(xi, lb, prob)
+        ((xf - tgt) ** 2).sum().backward()
+        return xi.grad
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    tp, td = timed(plain), timed(diff)
+    geom.close()
+    return {"workload": f"c3_diff: {cfg['nx']}x{cfg['ny']}x{cfg['nz']} image, {cfg['n_views']} views x "
+                        f"{cfg['n_rad']} radial x {configs.n_planes(cfg)} planes, {n} subsets, {E} unrolled epochs",
+            "plain_epochs_per_s": E / tp, "forward_reverse_epochs_per_s": E / td, "reverse_cost_ratio": td / tp}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +258,7 @@ def main():
     ap.add_argument("--ref-iters", type=int, default=500,
                     help="L-BFGS-B iterations (at most) of the converged reference image for the NRMSE")
     ap.add_argument("--nrmse-max-epochs", type=int, default=200)
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiable (unrolled) leg")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size reference kernel "
                          "for calibrating hardware byte counters)")
@@ -314,6 +379,11 @@ def main():
         nrmse = time_to_nrmse(args, cfg, geom, pm, epoch, y, r, a, beta, eps, delta, x0_host,
                               nrmse_mask, nrmse_level)
 
+    diff = None
+    if not args.no_diff:
+        log("[bench] differentiable leg (unrolled SVRG, forward + reverse) ...")
+        diff = differentiable_leg(pm)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a one-view sample ...")
@@ -348,6 +418,7 @@ def main():
         "hbm_gbps_epoch": epoch_bytes * value / 1e9,
         "objective_final": objective,
         "time_to_nrmse": nrmse,
+        "differentiable": diff,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
