@@ -268,6 +268,46 @@ pet_status pet_svrg_epoch_vjp(pet_geom g, const pet_svrg_state *state, pet_svrg_
                               const int32_t *subset_seq, const float *tau, const uint8_t *update_pc,
                               void *stream);
 
+/* Batches of reconstructions ------------------------------------------------
+ * Many independent reconstructions (members), each with its own geometry,
+ * sizes, TOF setting, data, beta and number of subsets, advanced together by
+ * preconditioned SVRG (Algorithm 1 with the clipped step of eq. (sgm)).
+ * A round is one epoch of every member: step j of the round performs
+ * iteration j of each member with j < n_subsets, as the same five launches
+ * for the whole batch; the subset gradients of a step are one persistent
+ * launch that takes (member, transaxial line) work items from a counter.  A
+ * member's results equal those of pet_svrg_epoch on the same schedule up to
+ * the summation order of the floating-point atomics. */
+typedef struct pet_batch_s *pet_batch;
+
+/* members: geometries (distinct handles, one device), SVRG states (as for
+ * pet_svrg_epoch; their buffers and the images x[r] must stay alive, and the
+ * geometries' scratch belongs to the batch while it runs) and images (device,
+ * in/out).  Allocates gradient-sheet slots for every subset of every member,
+ * the device schedule and a stream of its own.  At most 64 members. */
+pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *const *states, float *const *x,
+                            int n_members, pet_batch *out);
+pet_status pet_batch_destroy(pet_batch b);
+
+/* n_rounds rounds.  subset_seq / tau / update_pc: HOST arrays holding, member
+ * after member (creation order), n_rounds * n_subsets(member) entries each,
+ * as for that member's consecutive pet_svrg_epoch calls.  Every member's
+ * state->k must be a multiple of its n_subsets (PET_E_STATE) and advances by
+ * n_subsets per round.  use_graph != 0: the launches of a round are captured
+ * in a HIP graph on first use and replayed; the round's schedule is copied to
+ * the device before each replay.  Ordered after prior work on `stream`; later
+ * work on `stream` waits for the rounds. */
+pet_status pet_batch_epochs(pet_batch b, int n_rounds, const int32_t *subset_seq, const float *tau,
+                            const uint8_t *update_pc, int use_graph, void *stream);
+
+/* Launch-shape autotuner: times the batched subset-gradient step (subset 0 of
+ * every member) for workgroup sizes of 16, 12 and 8 waves, one or two
+ * workgroups per compute unit and two work-item orders (longest lines
+ * first / creation order), and keeps the fastest.  Touches only scratch
+ * sheets.  config_out (host int[3], nullable): workgroups, waves, order;
+ * best_ms_out (host, nullable): its time. */
+pet_status pet_batch_autotune(pet_batch b, int *config_out, double *best_ms_out, void *stream);
+
 /* Instrumentation --------------------------------------------------------
  * Work of the line kernels on `subset` (-1: all), exactly as they traverse it:
  * out[0] = Joseph samples, out[1] = sample-TOF-bin pairs with nonzero weight

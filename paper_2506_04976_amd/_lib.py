@@ -27,6 +27,7 @@ _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "P
 EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
            "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
+           "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_autotune",
            "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
 PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
 PET_KERNEL_HVP = 6
@@ -94,6 +95,12 @@ def lib():
         L.pet_svrg_epoch_vjp.argtypes = [P, ctypes.POINTER(SvrgState), ctypes.POINTER(SvrgVjpBufs),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(F),
                                          ctypes.POINTER(ctypes.c_uint8), P]
+        L.pet_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(ctypes.POINTER(SvrgState)),
+                                       ctypes.POINTER(P), I, ctypes.POINTER(P)]
+        L.pet_batch_destroy.argtypes = [P]
+        L.pet_batch_epochs.argtypes = [P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(F),
+                                       ctypes.POINTER(ctypes.c_uint8), I, P]
+        L.pet_batch_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D), P]
         L.pet_work_counts.argtypes = [P, I, P, P]
         L.pet_profile_enable.argtypes = [P, I]
         L.pet_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
@@ -403,3 +410,60 @@ class VjpBuffers:
         self.c.x_start = _ptr(x_start, torch.float32, self.nv, "x_start").value
         self.c.x_snap_src = _ptr(x_snap_src, torch.float32, self.nv, "x_snap_src").value if x_snap_src is not None else None
         self.c.D_start = _ptr(D_start, torch.float32, self.nv, "D_start").value if D_start is not None else None
+
+
+class Batch:
+    """A batch of independent reconstructions (pet_batch_*).  members: list of
+    (Geometry, SvrgStateBuffers, x) with distinct geometries; the batch keeps
+    references to them."""
+
+    def __init__(self, members):
+        if not members:
+            raise ValueError("a batch needs at least one member")
+        self.members = list(members)
+        n = len(self.members)
+        geoms = (ctypes.c_void_p * n)(*[m[0].handle.value for m in self.members])
+        states = (ctypes.POINTER(SvrgState) * n)(*[ctypes.pointer(m[1].c) for m in self.members])
+        xs = (ctypes.c_void_p * n)(*[_ptr(m[2], torch.float32, m[0].n_vox, "x").value for m in self.members])
+        h = ctypes.c_void_p()
+        _check(lib().pet_batch_create(geoms, states, xs, n, ctypes.byref(h)))
+        self.handle = h
+
+    def epochs(self, subset_seqs, taus, update_pcs, use_graph=True, stream=None):
+        """One or more rounds: subset_seqs[r] (and taus[r], update_pcs[r]) hold
+        n_rounds * n_subsets entries of member r."""
+        n_rounds = None
+        seq, tau, upd = [], [], []
+        for (g, _, _), s, t, u in zip(self.members, subset_seqs, taus, update_pcs):
+            s, t, u = list(s), list(t), list(u)
+            if not (len(s) == len(t) == len(u)) or len(s) % g.n_subsets:
+                raise ValueError("each member needs n_rounds * n_subsets schedule entries")
+            nr = len(s) // g.n_subsets
+            if n_rounds is None:
+                n_rounds = nr
+            elif nr != n_rounds:
+                raise ValueError("every member needs the same number of rounds")
+            seq += [int(v) for v in s]
+            tau += [float(v) for v in t]
+            upd += [1 if v else 0 for v in u]
+        m = len(seq)
+        _check(lib().pet_batch_epochs(self.handle, n_rounds, (ctypes.c_int32 * m)(*seq), (ctypes.c_float * m)(*tau),
+                                      (ctypes.c_uint8 * m)(*upd), 1 if use_graph else 0, _stream(stream)))
+
+    def autotune(self, stream=None):
+        """(workgroups, waves per workgroup, order) of the fastest launch shape, and its step time in ms."""
+        cfg = (ctypes.c_int * 3)()
+        ms = ctypes.c_double()
+        _check(lib().pet_batch_autotune(self.handle, cfg, ctypes.byref(ms), _stream(stream)))
+        return (cfg[0], cfg[1], cfg[2]), ms.value
+
+    def close(self):
+        if self.handle:
+            lib().pet_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

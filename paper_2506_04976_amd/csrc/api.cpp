@@ -114,6 +114,9 @@ hipError_t hvp_impl(pet_geom g, int subset, const float *x, const float *v, cons
 }
 
 }  // namespace
+
+ProjArgs geom_proj_args(pet_geom_s *g) { return base_args(g, -1); }
+
 }  // namespace pet
 
 using namespace pet;

@@ -88,6 +88,35 @@ struct ProjArgs {
     TofTable tof;
 };
 
+// ---- batches of reconstructions -------------------------------------------
+constexpr int BATCH_MAX = 64;
+enum BStepFlags { B_ACTIVE = 1, B_SNAP = 2, B_UPDATE = 4 };
+
+// What one member does at one step of a round (device schedule).
+struct BStep {
+    int subset;
+    float tau;
+    int flags;
+    int pad;
+};
+
+// One member of a batch as the batched kernels see it.
+struct BMember {
+    ProjArgs pa;               // geometry tables, image sheets, data; G0/G1 = slot 0
+    const int *views;          // [n_sub + 1][views_stride] view lists (last row: all views)
+    const int *sub_nviews;     // views per subset
+    int views_stride, n_sub, n_views, is_tof, tof_waves, nx, ny, nz;
+    int64_t n_vox, g_slot;     // voxels; floats per gradient-sheet slot (G1 = G0 + t0 within a slot)
+    int64_t t0_elems;
+    // SVRG state (Algorithm 1)
+    float *x, *xtmp, *g, *ghat_i, *D;
+    double *ghat;
+    const float *sens, *kappa;
+    float w[27];
+    float beta, gamma, eps, alpha, delta, n_subf;
+    const BStep *steps;        // [max_steps] of the current round
+};
+
 }  // namespace pet
 
 struct pet_geom_s {
@@ -129,6 +158,13 @@ pet_status hip_check(hipError_t e, const char *what);
 
 // projector launches (proj.hip)
 hipError_t launch_line_kernel(pet_geom_s *g, int mode, int subset, const ProjArgs &a, hipStream_t s);
+// persistent batched subset-gradient line kernel over the work items of one step
+hipError_t launch_line_batched(const BMember *mem, const int *order, int n_mem, int step, int *counter, int blocks,
+                               int waves, size_t lds, hipStream_t s);
+// raise the batched kernel's dynamic-LDS limit (outside any stream capture)
+hipError_t prime_line_batched(size_t lds);
+// line-kernel argument block of a geometry (all views)
+ProjArgs geom_proj_args(pet_geom_s *g);
 int n_line_blocks(const pet_geom_s *g, int subset);
 
 // image kernels (image.hip)
@@ -152,6 +188,11 @@ hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *gha
 int rdp_blocks(const pet_geom_s *g);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_fill(float *dst, int64_t n, float val, hipStream_t s);
+// batched image-space kernels (batch.hip): one launch each for all active members of a step
+hipError_t launch_b_prep(const BMember *mem, int n_mem, int step, int *counter, hipStream_t s);
+hipError_t launch_b_gather(const BMember *mem, int n_mem, int step, hipStream_t s);
+hipError_t launch_b_step(const BMember *mem, int n_mem, int step, hipStream_t s);
+hipError_t launch_b_commit(const BMember *mem, int n_mem, int step, hipStream_t s);
 // reverse-mode kernels (adjoint.hip)
 int adj_blocks(const pet_geom_s *g);
 hipError_t launch_rdp_hvp(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,

@@ -117,9 +117,10 @@ __device__ __forceinline__ void build_sheets(const ProjArgs &a, const LineP &L, 
 }
 
 // Block epilogue: spread the gradient sheet over the two transaxial neighbours.
-__device__ __forceinline__ void scatter_sheet(const ProjArgs &a, const LineP &L, int nrow, const double *Z) {
+__device__ __forceinline__ void scatter_sheet(const ProjArgs &a, const LineP &L, int nrow, const double *Z,
+                                              int64_t g_off = 0) {
     const int rz = a.rz;
-    float *Gout = L.axis ? a.G1 : a.G0;
+    float *Gout = (L.axis ? a.G1 : a.G0) + g_off;
     const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
     for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
         float val = (float)Z[e];
@@ -164,15 +165,12 @@ __device__ __forceinline__ void block_sums(double v0, double v1, double *partial
 
 // ---------------------------------------------------------------------------
 // Non-TOF: threads over planes (dense), one line per workgroup.
+// One transaxial line (all its planes) of a non-TOF geometry, by the whole
+// workgroup; returns this thread's FP64 partial (KL or sample count).
 template <int MODE>
-__global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
-    extern __shared__ float4 smem4[];
-    float *smem = reinterpret_cast<float *>(smem4);
+__device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, float *smem, int64_t g_off = 0) {
     constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
     constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM || MODE == M_HVP;
-    const int jv = blockIdx.x / a.n_rad;
-    const int k = blockIdx.x - jv * a.n_rad;
-    const int line = a.views[jv] * a.n_rad + k;
     const LineP L = a.lines[line];
     const int nrow = L.i_hi - L.i_lo + 1;
     const int rz = a.rz;
@@ -242,8 +240,17 @@ __global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
     }
     if (NEED_Z && nrow > 0) {
         __syncthreads();
-        scatter_sheet(a, L, nrow, Z);
+        scatter_sheet(a, L, nrow, Z, g_off);
     }
+    return kl;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
+    extern __shared__ float4 smem4[];
+    const int jv = blockIdx.x / a.n_rad;
+    const int k = blockIdx.x - jv * a.n_rad;
+    const double kl = line_nt_body<MODE>(a, a.views[jv] * a.n_rad + k, reinterpret_cast<float *>(smem4));
     if (MODE != M_FWD && MODE != M_BACK && a.partial) block_sums(kl, kl, a.partial, MODE == M_COUNT);
 }
 
@@ -412,18 +419,16 @@ __device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, dou
         default: FN<8>(__VA_ARGS__); break; \
     }
 
+// One transaxial line of a TOF geometry by the whole workgroup, segments
+// spread over the first nwaves waves (the others only help with the sheets);
+// returns this thread's FP64 partials (KL or samples, and sample-bin pairs).
 template <int MODE>
-__global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
-    extern __shared__ float4 smem4[];
-    float *smem = reinterpret_cast<float *>(smem4);
+__device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float *smem, int nwaves, double &kl,
+                                              double &pairs, int64_t g_off = 0) {
     constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
     constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM || MODE == M_HVP;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
-    const int jv = blockIdx.x / a.n_rad;
-    const int k = blockIdx.x - jv * a.n_rad;
-    const int line = a.views[jv] * a.n_rad + k;
     const LineP L = a.lines[line];
     const int nrow = L.i_hi - L.i_lo + 1;
     const int rz = a.rz;
@@ -445,8 +450,9 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
     const int na_l = lane < a.tof.n_int ? a.tof.na[lane] : 0;
     const int bf_l = lane < a.tof.n_int ? a.tof.bf[lane] : 0;
 
-    double kl = 0.0, pairs = 0.0;
-    for (int sg = wave; sg < a.n_seg; sg += nwaves) {
+    kl = 0.0;
+    pairs = 0.0;
+    for (int sg = wave; wave < nwaves && sg < a.n_seg; sg += nwaves) {
         const SegP S = a.segs[sg];
         const bool has = lane < S.np;
         const int p = S.p0 + (has ? lane : 0);
@@ -576,9 +582,70 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
     }
     if (NEED_Z && nrow > 0) {
         __syncthreads();
-        scatter_sheet(a, L, nrow, Z);
+        scatter_sheet(a, L, nrow, Z, g_off);
     }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
+    extern __shared__ float4 smem4[];
+    const int jv = blockIdx.x / a.n_rad;
+    const int k = blockIdx.x - jv * a.n_rad;
+    double kl, pairs;
+    line_tof_body<MODE>(a, a.views[jv] * a.n_rad + k, reinterpret_cast<float *>(smem4), blockDim.x >> 6, kl, pairs);
     if (MODE != M_FWD && MODE != M_BACK && a.partial) block_sums(kl, pairs, a.partial, MODE == M_COUNT);
+}
+
+// Persistent subset-gradient kernel over a batch: the work items of one step
+// are the transaxial lines of every active member (all lines at a snapshot,
+// each into the gradient-sheet slot of its view's subset; else the lines of
+// the step's subset into slot 0), concatenated in `order`.  Workgroups take
+// items from a global counter (zeroed by the step's prep kernel) until none
+// is left.
+__global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_batched(const BMember *__restrict__ mem,
+                                                                     const int *__restrict__ order, int n_mem,
+                                                                     int step, int *__restrict__ counter) {
+    extern __shared__ float4 smem4[];
+    float *smem = reinterpret_cast<float *>(smem4);
+    __shared__ int s_cum[BATCH_MAX + 1];
+    __shared__ int s_item;
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int q = 0; q < n_mem; ++q) {
+            s_cum[q] = c;
+            const BMember &m = mem[order[q]];
+            const BStep st = m.steps[step];
+            if (st.flags & B_ACTIVE) c += ((st.flags & B_SNAP) ? m.n_views : m.sub_nviews[st.subset]) * m.pa.n_rad;
+        }
+        s_cum[n_mem] = c;
+    }
+    __syncthreads();
+    const int total = s_cum[n_mem];
+    const int nw = blockDim.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= total) break;
+        int q = 0;
+        while (s_cum[q + 1] <= item) ++q;
+        const BMember &m = mem[order[q]];
+        const BStep st = m.steps[step];
+        const int local = item - s_cum[q];
+        const int n_rad = m.pa.n_rad;
+        const int jv = local / n_rad;
+        const int k = local - jv * n_rad;
+        const bool snap = (st.flags & B_SNAP) != 0;
+        const int view = snap ? jv : m.views[st.subset * m.views_stride + jv];
+        const int64_t g_off = snap ? (int64_t)(jv % m.n_sub) * m.g_slot : 0;
+        if (m.is_tof) {
+            double kl, pairs;
+            line_tof_body<M_GRAD>(m.pa, view * n_rad + k, smem, min(m.tof_waves, nw), kl, pairs, g_off);
+        } else {
+            line_nt_body<M_GRAD>(m.pa, view * n_rad + k, smem, g_off);
+        }
+        __syncthreads();
+    }
 }
 
 template <int MODE>
@@ -599,9 +666,10 @@ void set_lds_attr(size_t need) {
     if (need <= granted) return;
     const void *fns[] = {(const void *)k_line_nt<M_FWD>,   (const void *)k_line_nt<M_BACK>,
                          (const void *)k_line_nt<M_GRAD>,  (const void *)k_line_nt<M_EM>,
-                         (const void *)k_line_nt<M_OBJ>,   (const void *)k_line_tof<M_FWD>,
-                         (const void *)k_line_tof<M_BACK>, (const void *)k_line_tof<M_GRAD>,
-                         (const void *)k_line_tof<M_EM>,   (const void *)k_line_tof<M_OBJ>};
+                         (const void *)k_line_nt<M_OBJ>,   (const void *)k_line_nt<M_HVP>,
+                         (const void *)k_line_tof<M_FWD>,  (const void *)k_line_tof<M_BACK>,
+                         (const void *)k_line_tof<M_GRAD>, (const void *)k_line_tof<M_EM>,
+                         (const void *)k_line_tof<M_OBJ>,  (const void *)k_line_tof<M_HVP>};
     hipError_t e = hipSuccess;
     for (const void *f : fns)
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
@@ -624,6 +692,20 @@ hipError_t launch_line_kernel_impl(const pet_geom_s *g, int mode, dim3 grid, con
 }
 
 }  // namespace
+
+hipError_t prime_line_batched(size_t lds) {
+    static size_t granted = 64 * 1024;
+    if (lds <= granted) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)k_line_batched, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) granted = lds;
+    return e;
+}
+
+hipError_t launch_line_batched(const BMember *mem, const int *order, int n_mem, int step, int *counter, int blocks,
+                               int waves, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(k_line_batched, dim3(blocks), dim3(64 * waves), lds, s, mem, order, n_mem, step, counter);
+    return hipGetLastError();
+}
 
 int n_line_blocks(const pet_geom_s *g, int subset) {
     int nv = subset < 0 ? g->d.n_views : (int)g->subset_views[subset].size();

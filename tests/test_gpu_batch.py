@@ -1,0 +1,142 @@
+"""GPU: batches of reconstructions.  Members of different geometries, sizes,
+TOF settings, count levels, beta and subset counts advanced by pet_batch_epochs
+(persistent subset-gradient launch, with and without HIP-graph replay) match
+the same members advanced one by one with pet_svrg_epoch on the same schedule
+(relative L2 <= 1e-5 per member; the two differ only in the summation order
+of floating-point atomics), and one member matches the FP64 oracle's
+Algorithm 1 (relative L2 <= 1e-4)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import recon
+from synth import configs, data
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [("mini_tof", 1.0), ("mini_nontof", 3.0), ("mini_2d", 0.5), ("c0_2d", 1.0)]
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+class Member:
+    def __init__(self, name, beta_factor):
+        import paper_2506_04976_amd as pm
+        self.pm = pm
+        self.cfg = configs.get(name)
+        self.d = data.make_dataset(self.cfg)
+        dev = torch.device("cuda:0")
+        self.dev = dev
+        self.y = torch.from_numpy(self.d["y"].ravel()).to(dev)
+        self.r = torch.from_numpy(self.d["r"].ravel()).to(dev)
+        self.a = torch.from_numpy(self.d["mult"].ravel()).to(dev)
+        self.beta = configs.beta_value(self.cfg) * beta_factor
+        g = pm.Geometry(self.cfg)
+        self.sens = torch.empty(g.n_vox, device=dev)
+        pm.pet_back(g, -1, None, self.a, self.sens)
+        x = torch.ones(g.n_vox, device=dev)
+        xmax = torch.zeros(1, device=dev)
+        pm.pet_osem_epoch(g, x, self.y, self.r, self.a, list(range(self.cfg["n_subsets"])), xmax)
+        self.x0 = x
+        self.eps = 1e-3 * float(xmax.cpu())
+        g.close()
+
+    def runner(self):
+        g = self.pm.Geometry(self.cfg)
+        st = self.pm.SvrgStateBuffers(g, self.y, self.r, self.a, self.sens, beta=self.beta, gamma=2.0, eps=self.eps,
+                                      alpha=1.0, delta=self.eps)
+        return g, st, self.x0.clone()
+
+    def schedule(self, n_epochs):
+        n = self.cfg["n_subsets"]
+        orders = data.subset_orders(self.cfg, n_epochs)
+        taus = [[1.0 / (1.0 + 0.02 * (e * n + j) / n) for j in range(n)] for e in range(n_epochs)]
+        upd = [[(e * n + j) in (0, n, 2 * n) for j in range(n)] for e in range(n_epochs)]
+        return orders, taus, upd
+
+
+@pytest.fixture(scope="module")
+def members():
+    _say("\n[batch] building members")
+    return [Member(n, f) for n, f in MEMBERS]
+
+
+def _rel(a, b):
+    return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_matches_individual_runs(members, use_graph):
+    pm = members[0].pm
+    E = 3
+    singles, batched = [], []
+    for m in members:
+        g, st, x = m.runner()
+        orders, taus, upd = m.schedule(E)
+        for e in range(E):
+            pm.pet_svrg_epoch(g, st, x, orders[e], taus[e], upd[e])
+        singles.append((g, st, x))
+        batched.append(m.runner())
+    b = pm.Batch(batched)
+    scheds = [m.schedule(E) for m in members]
+    # one round, then two more (schedule refresh between graph replays)
+    for lo, hi in ((0, 1), (1, E)):
+        b.epochs([[int(v) for e in range(lo, hi) for v in s[0][e]] for s in scheds],
+                 [[v for e in range(lo, hi) for v in s[1][e]] for s in scheds],
+                 [[v for e in range(lo, hi) for v in s[2][e]] for s in scheds], use_graph=use_graph)
+    torch.cuda.synchronize()
+    for m, (g1, st1, x1), (g2, st2, x2) in zip(members, singles, batched):
+        err = _rel(x2, x1)
+        _say(f"[batch graph={use_graph}] {m.cfg['name']}: batched vs single relative L2 {err:.2e}")
+        assert err <= 1e-5
+        assert st2.k == st1.k == E * m.cfg["n_subsets"]
+    b.close()
+
+
+def test_batch_member_matches_oracle(members):
+    pm = members[0].pm
+    E = 3
+    runs = [m.runner() for m in members]
+    b = pm.Batch(runs)
+    scheds = [m.schedule(E) for m in members]
+    b.epochs([[int(v) for e in range(E) for v in s[0][e]] for s in scheds],
+             [[v for e in range(E) for v in s[1][e]] for s in scheds],
+             [[v for e in range(E) for v in s[2][e]] for s in scheds])
+    m = members[0]
+    n = m.cfg["n_subsets"]
+    x_gpu = runs[0][2].cpu().double().numpy()
+    prob = recon.Problem(m.cfg, m.d["y"], m.d["r"], m.d["mult"], beta=m.beta, gamma=2.0, eps=m.eps, alpha=1.0,
+                         delta=m.eps)
+    orders, taus, _ = scheds[0]
+    x0 = m.x0.cpu().double().numpy().reshape(prob.shape)
+    x_orc = recon.svrg(prob, x0, E, recon.order_rule(orders), lambda k: taus[k // n][k % n],
+                       recon.pc_update_iters(n)).ravel()
+    err = np.linalg.norm(x_gpu - x_orc) / np.linalg.norm(x_orc)
+    _say(f"[batch] {m.cfg['name']} after {E} rounds vs oracle: relative L2 {err:.2e}")
+    assert err <= 1e-4
+    b.close()
+
+
+def test_batch_autotune_keeps_results(members):
+    pm = members[0].pm
+    E = 2
+    ref = [m.runner() for m in members]
+    for m, (g, st, x) in zip(members, ref):
+        orders, taus, upd = m.schedule(E)
+        for e in range(E):
+            pm.pet_svrg_epoch(g, st, x, orders[e], taus[e], upd[e])
+    runs = [m.runner() for m in members]
+    b = pm.Batch(runs)
+    (blocks, waves, order), ms = b.autotune()
+    _say(f"[batch] autotune: {blocks} workgroups x {waves} waves, order {order}, step {ms:.3f} ms")
+    assert blocks > 0 and waves in (8, 12, 16) and order in (0, 1) and ms > 0
+    scheds = [m.schedule(E) for m in members]
+    b.epochs([[int(v) for e in range(E) for v in s[0][e]] for s in scheds],
+             [[v for e in range(E) for v in s[1][e]] for s in scheds],
+             [[v for e in range(E) for v in s[2][e]] for s in scheds])
+    for m, (_, _, x1), (_, _, x2) in zip(members, ref, runs):
+        assert _rel(x2, x1) <= 1e-5, m.cfg["name"]
+    b.close()
