@@ -407,6 +407,45 @@ __device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, dou
     }
 }
 
+// Bin window <-> per-bin accumulators. The first bin BF is a template
+// argument so that every register index is static: indexing a register array
+// by a run-time value compiles to indexed register moves, which the compiler
+// may execute speculatively for indices the source guards out and which then
+// write registers past the array.
+template <int BF>
+__device__ __forceinline__ void add_window(float (&acc)[NT_MAX], const float (&win)[WS_MAX], int na) {
+#pragma unroll
+    for (int j = 0; j < WS_MAX; ++j)
+        if (BF + j < NT_MAX && j < na) acc[BF + j] += win[j];
+}
+
+template <int BF>
+__device__ __forceinline__ void get_window(const float (&acc)[NT_MAX], float (&win)[WS_MAX], int na) {
+#pragma unroll
+    for (int j = 0; j < WS_MAX; ++j) win[j] = (BF + j < NT_MAX && j < na) ? acc[BF + j] : 0.f;
+}
+
+static_assert(NT_MAX == 16, "the first-bin switch below covers bins 0 .. 15");
+#define PET_BF_SWITCH(FN, ...)                \
+    switch (bf) {                             \
+        case 0: FN<0>(__VA_ARGS__); break;    \
+        case 1: FN<1>(__VA_ARGS__); break;    \
+        case 2: FN<2>(__VA_ARGS__); break;    \
+        case 3: FN<3>(__VA_ARGS__); break;    \
+        case 4: FN<4>(__VA_ARGS__); break;    \
+        case 5: FN<5>(__VA_ARGS__); break;    \
+        case 6: FN<6>(__VA_ARGS__); break;    \
+        case 7: FN<7>(__VA_ARGS__); break;    \
+        case 8: FN<8>(__VA_ARGS__); break;    \
+        case 9: FN<9>(__VA_ARGS__); break;    \
+        case 10: FN<10>(__VA_ARGS__); break;  \
+        case 11: FN<11>(__VA_ARGS__); break;  \
+        case 12: FN<12>(__VA_ARGS__); break;  \
+        case 13: FN<13>(__VA_ARGS__); break;  \
+        case 14: FN<14>(__VA_ARGS__); break;  \
+        default: FN<15>(__VA_ARGS__); break;  \
+    }
+
 #define PET_NA_SWITCH(FN, ...)              \
     switch (na) {                           \
         case 1: FN<1>(__VA_ARGS__); break;  \
@@ -428,7 +467,10 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
     constexpr bool NEED_Z = MODE == M_BACK || MODE == M_GRAD || MODE == M_EM || MODE == M_HVP;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave index and wave count are wave-uniform: the segment loop below runs
+    // under scalar control flow
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    nwaves = __builtin_amdgcn_readfirstlane(nwaves);
     const LineP L = a.lines[line];
     const int nrow = L.i_hi - L.i_lo + 1;
     const int rz = a.rz;
@@ -516,9 +558,7 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                     const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
                     PET_NA_SWITCH(tof_fwd_run, zAf, zBf, zmax, X + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
                                   w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, win)
-#pragma unroll
-                    for (int j = 0; j < WS_MAX; ++j)
-                        if (j < na) acc[bf + j] += win[j];
+                    PET_BF_SWITCH(add_window, acc, win, na)
                 }
             }
 
@@ -568,8 +608,7 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                     const int c1 = __builtin_amdgcn_readlane(cut_next, s);
                     const int bf = __builtin_amdgcn_readlane(bf_l, s);
                     float win[WS_MAX];
-#pragma unroll
-                    for (int j = 0; j < WS_MAX; ++j) win[j] = (j < na) ? acc[min(bf + j, NT_MAX - 1)] : 0.f;
+                    PET_BF_SWITCH(get_window, acc, win, na)
                     const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
                     PET_NA_SWITCH(tof_back_run, zA, zB, zmax, Z + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
                                   w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, c0 - qlo_b, span, win)
