@@ -247,6 +247,99 @@ def differentiable_leg(pm):
             "plain_epochs_per_s": E / tp, "forward_reverse_epochs_per_s": E / td, "reverse_cost_ratio": td / tp}
 
 
+def batched_leg(args):
+    """Batched workload: 24 independent reconstructions of uneven sizes, TOF
+    settings, counts, beta and subset counts.  Member-epochs/s of the plain
+    path (each member's epochs with pet_svrg_epoch, one member after another)
+    against the batched path (pet_batch_epochs: one persistent subset-gradient
+    launch per step for all members, HIP-graph-captured rounds, autotuned
+    launch shape), same members, same schedules, inputs resident in HBM."""
+    import numpy as np
+    import torch
+
+    import paper_2506_04976_amd as pm
+    from synth import configs, data
+
+    cfg = configs.get("c4_batch")
+    members = data.batch_members(cfg)
+    E = args.batch_rounds
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    M = []
+    for m in members:
+        d = data.make_dataset(m)
+        y = torch.from_numpy(d["y"].reshape(-1)).to(dev)
+        r = torch.from_numpy(d["r"].reshape(-1)).to(dev)
+        a = torch.from_numpy(d["mult"].reshape(-1)).to(dev)
+        del d
+        g = pm.Geometry(m)
+        sens = torch.empty(g.n_vox, device=dev)
+        pm.pet_back(g, -1, None, a, sens)
+        x0 = torch.ones(g.n_vox, device=dev)
+        xmax = torch.zeros(1, device=dev)
+        n = m["n_subsets"]
+        pm.pet_osem_epoch(g, x0, y, r, a, list(range(n)), xmax)
+        eps = 1e-3 * float(xmax.cpu())
+        orders = data.subset_orders(m, E + 1)
+        taus = [[1.0 / (1.0 + 0.02 * (e * n + j) / n) for j in range(n)] for e in range(E + 1)]
+        upd = [[(e * n + j) in (0, n, 2 * n) for j in range(n)] for e in range(E + 1)]
+        M.append(dict(cfg=m, y=y, r=r, a=a, g=g, sens=sens, x0=x0, eps=eps, orders=orders, taus=taus, upd=upd))
+        log(f"[bench] member {m['name']}: {g.n_bins} bins, y {y.dtype}, {n} subsets ({time.time() - t0:.0f} s)")
+
+    def state(mm):
+        return pm.SvrgStateBuffers(mm["g"], mm["y"], mm["r"], mm["a"], mm["sens"], beta=mm["cfg"]["beta"],
+                                   gamma=mm["cfg"]["gamma"], eps=mm["eps"], alpha=1.0, delta=mm["eps"])
+
+    # plain path: epoch 0 untimed, epochs 1..E timed
+    finals = []
+    t_plain = 0.0
+    for mm in M:
+        st, x = state(mm), mm["x0"].clone()
+        pm.pet_svrg_epoch(mm["g"], st, x, mm["orders"][0], mm["taus"][0], mm["upd"][0])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for e in range(1, E + 1):
+            pm.pet_svrg_epoch(mm["g"], st, x, mm["orders"][e], mm["taus"][e], mm["upd"][e])
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t1
+        finals.append(x)
+        del st
+    # batched path
+    runs = [(mm["g"], state(mm), mm["x0"].clone()) for mm in M]
+    b = pm.Batch(runs)
+    (blocks, waves, order), step_ms = b.autotune()
+    log(f"[bench] autotuned: {blocks} workgroups x {waves} waves, order {order} ({step_ms:.2f} ms per test step)")
+
+    def rounds(lo, hi):
+        b.epochs([[int(v) for e in range(lo, hi) for v in mm["orders"][e]] for mm in M],
+                 [[v for e in range(lo, hi) for v in mm["taus"][e]] for mm in M],
+                 [[v for e in range(lo, hi) for v in mm["upd"][e]] for mm in M], use_graph=True)
+
+    rounds(0, 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rounds(1, E + 1)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t1
+    diff = max(float(torch.linalg.norm(x2 - x1) / torch.linalg.norm(x1)) for (_, _, x2), x1 in zip(runs, finals))
+    b.close()
+    n_ep = len(M) * E
+    return {
+        "metric": "batched SVRG reconstructions: member-epochs/s",
+        "value": n_ep / t_batch, "unit": "member-epochs/s", "n_gpus": 1, "steps": E, "warmup": 1,
+        "ms_per_step": 1e3 * t_batch / E, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4_batch: 24 reconstructions, 4 per (size in {96x96x32, 128x128x48, 128x128x71}, "
+                               "TOF 13 bins / non-TOF) cell, counts 1e6-1e8, beta 0.1-10x, 8-25 subsets",
+                   "members": [{"name": mm["cfg"]["name"], "bins": mm["g"].n_bins, "subsets": mm["cfg"]["n_subsets"],
+                                "counts": mm["cfg"]["counts"], "beta": mm["cfg"]["beta"]} for mm in M],
+                   "parallelism": "single GPU"},
+        "plain_value": n_ep / t_plain, "speedup_vs_plain": t_plain / t_batch,
+        "autotuned": {"workgroups": blocks, "waves": waves, "order": ["longest lines first", "creation"][order]},
+        "max_member_rel_diff_vs_plain": diff,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +352,9 @@ def main():
                     help="L-BFGS-B iterations (at most) of the converged reference image for the NRMSE")
     ap.add_argument("--nrmse-max-epochs", type=int, default=200)
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable (unrolled) leg")
+    ap.add_argument("--batched", action="store_true",
+                    help="measure only the batched workload (24 reconstructions; prints its own JSON line)")
+    ap.add_argument("--batch-rounds", type=int, default=3)
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (a known-size reference kernel "
                          "for calibrating hardware byte counters)")
@@ -268,6 +364,10 @@ def main():
               "(the reconstruction would shard views across GPUs with one image all-reduce per iteration; "
               "that path is not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.batched:
+        print(json.dumps(batched_leg(args)), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -308,6 +308,11 @@ pet_status pet_batch_epochs(pet_batch b, int n_rounds, const int32_t *subset_seq
  * best_ms_out (host, nullable): its time. */
 pet_status pet_batch_autotune(pet_batch b, int *config_out, double *best_ms_out, void *stream);
 
+/* Sets the launch shape of the batched subset-gradient step by hand
+ * (workgroups, waves per workgroup 1..16, order 0 = longest lines first,
+ * 1 = creation order); PET_E_ARG if the sheets do not fit. */
+pet_status pet_batch_set_launch(pet_batch b, int workgroups, int waves, int order);
+
 /* Instrumentation --------------------------------------------------------
  * Work of the line kernels on `subset` (-1: all), exactly as they traverse it:
  * out[0] = Joseph samples, out[1] = sample-TOF-bin pairs with nonzero weight

@@ -27,7 +27,7 @@ _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "P
 EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
            "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
-           "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_autotune",
+           "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_autotune", "pet_batch_set_launch",
            "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
 PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
 PET_KERNEL_HVP = 6
@@ -101,6 +101,7 @@ def lib():
         L.pet_batch_epochs.argtypes = [P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(F),
                                        ctypes.POINTER(ctypes.c_uint8), I, P]
         L.pet_batch_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D), P]
+        L.pet_batch_set_launch.argtypes = [P, I, I, I]
         L.pet_work_counts.argtypes = [P, I, P, P]
         L.pet_profile_enable.argtypes = [P, I]
         L.pet_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
@@ -456,6 +457,9 @@ class Batch:
         ms = ctypes.c_double()
         _check(lib().pet_batch_autotune(self.handle, cfg, ctypes.byref(ms), _stream(stream)))
         return (cfg[0], cfg[1], cfg[2]), ms.value
+
+    def set_launch(self, workgroups, waves, order=0):
+        _check(lib().pet_batch_set_launch(self.handle, workgroups, waves, order))
 
     def close(self):
         if self.handle:

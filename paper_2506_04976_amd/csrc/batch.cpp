@@ -377,3 +377,21 @@ extern "C" pet_status pet_batch_autotune(pet_batch b, int *config_out, double *b
     if (e == hipSuccess) e = hipStreamWaitEvent(cs, b->ev_out, 0);
     return hip_check(e, "pet_batch_autotune");
 }
+
+extern "C" pet_status pet_batch_set_launch(pet_batch b, int workgroups, int waves, int order) {
+    if (!b) return fail(PET_E_ARG, "pet_batch_set_launch: null batch");
+    if (workgroups < 1 || waves < 1 || waves > TOF_MAX_WAVES || (order != 0 && order != 1))
+        return fail(PET_E_ARG, "pet_batch_set_launch: workgroups >= 1, 1 <= waves <= 16, order 0 or 1");
+    int max_lds = 0;
+    hipError_t e = hipSetDevice(b->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device);
+    if (e == hipSuccess && batch_lds(b, waves) > (size_t)max_lds)
+        return fail(PET_E_ARG, "pet_batch_set_launch: too many waves for the LDS");
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_check(e, "pet_batch_set_launch");
+    b->blocks = workgroups;
+    b->waves = waves;
+    b->order_kind = order;
+    drop_graph(b);
+    return hip_check(upload_order(b), "pet_batch_set_launch");
+}

@@ -62,6 +62,15 @@ CONFIGS = {
         n_subsets=8, phantom="head", counts=5e6, bg_fraction_of_prompts=0.2,
         beta_tilde=4.0, gamma=2.0, seed=0, epochs=10,
     ),
+    # Batched workload: 24 independent reconstructions, 4 per (size, TOF) cell
+    # with sizes {96x96x32 (c3_diff geometry), 128x128x48 (43 rings, ring
+    # difference <= 14, 1037 planes), 128x128x71 (c1_3d geometry)}, TOF as
+    # c2_tof; counts log-uniform in [1e6, 1e8], beta log-uniform within
+    # [0.1, 10] x the count-scaled rule, 8..25 subsets (synth.data.batch_members).
+    "c4_batch": dict(
+        name="c4_batch", kind="batch", per_cell=4, counts_range=(1e6, 1e8), beta_factor_range=(0.1, 10.0),
+        subsets_range=(8, 25), beta_tilde=4.0, gamma=2.0, seed=0, epochs=3,
+    ),
     # Test geometries: ragged sizes, several segments, TOF on/off.
     "mini_tof": dict(
         name="mini_tof", kind="cylinder",
@@ -90,6 +99,22 @@ CONFIGS = {
         beta=0.01, gamma=2.0, seed=3, epochs=4,
     ),
 }
+
+
+MID_PITCH = 48 * 2.03 / 43  # 43 rings spanning the 48-slice image
+
+
+def batch_size_config(size, tof):
+    """Geometry of one batch member: size 0 = c3_diff, 1 = 128x128x48 with 43
+    rings (ring difference <= 14), 2 = c1_3d; tof adds c2_tof's 13 bins."""
+    base = get("c3_diff") if size == 0 else get("c1_3d")
+    if size == 1:
+        base.update(nz=48, n_rings=43, ring_pitch=MID_PITCH, max_ring_diff=14)
+    if tof:
+        t = CONFIGS["c2_tof"]
+        base.update(n_tof=t["n_tof"], tof_bin=t["tof_bin"], tof_sigma=t["tof_sigma"], tof_nsigma=t["tof_nsigma"])
+    base["name"] = f"c4_{('s', 'm', 'l')[size]}{'_tof' if tof else ''}"
+    return base
 
 
 def get(name, **overrides):

@@ -221,3 +221,29 @@ def nrmse_region(cfg, scale):
     w = zz - cz
     mask = (u / ax) ** 2 + (v / ay) ** 2 + (w / az) ** 2 <= 1.0
     return mask, float(inc * scale)
+
+
+def batch_members(cfg):
+    """Member workloads of a batched configuration (kind "batch"): per_cell
+    members for each (size, TOF) cell, with counts log-uniform in
+    counts_range, beta = (count-scaled rule) x a factor log-uniform in
+    beta_factor_range, and a uniform number of subsets in subsets_range, drawn
+    from the configuration's batch seed stream; each member has its own data
+    seed."""
+    rng = np.random.Generator(np.random.PCG64(seeds(cfg)[2]))
+    lo, hi = cfg["counts_range"]
+    blo, bhi = cfg["beta_factor_range"]
+    slo, shi = cfg["subsets_range"]
+    out = []
+    for size in range(3):
+        for tof in (False, True):
+            for j in range(cfg["per_cell"]):
+                m = configs.batch_size_config(size, tof)
+                counts = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+                factor = float(np.exp(rng.uniform(np.log(blo), np.log(bhi))))
+                m.update(counts=counts, n_subsets=int(rng.integers(slo, shi + 1)), seed=1000 + len(out),
+                         beta_tilde=cfg["beta_tilde"], gamma=cfg["gamma"])
+                m["beta"] = configs.beta_value(m) * factor
+                m["name"] = f"{m['name']}_{j}"
+                out.append(m)
+    return out

@@ -120,6 +120,34 @@ def test_batch_member_matches_oracle(members):
     b.close()
 
 
+@pytest.mark.parametrize("shape", [(64, 2, 1), (300, 3, 0)])
+def test_batch_few_waves_matches_individual_runs(members, shape):
+    # fewer waves per workgroup than TOF segments: every wave takes several
+    # segments of a line in turn
+    pm = members[0].pm
+    E = 2
+    ref = [m.runner() for m in members]
+    for m, (g, st, x) in zip(members, ref):
+        orders, taus, upd = m.schedule(E)
+        for e in range(E):
+            pm.pet_svrg_epoch(g, st, x, orders[e], taus[e], upd[e])
+    runs = [m.runner() for m in members]
+    b = pm.Batch(runs)
+    b.set_launch(*shape)
+    scheds = [m.schedule(E) for m in members]
+    b.epochs([[int(v) for e in range(E) for v in s[0][e]] for s in scheds],
+             [[v for e in range(E) for v in s[1][e]] for s in scheds],
+             [[v for e in range(E) for v in s[2][e]] for s in scheds])
+    torch.cuda.synchronize()
+    for m, (_, _, x1), (_, _, x2) in zip(members, ref, runs):
+        err = _rel(x2, x1)
+        _say(f"[batch {shape}] {m.cfg['name']}: batched vs single relative L2 {err:.2e}")
+        assert err <= 1e-5, m.cfg["name"]
+    with pytest.raises(pm.PetError):
+        b.set_launch(64, 17)
+    b.close()
+
+
 def test_batch_autotune_keeps_results(members):
     pm = members[0].pm
     E = 2
