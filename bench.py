@@ -127,11 +127,12 @@ def map_reference(cfg, geom, pm, y, r, a, sens, beta, eps, delta, x0, max_iter):
                    "kkt_residual": kkt, "objective": phi}
 
 
-def time_to_nrmse(args, cfg, geom, pm, epoch, y, r, a, beta, eps, delta, x0_host, mask_np, level):
-    """Wall time to NRMSE < 1% of the converged MAP image x*.
+def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_host, mask_np, level):
+    """Wall time to NRMSE < 1% of the converged MAP image x*, for each
+    estimator in `epochs` (name -> epoch function; the first is the headline).
 
-    A fresh reconstruction is timed from the first device call after the data
-    upload (sensitivity, one OSEM epoch, SVRG epochs); the NRMSE
+    Each reconstruction is fresh and timed from the first device call after the
+    data upload (sensitivity, one OSEM epoch, epochs of the estimator); the NRMSE
     sqrt(mean_M (x - x*)^2) / c over the phantom's outer region M, with c the
     value of that region in the scaled phantom, is evaluated after every epoch
     with the clock stopped."""
@@ -154,34 +155,45 @@ def time_to_nrmse(args, cfg, geom, pm, epoch, y, r, a, beta, eps, delta, x0_host
         dlt = (img.double() - xstar.double()) * mask
         return float(torch.sqrt((dlt * dlt).sum() / nm)) / level
 
-    x1 = torch.empty(geom.n_vox, device=dev)
-    xmax = torch.zeros(1, device=dev)
-    sens = torch.empty(geom.n_vox, device=dev)
-    torch.cuda.synchronize()
-    t_clock = 0.0
-    t0 = time.perf_counter()
-    x1.fill_(1.0)
-    pm.pet_back(geom, -1, None, a, sens)
-    pm.pet_osem_epoch(geom, x1, y, r, a, list(range(n)), xmax)
-    st1 = pm.SvrgStateBuffers(geom, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0, delta=delta)
-    torch.cuda.synchronize()
-    t_clock += time.perf_counter() - t0
-    trace = [nrmse_of(x1)]
-    reached = None
-    for e in range(args.nrmse_max_epochs):
+    out = {}
+    for name, epoch in epochs.items():
+        x1 = torch.empty(geom.n_vox, device=dev)
+        xmax = torch.zeros(1, device=dev)
+        sens = torch.empty(geom.n_vox, device=dev)
+        torch.cuda.synchronize()
+        t_clock = 0.0
+        t_epochs = 0.0
         t0 = time.perf_counter()
-        epoch(e, st=st1, x=x1)
+        x1.fill_(1.0)
+        pm.pet_back(geom, -1, None, a, sens)
+        pm.pet_osem_epoch(geom, x1, y, r, a, list(range(n)), xmax)
+        st1 = pm.SvrgStateBuffers(geom, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0,
+                                  delta=delta)
         torch.cuda.synchronize()
         t_clock += time.perf_counter() - t0
-        trace.append(nrmse_of(x1))
-        if trace[-1] < 0.01:
-            reached = e + 1
-            break
-    log(f"[bench] NRMSE after OSEM and each SVRG epoch: {['%.4f' % v for v in trace]}")
-    return {"seconds": t_clock if reached else None, "epochs": reached, "threshold": 0.01,
-            "includes": "sensitivity backprojection, 1 OSEM epoch, SVRG epochs (NRMSE evaluation excluded)",
-            "nrmse_per_epoch": [round(v, 5) for v in trace], "reference": ref,
-            "region_voxels": int(nm), "level": level}
+        trace = [nrmse_of(x1)]
+        reached = None
+        for e in range(args.nrmse_max_epochs):
+            t0 = time.perf_counter()
+            epoch(e, st=st1, x=x1)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t_clock += dt
+            t_epochs += dt
+            trace.append(nrmse_of(x1))
+            if trace[-1] < 0.01:
+                reached = e + 1
+                break
+        log(f"[bench] {name}: NRMSE after OSEM and each epoch: {['%.4f' % v for v in trace]}")
+        out[name] = {"seconds": t_clock if reached else None, "epochs": reached, "threshold": 0.01,
+                     "epochs_per_s": (len(trace) - 1) / t_epochs,
+                     "includes": f"sensitivity backprojection, 1 OSEM epoch, {name.upper()} epochs "
+                                 "(NRMSE evaluation excluded)",
+                     "nrmse_per_epoch": [round(v, 5) for v in trace]}
+        del st1, x1, sens
+    first = next(iter(out))
+    out[first].update({"reference": ref, "region_voxels": int(nm), "level": level})
+    return out
 
 
 def differentiable_leg(pm):
@@ -351,6 +363,8 @@ def main():
     ap.add_argument("--ref-iters", type=int, default=500,
                     help="L-BFGS-B iterations (at most) of the converged reference image for the NRMSE")
     ap.add_argument("--nrmse-max-epochs", type=int, default=200)
+    ap.add_argument("--no-estimators", action="store_true",
+                    help="time to NRMSE for SVRG only (not SAGA and SGD)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable (unrolled) leg")
     ap.add_argument("--batched", action="store_true",
                     help="measure only the batched workload (24 reconstructions; prints its own JSON line)")
@@ -406,10 +420,14 @@ def main():
     orders = data.subset_orders(cfg, max(total, args.nrmse_max_epochs))
     upd_iters = {0, n, 2 * n}
 
-    def epoch(e, st=st, x=x):
-        ks = [e * n + j for j in range(n)]
-        pm.pet_svrg_epoch(geom, st, x, orders[e], [1.0 / (1.0 + 0.02 * k / n) for k in ks],
-                          [k in upd_iters for k in ks])
+    def make_epoch(fn):
+        # vanishing stepsize tau_k = 1 / (1 + 0.02 k / n) (Section 3) for every estimator
+        def epoch(e, st=st, x=x):
+            ks = [e * n + j for j in range(n)]
+            fn(geom, st, x, orders[e], [1.0 / (1.0 + 0.02 * k / n) for k in ks], [k in upd_iters for k in ks])
+        return epoch
+
+    epoch = make_epoch(pm.pet_svrg_epoch)
 
     if args.copy_ref_mib > 0:
         src = torch.ones(args.copy_ref_mib * 262144, device=dev)
@@ -474,10 +492,16 @@ def main():
     objective = float(obj.cpu())
 
     nrmse = None
+    estimators = None
     if not args.no_nrmse:
         del st
-        nrmse = time_to_nrmse(args, cfg, geom, pm, epoch, y, r, a, beta, eps, delta, x0_host,
-                              nrmse_mask, nrmse_level)
+        algos = {"svrg": epoch}
+        if not args.no_estimators:
+            algos.update(saga=make_epoch(pm.pet_saga_epoch), sgd=make_epoch(pm.pet_sgd_epoch))
+        nrmse_all = time_to_nrmse(args, cfg, geom, pm, algos, y, r, a, beta, eps, delta, x0_host,
+                                  nrmse_mask, nrmse_level)
+        nrmse = nrmse_all.pop("svrg")
+        estimators = nrmse_all or None
 
     diff = None
     if not args.no_diff:
@@ -518,6 +542,7 @@ def main():
         "hbm_gbps_epoch": epoch_bytes * value / 1e9,
         "objective_final": objective,
         "time_to_nrmse": nrmse,
+        "time_to_nrmse_other_estimators": estimators,
         "differentiable": diff,
         "cpu_baseline": cpu,
     }

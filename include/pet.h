@@ -192,6 +192,26 @@ pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *state, float *x, const int
                           const float *tau, const uint8_t *update_pc, double *objective_out,
                           void *stream);
 
+/* The other stochastic estimators of Section 2.1, on the same iteration,
+ * state, schedules and clipped step as pet_svrg_epoch (J_i = D_i + (beta/n) S,
+ * eq. (template)):
+ *   SAGA, eq. (saga): g = n (grad J_i(x) - T_i) + sum_q T_q, then
+ *     T_i <- grad J_i(x).  The table T lives in state->ghat_i (n_subsets images,
+ *     FP32) and its sum in state->ghat (FP64).  When state->k == 0 the table is
+ *     filled at the current x before the first iteration (all subsets; that
+ *     iteration then steps along sum_q T_q, the full gradient).
+ *   SGD: g = n grad J_i(x) = n grad D_i(x) + beta grad S(x); ghat_i / ghat are
+ *     not used (may be null).
+ * x_snap and omega are not used.  A state serves one estimator: the SVRG
+ * snapshot table (data gradients only) is not a SAGA table.  Same argument
+ * rules and errors as pet_svrg_epoch. */
+pet_status pet_saga_epoch(pet_geom g, pet_svrg_state *state, float *x, const int32_t *subset_seq,
+                          const float *tau, const uint8_t *update_pc, double *objective_out,
+                          void *stream);
+pet_status pet_sgd_epoch(pet_geom g, pet_svrg_state *state, float *x, const int32_t *subset_seq,
+                         const float *tau, const uint8_t *update_pc, double *objective_out,
+                         void *stream);
+
 /* Reverse mode (unrolled reconstruction) -----------------------------------
  * Derivatives for differentiating through pet_svrg_epoch (Algorithm 1 with the
  * clipped step of eq. (sgm)); the second derivatives of the data term follow

@@ -26,6 +26,7 @@ _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "P
 
 EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
+           "pet_saga_epoch", "pet_sgd_epoch",
            "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
            "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_autotune", "pet_batch_set_launch",
            "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
@@ -89,6 +90,10 @@ def lib():
         L.pet_objective.argtypes = [P, P, P, I, P, P, P, ctypes.POINTER(F), F, F, F, P, P]
         L.pet_svrg_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), P, P]
+        L.pet_saga_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), P, P]
+        L.pet_sgd_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), P, P]
         L.pet_subset_hvp.argtypes = [P, I, P, P, P, I, P, P, P, P, I, P]
         L.pet_rdp_hvp.argtypes = [P, P, P, ctypes.POINTER(F), F, F, F, P, P, I, P, P]
         L.pet_precond_vjp.argtypes = [P, P, P, P, ctypes.POINTER(F), F, F, F, F, F, P, P, P, P]
@@ -287,6 +292,28 @@ def pet_svrg_epoch(geom, state, x, subset_seq, tau, update_pc, objective_out=Non
     _check(lib().pet_svrg_epoch(geom.handle, ctypes.byref(state.c), _ptr(x, torch.float32, geom.n_vox, "x"), seq,
                                 taus, upd, _ptr(objective_out, torch.float64, 1, "objective_out"), _stream(stream)))
     return x
+
+
+def _sgm_epoch(fn, geom, state, x, subset_seq, tau, update_pc, objective_out, stream):
+    n = geom.n_subsets
+    if not (len(subset_seq) == len(tau) == len(update_pc) == n):
+        raise ValueError("subset_seq, tau and update_pc need n_subsets entries each")
+    seq = (ctypes.c_int32 * n)(*[int(v) for v in subset_seq])
+    taus = (ctypes.c_float * n)(*[float(v) for v in tau])
+    upd = (ctypes.c_uint8 * n)(*[1 if v else 0 for v in update_pc])
+    _check(fn(geom.handle, ctypes.byref(state.c), _ptr(x, torch.float32, geom.n_vox, "x"), seq, taus, upd,
+              _ptr(objective_out, torch.float64, 1, "objective_out"), _stream(stream)))
+    return x
+
+
+def pet_saga_epoch(geom, state, x, subset_seq, tau, update_pc, objective_out=None, stream=None):
+    """SAGA epoch; state.ghat_i holds the table of grad J_i, state.ghat its FP64 sum."""
+    return _sgm_epoch(lib().pet_saga_epoch, geom, state, x, subset_seq, tau, update_pc, objective_out, stream)
+
+
+def pet_sgd_epoch(geom, state, x, subset_seq, tau, update_pc, objective_out=None, stream=None):
+    """SGD epoch (estimator n grad J_i)."""
+    return _sgm_epoch(lib().pet_sgd_epoch, geom, state, x, subset_seq, tau, update_pc, objective_out, stream)
 
 
 def pet_subset_hvp(geom, subset, x, v, y, add, mult, ybar_work, hv_out, accumulate=False, stream=None):

@@ -269,6 +269,67 @@ extern "C" pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *st, float *x, c
     return hip_check(e, "pet_svrg_epoch");
 }
 
+// SAGA (eq. (saga)) and SGD epochs: the same iteration as pet_svrg_epoch with
+// another estimator (Section 2.1).  SAGA fills its table of grad J_i at the
+// current x when the state is fresh (k = 0).
+static pet_status sgm_epoch(pet_geom g, pet_svrg_state *st, int estimator, float *x, const int32_t *subset_seq,
+                            const float *tau, const uint8_t *update_pc, double *objective_out, void *stream,
+                            const char *name) {
+    const std::string nm(name);
+    if (!g || !st || !x || !subset_seq || !tau || !update_pc) return fail(PET_E_ARG, nm + ": null argument");
+    if (!st->D || !st->sens || !st->y || (estimator == SGM_SAGA && (!st->ghat_i || !st->ghat)))
+        return fail(PET_E_ARG, nm + ": incomplete state");
+    if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, nm + ": bad y dtype");
+    if (st->k < 0) return fail(PET_E_STATE, nm + ": negative iteration counter");
+    const int n = g->d.n_subsets;
+    for (int j = 0; j < n; ++j)
+        if (subset_seq[j] < 0 || subset_seq[j] >= n) return fail(PET_E_ARG, nm + ": subset_seq entry out of range");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    const int64_t nv = g->n_vox;
+    for (int j = 0; j < n && e == hipSuccess; ++j) {
+        const int64_t k = st->k + j;
+        const int i = subset_seq[j];
+        const bool first = estimator == SGM_SAGA && k == 0;
+        e = launch_to_sheets(g, x, s);
+        if (first) {
+            // table of data gradients at x, then the prior shares and the sum
+            for (int q = 0; q < n && e == hipSuccess; ++q) {
+                e = subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+                if (e == hipSuccess) e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s);
+            }
+            if (e == hipSuccess)
+                e = launch_rdp(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, g->num, nullptr, nullptr, s);
+            if (e == hipSuccess) e = launch_saga_table_prior(g, st->ghat_i, st->ghat, g->num, s);
+        } else {
+            e = subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+            if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
+        }
+        if (e == hipSuccess)
+            e = launch_sgm_step(g, estimator, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j],
+                                st->sens, st->alpha, st->delta, st->D, first, g->g,
+                                estimator == SGM_SAGA ? st->ghat_i + (size_t)i * nv : nullptr, st->ghat, (float)n,
+                                tau[j], g->xtmp, s);
+        if (e == hipSuccess) e = launch_copy(x, g->xtmp, nv, s);
+    }
+    if (e != hipSuccess) return hip_check(e, name);
+    st->k += n;
+    if (objective_out)
+        e = objective_impl(g, x, st->y, st->y_dtype, st->add, st->mult, st->kappa, st->w, st->beta, st->gamma,
+                           st->eps, objective_out, s);
+    return hip_check(e, name);
+}
+
+extern "C" pet_status pet_saga_epoch(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
+                                     const float *tau, const uint8_t *update_pc, double *objective_out, void *stream) {
+    return sgm_epoch(g, st, SGM_SAGA, x, subset_seq, tau, update_pc, objective_out, stream, "pet_saga_epoch");
+}
+
+extern "C" pet_status pet_sgd_epoch(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
+                                    const float *tau, const uint8_t *update_pc, double *objective_out, void *stream) {
+    return sgm_epoch(g, st, SGM_SGD, x, subset_seq, tau, update_pc, objective_out, stream, "pet_sgd_epoch");
+}
+
 extern "C" pet_status pet_work_counts(pet_geom g, int subset, double *out, void *stream) {
     if (!g || !out) return fail(PET_E_ARG, "pet_work_counts: null argument");
     if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_work_counts: subset out of range");

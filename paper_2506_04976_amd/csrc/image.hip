@@ -58,6 +58,8 @@ enum RdpFlags {
     R_UPDATE = 16,    // SVRG step with clip into x_out
     R_SNAPSHOT = 32,  // estimator is ghat + beta grad S (snapshot iteration)
     R_EST_OUT = 64,   // also write the estimator (for the reverse pass)
+    R_SAGA = 128,     // SAGA estimator and table update (eq. (saga))
+    R_SGD = 256,      // SGD estimator n grad J_i
 };
 
 struct RdpArgs {
@@ -76,6 +78,9 @@ struct RdpArgs {
     const double *ghat;
     float n_sub, tau;
     float *x_out, *est_out;
+    // SAGA: table entry of the sampled subset and the table's FP64 sum
+    float *table_i;
+    double *table_sum;
 };
 
 // One thread per voxel.  RDP (eq. (rdp)) with gradient and Hessian diagonal as
@@ -140,7 +145,21 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
         }
         if (F & R_UPDATE) {
             float est;
-            if (F & R_SNAPSHOT) {
+            if (F & R_SAGA) {
+                // J_i = D_i + (beta / n) S, eq. (template); the table holds
+                // grad J_i at the iterate where subset i was last sampled
+                if (F & R_SNAPSHOT) {
+                    est = (float)a.table_sum[v];  // first iteration: table just filled at x
+                } else {
+                    const float ji = a.gi[v] + bg / a.n_sub;
+                    const float ti = a.table_i[v];
+                    est = fmaf(a.n_sub, ji - ti, (float)a.table_sum[v]);
+                    a.table_sum[v] += (double)ji - (double)ti;
+                    a.table_i[v] = ji;
+                }
+            } else if (F & R_SGD) {
+                est = fmaf(a.n_sub, a.gi[v], bg);
+            } else if (F & R_SNAPSHOT) {
                 est = (float)a.ghat[v] + bg;
             } else {
                 est = fmaf(a.n_sub, a.gi[v] - a.ghat_i[v], (float)a.ghat[v]) + bg;
@@ -184,6 +203,23 @@ __global__ void k_snapshot_accum(const float *__restrict__ G0, const float *__re
         ghat_i[v] = s;
         if (gcopy) gcopy[v] = s;
         ghat[v] = first ? (double)s : ghat[v] + (double)s;
+    }
+}
+
+// SAGA table at the first iteration: the data gradients of every subset are
+// in table (n x nvox); add each subset's prior share (beta / n) grad S(x) and
+// form the table's sum in FP64 from the stored entries.
+__global__ void k_saga_table_prior(float *__restrict__ table, double *__restrict__ table_sum,
+                                   const float *__restrict__ bgrad, int n_sub, int64_t nv) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        const float share = bgrad[v] / (float)n_sub;
+        double sum = 0.0;
+        for (int i = 0; i < n_sub; ++i) {
+            const float t = table[(size_t)i * nv + v] + share;
+            table[(size_t)i * nv + v] = t;
+            sum += (double)t;
+        }
+        table_sum[v] = sum;
     }
 }
 
@@ -329,6 +365,48 @@ hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *ka
         case 5: return rdp_launch<R_PRECOND | R_UPDATE | R_EST_OUT>(a, g->n_vox, s);
         case 6: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
         default: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT | R_EST_OUT>(a, g->n_vox, s);
+    }
+}
+
+hipError_t launch_saga_table_prior(const pet_geom_s *g, float *table, double *table_sum, const float *bgrad,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_saga_table_prior, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, table, table_sum, bgrad,
+                       g->d.n_subsets, g->n_vox);
+    return hipGetLastError();
+}
+
+hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, const float *kappa, const float *w27,
+                           float beta, float gamma, float eps, int update_pc, const float *sens, float alpha,
+                           float delta, float *D, int first, const float *gi, float *table_i, double *table_sum,
+                           float n_sub, float tau, float *x_out, hipStream_t s) {
+    RdpArgs a{};
+    a.x = x;
+    a.kappa = kappa;
+    for (int i = 0; i < 27; ++i) a.w.w[i] = w27[i];
+    a.beta = beta;
+    a.gamma = gamma;
+    a.eps = eps;
+    a.nx = g->d.nx;
+    a.ny = g->d.ny;
+    a.nz = g->d.nz;
+    a.sens = sens;
+    a.alpha = alpha;
+    a.delta = delta;
+    a.D = D;
+    a.gi = gi;
+    a.table_i = table_i;
+    a.table_sum = table_sum;
+    a.n_sub = n_sub;
+    a.tau = tau;
+    a.x_out = x_out;
+    if (estimator == SGM_SGD)
+        return update_pc ? rdp_launch<R_PRECOND | R_UPDATE | R_SGD>(a, g->n_vox, s)
+                         : rdp_launch<R_UPDATE | R_SGD>(a, g->n_vox, s);
+    switch ((update_pc ? 2 : 0) | (first ? 1 : 0)) {
+        case 0: return rdp_launch<R_UPDATE | R_SAGA>(a, g->n_vox, s);
+        case 1: return rdp_launch<R_UPDATE | R_SAGA | R_SNAPSHOT>(a, g->n_vox, s);
+        case 2: return rdp_launch<R_PRECOND | R_UPDATE | R_SAGA>(a, g->n_vox, s);
+        default: return rdp_launch<R_PRECOND | R_UPDATE | R_SAGA | R_SNAPSHOT>(a, g->n_vox, s);
     }
 }
 

@@ -183,6 +183,13 @@ hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *ka
                             float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
                             float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
                             float n_sub, float tau, float *x_out, float *est_out, hipStream_t s);
+enum SgmEstimator { SGM_SAGA = 1, SGM_SGD = 2 };
+hipError_t launch_saga_table_prior(const pet_geom_s *g, float *table, double *table_sum, const float *bgrad,
+                                  hipStream_t s);
+hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, const float *kappa, const float *w27,
+                           float beta, float gamma, float eps, int update_pc, const float *sens, float alpha,
+                           float delta, float *D, int first, const float *gi, float *table_i, double *table_sum,
+                           float n_sub, float tau, float *x_out, hipStream_t s);
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
                                  hipStream_t s);
 int rdp_blocks(const pet_geom_s *g);

@@ -195,8 +195,9 @@ def test_osem_and_objective_parity(case):
     assert float(out.cpu()) == pytest.approx(case.prob.objective(case.x_np.astype(np.float64)), rel=1e-5)
 
 
-def _svrg_pair(case, epochs):
-    """Run OSEM init + `epochs` SVRG epochs on the GPU and in the oracle."""
+def _svrg_pair(case, epochs, algo="svrg"):
+    """Run OSEM init + `epochs` epochs of SVRG, SAGA or SGD on the GPU and in
+    the oracle."""
     pm = case.pm
     cfg, n = case.cfg, case.cfg["n_subsets"]
     beta = configs.beta_value(cfg)
@@ -210,18 +211,19 @@ def _svrg_pair(case, epochs):
     st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=beta, gamma=2.0, eps=1e-3 * mx,
                              alpha=1.0, delta=1e-3 * mx)
     orders = data.subset_orders(cfg, epochs)
-    tau_rule = recon.stepsize_vanishing(1.0, 0.02, n)
+    tau_rule = recon.stepsize_vanishing(0.3, 0.5, n) if algo == "sgd" else recon.stepsize_vanishing(1.0, 0.02, n)
     upd = recon.pc_update_iters(n)
+    epoch_fn = {"svrg": pm.pet_svrg_epoch, "saga": pm.pet_saga_epoch, "sgd": pm.pet_sgd_epoch}[algo]
     for e in range(epochs):
         ks = [e * n + j for j in range(n)]
-        pm.pet_svrg_epoch(case.geom, st, x, orders[e], [tau_rule(k) for k in ks], [k in upd for k in ks])
+        epoch_fn(case.geom, st, x, orders[e], [tau_rule(k) for k in ks], [k in upd for k in ks])
     x_gpu = x.cpu().double().numpy()
     # oracle
     x0 = recon.osem_epoch(case.prob, np.ones(case.prob.shape))
     m0 = float(x0.max())
     prob = recon.Problem(cfg, case.d["y"], case.d["r"], case.d["mult"], beta=beta, gamma=2.0, eps=1e-3 * m0,
                          alpha=1.0, delta=1e-3 * m0)
-    x_orc = recon.svrg(prob, x0, epochs, recon.order_rule(orders), tau_rule, upd)
+    x_orc = getattr(recon, algo)(prob, x0, epochs, recon.order_rule(orders), tau_rule, upd)
     return x_gpu, x_orc.ravel()
 
 
@@ -230,4 +232,13 @@ def test_svrg_reconstruction_parity(case):
     x_gpu, x_orc = _svrg_pair(case, epochs)
     err = _rel(x_gpu, x_orc)
     print(f"[{case.cfg['name']}] {epochs} epochs: relative L2 {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("algo", ["saga", "sgd"])
+def test_saga_sgd_reconstruction_parity(case, algo):
+    epochs = case.cfg["epochs"]
+    x_gpu, x_orc = _svrg_pair(case, epochs, algo)
+    err = _rel(x_gpu, x_orc)
+    print(f"[{case.cfg['name']}] {algo} {epochs} epochs: relative L2 {err:.2e}", flush=True)
     assert err <= 1e-4

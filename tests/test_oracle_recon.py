@@ -1,8 +1,10 @@
 """Pins for the oracle's data term, preconditioner and algorithms: KL special
 cases, the harmonic-mean identity and bound of the preconditioner (Section 2.3),
-MLEM monotonicity, SVRG unbiasedness, the n = 1 reduction of Algorithm 1 to
-projected gradient descent, and convergence to an independently computed MAP
-(scipy L-BFGS-B on a dense system matrix built from unit images)."""
+MLEM monotonicity, SVRG unbiasedness, the n = 1 reduction of Algorithm 1, SAGA
+and SGD to projected gradient descent, the objective's gradient against finite
+differences, SAGA's first step, and convergence of SVRG and SAGA to an
+independently computed MAP (scipy L-BFGS-B on a dense system matrix built from
+unit images)."""
 
 import os
 
@@ -134,8 +136,9 @@ def xmap_has_bound_voxels(x):
     return np.any(x == 0.0)
 
 
-def test_svrg_converges_to_dense_map(oracle_built):
-    cfg, d, prob, x0 = _tiny_problem()
+def _dense_map(prob):
+    """MAP by scipy L-BFGS-B on the dense system (bounds x >= 0), and the
+    dense objective evaluated there."""
     A = _dense(prob)
     y = np.concatenate([yi.ravel() for yi in prob.y])
     r = np.concatenate([ri.ravel() for ri in prob.r])
@@ -151,8 +154,13 @@ def test_svrg_converges_to_dense_map(oracle_built):
 
     res = minimize(f, np.ones(A.shape[1]), jac=True, method="L-BFGS-B", bounds=[(0, None)] * A.shape[1],
                    options=dict(maxiter=50000, maxfun=100000, ftol=1e-16, gtol=1e-14))
-    assert xmap_has_bound_voxels(res.x)
-    xmap = res.x.reshape(prob.shape)
+    return res.x.reshape(prob.shape), f(res.x)[0]
+
+
+def test_svrg_converges_to_dense_map(oracle_built):
+    cfg, d, prob, x0 = _tiny_problem()
+    xmap, fmap = _dense_map(prob)
+    assert xmap_has_bound_voxels(xmap)
     x_init = recon.osem_epoch(prob, x0)
     orders = data.subset_orders(cfg, 300)
     x = recon.svrg(prob, x_init, 300, recon.order_rule(orders), recon.stepsize_vanishing(1.0, 0.02, prob.n),
@@ -163,14 +171,65 @@ def test_svrg_converges_to_dense_map(oracle_built):
                       recon.pc_update_iters(prob.n))
     assert np.linalg.norm(x_fp - xmap) / np.linalg.norm(xmap) < 1e-5
     # objective agrees with the dense evaluation
-    assert prob.objective(xmap) == pytest.approx(f(res.x)[0], rel=1e-12)
+    assert prob.objective(xmap) == pytest.approx(fmap, rel=1e-12)
 
 
-def test_saga_and_sgd_run(oracle_built):
+def test_full_gradient_matches_objective_differences(oracle_built):
+    # the sum of the subset gradients grad J_i = grad D_i + (beta/n) grad S
+    # (eq. (template)) is the gradient of the objective, checked against
+    # central differences of the separately coded objective value
     cfg, d, prob, x0 = _tiny_problem()
-    orders = data.subset_orders(cfg, 20)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.5, 2.0, x0.shape)
+    g = sum(prob.grad_J(x, i) for i in range(prob.n))
+    for _ in range(3):
+        v = rng.standard_normal(x.shape)
+        h = 1e-6
+        fd = (prob.objective(x + h * v) - prob.objective(x - h * v)) / (2 * h)
+        assert float(np.sum(g * v)) == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("algo", ["saga", "sgd"])
+def test_single_subset_is_projected_gradient(oracle_built, algo):
+    # with one subset every estimator is the full gradient
+    cfg, d, prob, x0 = _tiny_problem(n_subsets=1)
+    x_alg = getattr(recon, algo)(prob, x0, 6, lambda k: 0, recon.stepsize_constant(0.5), {0})
+    x = np.array(x0, np.float64)
+    D = recon.precond_harmonic(x, prob.sens(), prob.prior_hessdiag(x), 1.0, 1e-3)
+    for _ in range(6):
+        x = np.maximum(0, x - 0.5 * D * prob.full_grad(x))
+    assert np.allclose(x_alg, x, rtol=1e-12, atol=1e-14)
+
+
+def test_saga_first_step_is_svrg_first_step(oracle_built):
+    # SAGA's table starts at x0, so its first estimator is the full gradient,
+    # as at SVRG's first (snapshot) iteration; later steps differ
+    cfg, d, prob, x0 = _tiny_problem()
+    x0 = recon.osem_epoch(prob, x0)
+    orders = data.subset_orders(cfg, 2)
     rule = recon.order_rule(orders)
-    xs = recon.saga(prob, x0, 20, rule, recon.stepsize_vanishing(1.0, 0.02, prob.n), recon.pc_update_iters(prob.n))
-    xg = recon.sgd(prob, x0, 20, rule, recon.stepsize_vanishing(0.3, 0.5, prob.n), recon.pc_update_iters(prob.n))
-    assert prob.objective(xs) < prob.objective(x0)
-    assert prob.objective(xg) < prob.objective(x0)
+    only_first = lambda k: 0.7 if k == 0 else 0.0  # noqa: E731
+    a = recon.saga(prob, x0, 1, rule, only_first, {0})
+    b = recon.svrg(prob, x0, 1, rule, only_first, {0})
+    assert np.array_equal(a, b)
+    a2 = recon.saga(prob, x0, 2, rule, recon.stepsize_constant(0.7), {0})
+    b2 = recon.svrg(prob, x0, 2, rule, recon.stepsize_constant(0.7), {0})
+    assert np.linalg.norm(a2 - b2) > 1e-6 * np.linalg.norm(b2)
+
+
+def test_saga_converges_to_dense_map_with_constant_steps(oracle_built):
+    # SAGA converges with a constant stepsize (Section 2.1); SGD with the same
+    # constant stepsize stalls at a distance set by its variance
+    cfg, d, prob, x0 = _tiny_problem()
+    xmap, _ = _dense_map(prob)
+    x_init = recon.osem_epoch(prob, x0)
+    orders = data.subset_orders(cfg, 400)
+    rule = recon.order_rule(orders)
+    x = recon.saga(prob, x_init, 400, rule, recon.stepsize_constant(0.5), recon.pc_update_iters(prob.n))
+    err_saga = np.linalg.norm(x - xmap) / np.linalg.norm(xmap)
+    assert err_saga < 1e-6
+    xg = recon.sgd(prob, x_init, 60, rule, recon.stepsize_constant(0.5), recon.pc_update_iters(prob.n))
+    assert np.linalg.norm(xg - xmap) / np.linalg.norm(xmap) > 10 * err_saga
+    # the MAP is a fixed point of SAGA
+    x_fp = recon.saga(prob, xmap, 4, rule, recon.stepsize_constant(1.0), recon.pc_update_iters(prob.n))
+    assert np.linalg.norm(x_fp - xmap) / np.linalg.norm(xmap) < 1e-5
