@@ -167,18 +167,36 @@ def osem_epoch(prob, x, order=None):
 
 
 # --- Algorithm 1: preconditioned SVRG -----------------------------------------
-def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, callback=None):
+def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, callback=None, bb_iters=None,
+         weight=None, importance_u=None, record=None):
     """Preconditioned SVRG as in Algorithm 1 (Appendix B) with the
     nonnegativity proximal step of eq. (sgm).
 
     subset_rule(k) -> subset index; stepsize(k) -> tau; update_pc_iters: set of
     iterations k at which D is recomputed by eq. (preconditioner).
+
+    bb_iters (ALG2/ALG3, Section 2.2): snapshot iterations at which the short
+    Barzilai-Borwein step is recomputed from the last two snapshots,
+    tau_bb = p.q / q.D q with p the difference of the snapshot images and q the
+    difference of their full gradients (D the current preconditioner; the
+    paper's p.q / q.q for D = I); it is +inf until first computed and the
+    step is min(stepsize(k), tau_bb).
+    weight(k): the estimator is weight(k) (grad J_i(x) - ghat_i) + ghat
+    instead of n (...) + ghat.
+    importance_u (importance sampling, Section 2.4): one uniform number in
+    [0, 1) per iteration; at each snapshot p_i = ||grad J_i|| / sum_j ||grad J_j||,
+    and iteration k samples i = min{i : p_0 + ... + p_i > u_k} (with
+    replacement) with weight 1 / p_i, which keeps the estimator unbiased.
+    subset_rule and weight are then not used.  record (a list) receives
+    ("snapshot", k, norms) and ("sample", k, i, weight) entries.
     """
     n = prob.n
     x = np.array(x0, np.float64)
     D = None
     ghat_i = [None] * n
     ghat = None
+    tau_bb = np.inf
+    x_prev = g_prev = None
     for k in range(n_epochs * n):
         if k in update_pc_iters:
             D = precond_harmonic(x, prob.sens(), prob.prior_hessdiag(x), prob.alpha, prob.delta)
@@ -187,14 +205,51 @@ def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, ca
                 ghat_i[i] = prob.grad_J(x, i)
             ghat = sum(ghat_i)
             g = ghat
+            if importance_u is not None:
+                norms = [float(np.linalg.norm(gi)) for gi in ghat_i]
+                probs = importance_probabilities(norms)
+                if record is not None:
+                    record.append(("snapshot", k, norms))
+            if bb_iters is not None:
+                if k in bb_iters and x_prev is not None:
+                    p = x - x_prev
+                    q = ghat - g_prev
+                    pq, qdq = float(np.sum(p * q)), float(np.sum(q * D * q))
+                    if pq > 0 and qdq > 0:
+                        tau_bb = pq / qdq
+                x_prev, g_prev = x.copy(), ghat.copy()
         else:
-            i = subset_rule(k)
-            g = n * (prob.grad_J(x, i) - ghat_i[i]) + ghat
-        tau = stepsize(k)
+            if importance_u is not None:
+                i = sample_inverse_cdf(probs, importance_u[k])
+                w = 1.0 / probs[i]
+                if record is not None:
+                    record.append(("sample", k, i, w))
+            else:
+                i = subset_rule(k)
+                w = n if weight is None else weight(k)
+            g = w * (prob.grad_J(x, i) - ghat_i[i]) + ghat
+        tau = stepsize(k) if bb_iters is None else min(stepsize(k), tau_bb)
         x = np.maximum(0.0, x - tau * D * g)
         if callback is not None and (k + 1) % n == 0:
             callback((k + 1) // n, x)
     return x
+
+
+def importance_probabilities(norms):
+    """p_i = ||grad J_i|| / sum_j ||grad J_j|| (Section 2.4)."""
+    total = float(sum(norms))
+    return [float(v) / total for v in norms]
+
+
+def sample_inverse_cdf(probs, u):
+    """Smallest i with p_0 + ... + p_i > u (the last index if rounding leaves
+    the total below u)."""
+    c = 0.0
+    for i, p in enumerate(probs):
+        c += p
+        if c > u:
+            return i
+    return len(probs) - 1
 
 
 def saga(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, callback=None):
