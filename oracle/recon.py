@@ -181,14 +181,16 @@ def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, ca
     difference of their full gradients (D the current preconditioner; the
     paper's p.q / q.q for D = I); it is +inf until first computed and the
     step is min(stepsize(k), tau_bb).
-    weight(k): the estimator is weight(k) (grad J_i(x) - ghat_i) + ghat
-    instead of n (...) + ghat.
+    weight(k): estimator weight w of the sampled subset.  With a weight the
+    estimator is w (grad D_i(x) - grad D_i(xhat)) + sum_j grad D_j(xhat)
+    + beta grad S(x): the weight applies to the data terms and the prior enters
+    exactly, which is eq. (svrg) for w = n and unbiased for w = 1 / p_i.
     importance_u (importance sampling, Section 2.4): one uniform number in
     [0, 1) per iteration; at each snapshot p_i = ||grad J_i|| / sum_j ||grad J_j||,
     and iteration k samples i = min{i : p_0 + ... + p_i > u_k} (with
-    replacement) with weight 1 / p_i, which keeps the estimator unbiased.
-    subset_rule and weight are then not used.  record (a list) receives
-    ("snapshot", k, norms) and ("sample", k, i, weight) entries.
+    replacement) with weight 1 / p_i.  subset_rule and weight are then not
+    used.  record (a list) receives ("snapshot", k, norms) and
+    ("sample", k, i, weight) entries.
     """
     n = prob.n
     x = np.array(x0, np.float64)
@@ -205,6 +207,9 @@ def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, ca
                 ghat_i[i] = prob.grad_J(x, i)
             ghat = sum(ghat_i)
             g = ghat
+            if weight is not None or importance_u is not None:
+                dhat_i = [prob.data_grad(x, i) for i in range(n)]
+                dhat = sum(dhat_i)
             if importance_u is not None:
                 norms = [float(np.linalg.norm(gi)) for gi in ghat_i]
                 probs = importance_probabilities(norms)
@@ -226,8 +231,11 @@ def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, ca
                     record.append(("sample", k, i, w))
             else:
                 i = subset_rule(k)
-                w = n if weight is None else weight(k)
-            g = w * (prob.grad_J(x, i) - ghat_i[i]) + ghat
+                w = None if weight is None else weight(k)
+            if w is None:
+                g = n * (prob.grad_J(x, i) - ghat_i[i]) + ghat
+            else:
+                g = w * (prob.data_grad(x, i) - dhat_i[i]) + dhat + prob.prior_grad(x)
         tau = stepsize(k) if bb_iters is None else min(stepsize(k), tau_bb)
         x = np.maximum(0.0, x - tau * D * g)
         if callback is not None and (k + 1) % n == 0:
