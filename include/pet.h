@@ -174,6 +174,16 @@ typedef struct {
     float beta, gamma, eps, alpha, delta;
     int omega;
     int64_t k;
+    /* ALG2/ALG3 extensions (pet_svrg_epoch_ex), all nullable device buffers:
+     * bb [4] double: short Barzilai-Borwein state {p.q, q.D q, tau_bb, updates},
+     *   reset at k = 0 with tau_bb = +inf; every step of an epoch then uses
+     *   min(tau[j], tau_bb);
+     * g_prev [n_vox] float: full gradient at the last snapshot (needed with bb);
+     * gnorm [n_subsets] double: ||grad J_i(xhat)|| at the last snapshot
+     *   (importance sampling, Section 2.4). */
+    double *bb;
+    float *g_prev;
+    double *gnorm;
 } pet_svrg_state;
 
 /* One epoch = n_subsets iterations of Algorithm 1 with the nonnegativity
@@ -191,6 +201,26 @@ typedef struct {
 pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *state, float *x, const int32_t *subset_seq,
                           const float *tau, const uint8_t *update_pc, double *objective_out,
                           void *stream);
+
+/* pet_svrg_epoch with the ALG2/ALG3 options (Section 2.2, Section 2.4, Section 4
+ * and its table of hyperparameters).  opt (host, nullable = pet_svrg_epoch):
+ *   bb_update [n] flags: at these iterations (snapshots only; PET_E_ARG
+ *     otherwise) recompute tau_bb = p.q / q.D q from the last two snapshots,
+ *     p the difference of the snapshot images and q of their full gradients
+ *     (the short BB step in the metric of the diagonal preconditioner D; the
+ *     paper's p.q / q.q for D = I); kept when either dot is not positive.  The
+ *     new bound already applies to that iteration's step.  Needs state->bb.
+ *   weight [n] floats (> 0): estimator weight w of the sampled subset,
+ *     g = w (grad D_i(x) - ghat_i) + ghat + beta grad S(x); w = n is uniform
+ *     sampling, w = 1 / p_i importance sampling with replacement.
+ * With state->gnorm set, every snapshot also writes ||grad J_i(xhat)||. */
+typedef struct {
+    const uint8_t *bb_update;
+    const float *weight;
+} pet_svrg_options;
+pet_status pet_svrg_epoch_ex(pet_geom g, pet_svrg_state *state, float *x, const int32_t *subset_seq,
+                             const float *tau, const uint8_t *update_pc, const pet_svrg_options *opt,
+                             double *objective_out, void *stream);
 
 /* The other stochastic estimators of Section 2.1, on the same iteration,
  * state, schedules and clipped step as pet_svrg_epoch (J_i = D_i + (beta/n) S,

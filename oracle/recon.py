@@ -189,8 +189,8 @@ def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, ca
     [0, 1) per iteration; at each snapshot p_i = ||grad J_i|| / sum_j ||grad J_j||,
     and iteration k samples i = min{i : p_0 + ... + p_i > u_k} (with
     replacement) with weight 1 / p_i.  subset_rule and weight are then not
-    used.  record (a list) receives ("snapshot", k, norms) and
-    ("sample", k, i, weight) entries.
+    used.  record (a list) receives ("snapshot", k, norms),
+    ("sample", k, i, weight) and ("bb", k, p.q, q.D q, tau_bb) entries.
     """
     n = prob.n
     x = np.array(x0, np.float64)
@@ -222,6 +222,8 @@ def svrg(prob, x0, n_epochs, subset_rule, stepsize, update_pc_iters, omega=2, ca
                     pq, qdq = float(np.sum(p * q)), float(np.sum(q * D * q))
                     if pq > 0 and qdq > 0:
                         tau_bb = pq / qdq
+                    if record is not None:
+                        record.append(("bb", k, pq, qdq, tau_bb))
                 x_prev, g_prev = x.copy(), ghat.copy()
         else:
             if importance_u is not None:

@@ -26,7 +26,7 @@ _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "P
 
 EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
-           "pet_saga_epoch", "pet_sgd_epoch",
+           "pet_svrg_epoch_ex", "pet_saga_epoch", "pet_sgd_epoch",
            "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
            "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_autotune", "pet_batch_set_launch",
            "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
@@ -56,7 +56,12 @@ class SvrgState(ctypes.Structure):
                 ("y_dtype", ctypes.c_int), ("add", ctypes.c_void_p), ("mult", ctypes.c_void_p),
                 ("kappa", ctypes.c_void_p), ("w", ctypes.c_float * 27), ("beta", ctypes.c_float),
                 ("gamma", ctypes.c_float), ("eps", ctypes.c_float), ("alpha", ctypes.c_float),
-                ("delta", ctypes.c_float), ("omega", ctypes.c_int), ("k", ctypes.c_int64)]
+                ("delta", ctypes.c_float), ("omega", ctypes.c_int), ("k", ctypes.c_int64),
+                ("bb", ctypes.c_void_p), ("g_prev", ctypes.c_void_p), ("gnorm", ctypes.c_void_p)]
+
+
+class SvrgOptions(ctypes.Structure):
+    _fields_ = [("bb_update", ctypes.POINTER(ctypes.c_uint8)), ("weight", ctypes.POINTER(ctypes.c_float))]
 
 
 class SvrgVjpBufs(ctypes.Structure):
@@ -90,6 +95,9 @@ def lib():
         L.pet_objective.argtypes = [P, P, P, I, P, P, P, ctypes.POINTER(F), F, F, F, P, P]
         L.pet_svrg_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), P, P]
+        L.pet_svrg_epoch_ex.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(SvrgOptions),
+                                        P, P]
         L.pet_saga_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8), P, P]
         L.pet_sgd_epoch.argtypes = [P, ctypes.POINTER(SvrgState), P, ctypes.POINTER(ctypes.c_int32),
@@ -281,16 +289,33 @@ def pet_objective(geom, x, y, add, mult, kappa, w27, beta, gamma, eps, out, stre
     return out
 
 
-def pet_svrg_epoch(geom, state, x, subset_seq, tau, update_pc, objective_out=None, stream=None):
-    """state: SvrgStateBuffers; subset_seq/tau/update_pc: host sequences of n_subsets entries."""
+def pet_svrg_epoch(geom, state, x, subset_seq, tau, update_pc, objective_out=None, stream=None, bb_update=None,
+                   weight=None):
+    """state: SvrgStateBuffers; subset_seq/tau/update_pc: host sequences of n_subsets entries.
+    bb_update (n flags) and weight (n floats) select pet_svrg_epoch_ex; bb_update needs a
+    state created with bb=True."""
     n = geom.n_subsets
     if not (len(subset_seq) == len(tau) == len(update_pc) == n):
         raise ValueError("subset_seq, tau and update_pc need n_subsets entries each")
     seq = (ctypes.c_int32 * n)(*[int(v) for v in subset_seq])
     taus = (ctypes.c_float * n)(*[float(v) for v in tau])
     upd = (ctypes.c_uint8 * n)(*[1 if v else 0 for v in update_pc])
-    _check(lib().pet_svrg_epoch(geom.handle, ctypes.byref(state.c), _ptr(x, torch.float32, geom.n_vox, "x"), seq,
-                                taus, upd, _ptr(objective_out, torch.float64, 1, "objective_out"), _stream(stream)))
+    xp = _ptr(x, torch.float32, geom.n_vox, "x")
+    op = _ptr(objective_out, torch.float64, 1, "objective_out")
+    if bb_update is None and weight is None:
+        _check(lib().pet_svrg_epoch(geom.handle, ctypes.byref(state.c), xp, seq, taus, upd, op, _stream(stream)))
+        return x
+    opt = SvrgOptions()
+    if bb_update is not None:
+        if len(bb_update) != n:
+            raise ValueError("bb_update needs n_subsets entries")
+        opt.bb_update = (ctypes.c_uint8 * n)(*[1 if v else 0 for v in bb_update])
+    if weight is not None:
+        if len(weight) != n:
+            raise ValueError("weight needs n_subsets entries")
+        opt.weight = (ctypes.c_float * n)(*[float(v) for v in weight])
+    _check(lib().pet_svrg_epoch_ex(geom.handle, ctypes.byref(state.c), xp, seq, taus, upd, ctypes.byref(opt), op,
+                                   _stream(stream)))
     return x
 
 
@@ -378,13 +403,18 @@ class SvrgStateBuffers:
     """Device buffers + the C state struct of preconditioned SVRG."""
 
     def __init__(self, geom, y, add, mult, sens, beta, gamma, eps, alpha=1.0, delta=0.0, w27=None, kappa=None,
-                 omega=2):
+                 omega=2, bb=False, gnorm=False):
         dev = y.device
         n, nv = geom.n_subsets, geom.n_vox
         self.ghat_i = torch.zeros((n, nv), dtype=torch.float32, device=dev)
         self.ghat = torch.zeros(nv, dtype=torch.float64, device=dev)
         self.x_snap = torch.zeros(nv, dtype=torch.float32, device=dev)
         self.D = torch.zeros(nv, dtype=torch.float32, device=dev)
+        # short Barzilai-Borwein state {p.q, q.D q, tau_bb, updates} and the
+        # last snapshot's full gradient; per-subset gradient norms
+        self.bb = torch.zeros(4, dtype=torch.float64, device=dev) if bb else None
+        self.g_prev = torch.zeros(nv, dtype=torch.float32, device=dev) if bb else None
+        self.gnorm = torch.zeros(n, dtype=torch.float64, device=dev) if gnorm else None
         self.refs = (y, add, mult, sens, kappa)
         if w27 is None:
             w27 = rdp_weights27(geom.cfg["vx"], geom.cfg["vy"], geom.cfg["vz"])
@@ -392,6 +422,9 @@ class SvrgStateBuffers:
         c.ghat_i = self.ghat_i.data_ptr()
         c.ghat = self.ghat.data_ptr()
         c.x_snap = self.x_snap.data_ptr()
+        c.bb = self.bb.data_ptr() if bb else None
+        c.g_prev = self.g_prev.data_ptr() if bb else None
+        c.gnorm = self.gnorm.data_ptr() if gnorm else None
         c.D = self.D.data_ptr()
         c.sens = _ptr(sens, torch.float32, nv, "sens").value
         c.y = _ptr(y, None, geom.n_bins, "y").value

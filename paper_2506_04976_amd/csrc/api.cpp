@@ -3,6 +3,7 @@
 // is a sequence of kernel launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -224,49 +225,82 @@ extern "C" pet_status pet_objective(pet_geom g, const float *x, const void *y, i
                      "pet_objective");
 }
 
-extern "C" pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
-                                     const float *tau, const uint8_t *update_pc, double *objective_out, void *stream) {
-    if (!g || !st || !x || !subset_seq || !tau || !update_pc) return fail(PET_E_ARG, "pet_svrg_epoch: null argument");
+static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
+                                  const float *tau, const uint8_t *update_pc, const pet_svrg_options *opt,
+                                  double *objective_out, void *stream, const char *name) {
+    const std::string nm(name);
+    if (!g || !st || !x || !subset_seq || !tau || !update_pc) return fail(PET_E_ARG, nm + ": null argument");
     if (!st->ghat_i || !st->ghat || !st->x_snap || !st->D || !st->sens || !st->y)
-        return fail(PET_E_ARG, "pet_svrg_epoch: incomplete state");
-    if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, "pet_svrg_epoch: bad y dtype");
-    if (st->omega < 1) return fail(PET_E_ARG, "pet_svrg_epoch: omega must be >= 1");
-    if (st->k < 0) return fail(PET_E_STATE, "pet_svrg_epoch: negative iteration counter");
+        return fail(PET_E_ARG, nm + ": incomplete state");
+    if (st->bb && !st->g_prev) return fail(PET_E_ARG, nm + ": g_prev is needed with bb");
+    if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, nm + ": bad y dtype");
+    if (st->omega < 1) return fail(PET_E_ARG, nm + ": omega must be >= 1");
+    if (st->k < 0) return fail(PET_E_STATE, nm + ": negative iteration counter");
     const int n = g->d.n_subsets;
-    for (int j = 0; j < n; ++j)
-        if (subset_seq[j] < 0 || subset_seq[j] >= n) return fail(PET_E_ARG, "pet_svrg_epoch: subset_seq entry out of range");
+    const int64_t om = (int64_t)st->omega * n;
+    for (int j = 0; j < n; ++j) {
+        if (subset_seq[j] < 0 || subset_seq[j] >= n) return fail(PET_E_ARG, nm + ": subset_seq entry out of range");
+        if (opt && opt->weight && !(opt->weight[j] > 0.f && std::isfinite(opt->weight[j])))
+            return fail(PET_E_ARG, nm + ": weights must be positive and finite");
+        if (opt && opt->bb_update && opt->bb_update[j] && (st->k + j) % om != 0)
+            return fail(PET_E_ARG, nm + ": bb_update only at snapshot iterations");
+    }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     const int64_t nv = g->n_vox;
+    const double *tau_bb = st->bb ? st->bb + 2 : nullptr;
     for (int j = 0; j < n && e == hipSuccess; ++j) {
         const int64_t k = st->k + j;
-        const bool snap = (k % ((int64_t)st->omega * n)) == 0;
-        e = launch_to_sheets(g, x, s);
+        const bool snap = (k % om) == 0;
+        const int i = subset_seq[j];
+        const float w = (opt && opt->weight) ? opt->weight[j] : (float)n;
+        if (st->bb && k == 0) e = launch_bb_init(st->bb, s);
+        if (e == hipSuccess) e = launch_to_sheets(g, x, s);
         if (snap) {
-            for (int i = 0; i < n && e == hipSuccess; ++i) {
-                e = subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
-                if (e == hipSuccess) e = launch_snapshot_accum(g, st->ghat_i + (size_t)i * nv, st->ghat, nullptr, i == 0, s);
+            for (int q = 0; q < n && e == hipSuccess; ++q) {
+                e = subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+                if (e == hipSuccess) e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s);
             }
+            // BB bookkeeping: 0 none, 1 keep the full gradient, 2 also recompute the step bound
+            const int bb_mode = !st->bb ? 0 : (opt && opt->bb_update && opt->bb_update[j] && k > 0) ? 2 : 1;
+            float *grad_out = st->gnorm ? g->num : nullptr;
+            if (e == hipSuccess)
+                e = launch_svrg_step_ex(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
+                                        st->alpha, st->delta, st->D, 1, g->g, st->ghat_i + (size_t)i * nv, st->ghat, w,
+                                        tau[j], tau_bb, bb_mode, st->x_snap, st->g_prev, grad_out, g->xtmp, s);
+            if (e == hipSuccess && bb_mode == 2) {
+                e = launch_bb_finish(g, st->bb, s);
+                if (e == hipSuccess) e = launch_step_stored(g, x, st->D, st->g_prev, tau[j], tau_bb, g->xtmp, s);
+            }
+            if (e == hipSuccess && st->gnorm) e = launch_subset_norms(g, st->ghat_i, g->num, st->gnorm, s);
             if (e == hipSuccess) e = launch_copy(st->x_snap, x, nv, s);
         } else {
-            const int i = subset_seq[j];
             e = subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
             if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
-        }
-        if (e == hipSuccess) {
-            const int i = subset_seq[j];
-            e = launch_svrg_step(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
-                                 st->alpha, st->delta, st->D, snap, g->g, st->ghat_i + (size_t)i * nv, st->ghat,
-                                 (float)n, tau[j], g->xtmp, nullptr, s);
+            if (e == hipSuccess)
+                e = launch_svrg_step_ex(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
+                                        st->alpha, st->delta, st->D, 0, g->g, st->ghat_i + (size_t)i * nv, st->ghat, w,
+                                        tau[j], tau_bb, 0, nullptr, nullptr, nullptr, g->xtmp, s);
         }
         if (e == hipSuccess) e = launch_copy(x, g->xtmp, nv, s);
     }
-    if (e != hipSuccess) return hip_check(e, "pet_svrg_epoch");
+    if (e != hipSuccess) return hip_check(e, name);
     st->k += n;
     if (objective_out)
         e = objective_impl(g, x, st->y, st->y_dtype, st->add, st->mult, st->kappa, st->w, st->beta, st->gamma,
                            st->eps, objective_out, s);
-    return hip_check(e, "pet_svrg_epoch");
+    return hip_check(e, name);
+}
+
+extern "C" pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
+                                     const float *tau, const uint8_t *update_pc, double *objective_out, void *stream) {
+    return svrg_epoch_impl(g, st, x, subset_seq, tau, update_pc, nullptr, objective_out, stream, "pet_svrg_epoch");
+}
+
+extern "C" pet_status pet_svrg_epoch_ex(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
+                                        const float *tau, const uint8_t *update_pc, const pet_svrg_options *opt,
+                                        double *objective_out, void *stream) {
+    return svrg_epoch_impl(g, st, x, subset_seq, tau, update_pc, opt, objective_out, stream, "pet_svrg_epoch_ex");
 }
 
 // SAGA (eq. (saga)) and SGD epochs: the same iteration as pet_svrg_epoch with

@@ -284,7 +284,8 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes == 0 ? 16 : bytes) == hipSuccess; };
     g->t0_elems = (size_t)d.nx * (d.ny + 2 * PADA) * rz;
     g->t1_elems = (size_t)d.ny * (d.nx + 2 * PADA) * rz;
-    g->n_partial = std::max<size_t>(2 * (size_t)nl, (size_t)(g->n_vox + 255) / 256) + 64;
+    // line-kernel partials (2 per line) or two per image block (BB dots)
+    g->n_partial = std::max<size_t>(2 * (size_t)nl, 2 * (size_t)((g->n_vox + IMG_BLOCK - 1) / IMG_BLOCK)) + 64;
     bool ok = alloc((void **)&g->lines, sizeof(LineP) * nl) && alloc((void **)&g->planes, sizeof(PlaneP) * planes.size()) &&
               alloc((void **)&g->segs, sizeof(SegP) * hsegs.size()) &&
               alloc((void **)&g->views_dev, sizeof(int) * hviews.size()) &&

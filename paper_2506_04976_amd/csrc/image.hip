@@ -7,8 +7,6 @@
 namespace pet {
 namespace {
 
-constexpr int IMG_BLOCK = 256;
-
 // x [iz][iy][ix] -> T0 [ix][iy + PADA][iz + PADZ] and T1 [iy][ix + PADA][iz + PADZ]
 // (interiors only; the zero borders are set once at creation).
 __global__ void k_to_sheets(const float *__restrict__ x, float *__restrict__ T0, float *__restrict__ T1,
@@ -60,6 +58,8 @@ enum RdpFlags {
     R_EST_OUT = 64,   // also write the estimator (for the reverse pass)
     R_SAGA = 128,     // SAGA estimator and table update (eq. (saga))
     R_SGD = 256,      // SGD estimator n grad J_i
+    R_BB_STORE = 512, // keep the snapshot's full gradient in g_prev
+    R_BB_DOT = 1024,  // short-BB dots against the previous snapshot; no step
 };
 
 struct RdpArgs {
@@ -81,6 +81,11 @@ struct RdpArgs {
     // SAGA: table entry of the sampled subset and the table's FP64 sum
     float *table_i;
     double *table_sum;
+    // short Barzilai-Borwein step: previous snapshot image and full gradient,
+    // and the current step bound (device, nullable)
+    const float *x_snap;
+    float *g_prev;
+    const double *tau_bb;
 };
 
 // One thread per voxel.  RDP (eq. (rdp)) with gradient and Hessian diagonal as
@@ -92,7 +97,7 @@ template <int F>
 __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
     const int64_t n = (int64_t)a.nx * a.ny * a.nz;
     const int64_t v = blockIdx.x * (int64_t)IMG_BLOCK + threadIdx.x;
-    double val = 0.0;
+    double val = 0.0, pq = 0.0, qdq = 0.0;
     if (v < n) {
         const int ix = v % a.nx;
         const int iy = (v / a.nx) % a.ny;
@@ -165,7 +170,39 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
                 est = fmaf(a.n_sub, a.gi[v] - a.ghat_i[v], (float)a.ghat[v]) + bg;
             }
             if (F & R_EST_OUT) a.est_out[v] = est;
-            a.x_out[v] = fmaxf(0.f, fmaf(-a.tau * Dv, est, xi));
+            if (F & R_BB_DOT) {
+                // p = x - x_snap_prev, q = est - g_prev (both full gradients)
+                const double p = (double)xi - (double)a.x_snap[v];
+                const double q = (double)est - (double)a.g_prev[v];
+                pq = p * q;
+                qdq = q * q * (double)Dv;
+            }
+            if (F & (R_BB_STORE | R_BB_DOT)) a.g_prev[v] = est;
+            if (!(F & R_BB_DOT)) {
+                const float tau = a.tau_bb ? fminf(a.tau, (float)*a.tau_bb) : a.tau;
+                a.x_out[v] = fmaxf(0.f, fmaf(-tau * Dv, est, xi));
+            }
+        }
+    }
+    if (F & R_BB_DOT) {
+        __shared__ double red2[2][IMG_BLOCK / 64];
+        for (int off = 32; off > 0; off >>= 1) {
+            pq += __shfl_down(pq, off, 64);
+            qdq += __shfl_down(qdq, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red2[0][threadIdx.x >> 6] = pq;
+            red2[1][threadIdx.x >> 6] = qdq;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int w = 0; w < IMG_BLOCK / 64; ++w) {
+                s0 += red2[0][w];
+                s1 += red2[1][w];
+            }
+            a.partial[blockIdx.x] = s0;
+            a.partial[gridDim.x + blockIdx.x] = s1;
         }
     }
     if (F & R_VALUE) {
@@ -220,6 +257,76 @@ __global__ void k_saga_table_prior(float *__restrict__ table, double *__restrict
             sum += (double)t;
         }
         table_sum[v] = sum;
+    }
+}
+
+// Short Barzilai-Borwein step from the block partials of p.q and q.D q:
+// bb = {p.q, q.D q, tau_bb, number of updates}; tau_bb is kept when either
+// dot is not positive.
+__global__ void __launch_bounds__(1024) k_bb_finish(const double *__restrict__ partial, int nb, double *__restrict__ bb) {
+    __shared__ double red[2][1024 / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 1024) {
+        s0 += partial[i];
+        s1 += partial[nb + i];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_down(s0, off, 64);
+        s1 += __shfl_down(s1, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s0;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double pq = 0.0, qdq = 0.0;
+        for (int w = 0; w < 1024 / 64; ++w) {
+            pq += red[0][w];
+            qdq += red[1][w];
+        }
+        bb[0] = pq;
+        bb[1] = qdq;
+        if (pq > 0.0 && qdq > 0.0) bb[2] = pq / qdq;
+        bb[3] += 1.0;
+    }
+}
+
+__global__ void k_bb_init(double *bb) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        bb[0] = 0.0;
+        bb[1] = 0.0;
+        bb[2] = __builtin_inf();
+        bb[3] = 0.0;
+    }
+}
+
+// Step along a stored estimator: x_out = max(0, x - min(tau, tau_bb) D est).
+__global__ void k_step_stored(const float *__restrict__ x, const float *__restrict__ D, const float *__restrict__ est,
+                              float tau, const double *__restrict__ tau_bb, float *__restrict__ x_out, int64_t n) {
+    const float t = tau_bb ? fminf(tau, (float)*tau_bb) : tau;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        x_out[v] = fmaxf(0.f, fmaf(-t * D[v], est[v], x[v]));
+}
+
+// ||grad J_i(xhat)|| for every subset: the data-only snapshot gradient plus
+// the subset's prior share, one workgroup per subset (FP64 sum of squares).
+__global__ void __launch_bounds__(1024) k_subset_norms(const float *__restrict__ ghat_i, const float *__restrict__ bgrad,
+                                                       int n_sub, int64_t nv, double *__restrict__ out) {
+    __shared__ double red[1024 / 64];
+    const int i = blockIdx.x;
+    double s = 0.0;
+    for (int64_t v = threadIdx.x; v < nv; v += 1024) {
+        const double t = (double)ghat_i[(size_t)i * nv + v] + (double)bgrad[v] / (double)n_sub;
+        s += t * t;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 1024 / 64; ++w) t += red[w];
+        out[i] = sqrt(t);
     }
 }
 
@@ -366,6 +473,88 @@ hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *ka
         case 6: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
         default: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT | R_EST_OUT>(a, g->n_vox, s);
     }
+}
+
+// SVRG iteration with the ALG2/ALG3 extensions: estimator weight `w` of the
+// sampled subset (n for uniform sampling), the step bound tau_bb (device,
+// nullable) and, at a snapshot, the BB bookkeeping (bb_mode 1: keep the full
+// gradient in g_prev; 2: also the dots into g->partial, no step) and the
+// prior gradient into grad_out (nullable; for the subset-gradient norms).
+hipError_t launch_svrg_step_ex(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
+                               float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
+                               float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
+                               float w, float tau, const double *tau_bb, int bb_mode, const float *x_snap,
+                               float *g_prev, float *grad_out, float *x_out, hipStream_t s) {
+    RdpArgs a{};
+    a.x = x;
+    a.kappa = kappa;
+    for (int i = 0; i < 27; ++i) a.w.w[i] = w27[i];
+    a.beta = beta;
+    a.gamma = gamma;
+    a.eps = eps;
+    a.nx = g->d.nx;
+    a.ny = g->d.ny;
+    a.nz = g->d.nz;
+    a.sens = sens;
+    a.alpha = alpha;
+    a.delta = delta;
+    a.D = D;
+    a.gi = gi;
+    a.ghat_i = ghat_i;
+    a.ghat = ghat;
+    a.n_sub = w;
+    a.tau = tau;
+    a.tau_bb = tau_bb;
+    a.x_out = x_out;
+    a.x_snap = x_snap;
+    a.g_prev = g_prev;
+    a.grad = grad_out;
+    a.partial = g->partial;
+    const int64_t n = g->n_vox;
+    if (!snapshot) {
+        return update_pc ? rdp_launch<R_PRECOND | R_UPDATE>(a, n, s) : rdp_launch<R_UPDATE>(a, n, s);
+    }
+    constexpr int B = R_UPDATE | R_SNAPSHOT;
+    const int code = (update_pc ? 1 : 0) | (grad_out ? 2 : 0) | (bb_mode << 2);
+    switch (code) {
+        case 0: return rdp_launch<B>(a, n, s);
+        case 1: return rdp_launch<B | R_PRECOND>(a, n, s);
+        case 2: return rdp_launch<B | R_GRAD_OUT>(a, n, s);
+        case 3: return rdp_launch<B | R_PRECOND | R_GRAD_OUT>(a, n, s);
+        case 4: return rdp_launch<B | R_BB_STORE>(a, n, s);
+        case 5: return rdp_launch<B | R_BB_STORE | R_PRECOND>(a, n, s);
+        case 6: return rdp_launch<B | R_BB_STORE | R_GRAD_OUT>(a, n, s);
+        case 7: return rdp_launch<B | R_BB_STORE | R_PRECOND | R_GRAD_OUT>(a, n, s);
+        case 8: return rdp_launch<B | R_BB_DOT>(a, n, s);
+        case 9: return rdp_launch<B | R_BB_DOT | R_PRECOND>(a, n, s);
+        case 10: return rdp_launch<B | R_BB_DOT | R_GRAD_OUT>(a, n, s);
+        case 11: return rdp_launch<B | R_BB_DOT | R_PRECOND | R_GRAD_OUT>(a, n, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bb_finish(const pet_geom_s *g, double *bb, hipStream_t s) {
+    hipLaunchKernelGGL(k_bb_finish, dim3(1), dim3(1024), 0, s, g->partial, rdp_blocks(g), bb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bb_init(double *bb, hipStream_t s) {
+    hipLaunchKernelGGL(k_bb_init, dim3(1), dim3(64), 0, s, bb);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_stored(const pet_geom_s *g, const float *x, const float *D, const float *est, float tau,
+                              const double *tau_bb, float *x_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_stored, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, D, est, tau, tau_bb, x_out,
+                       g->n_vox);
+    return hipGetLastError();
+}
+
+hipError_t launch_subset_norms(const pet_geom_s *g, const float *ghat_i, const float *bgrad, double *out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_subset_norms, dim3(g->d.n_subsets), dim3(1024), 0, s, ghat_i, bgrad, g->d.n_subsets,
+                       g->n_vox, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_saga_table_prior(const pet_geom_s *g, float *table, double *table_sum, const float *bgrad,

@@ -21,6 +21,7 @@ constexpr int PADZ = 2;
 constexpr int NT_MAX = 16;     // TOF bins supported
 constexpr int NINT_MAX = 2 * NT_MAX + 1;
 constexpr int NT_BLOCK = 768;   // non-TOF line kernel: threads per workgroup
+constexpr int IMG_BLOCK = 256;  // image-space kernels: threads per workgroup
 constexpr int TOF_MAX_WAVES = 16;  // TOF line kernel: at most 16 segment waves
 constexpr int WS_MAX = 8;       // TOF bins overlapping one point
 constexpr int CUTS_PAD = 36;    // per-wave TOF interval cut indices (>= NINT_MAX + 1, multiple of 4)
@@ -183,6 +184,17 @@ hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *ka
                             float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
                             float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
                             float n_sub, float tau, float *x_out, float *est_out, hipStream_t s);
+hipError_t launch_svrg_step_ex(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
+                               float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
+                               float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
+                               float w, float tau, const double *tau_bb, int bb_mode, const float *x_snap,
+                               float *g_prev, float *grad_out, float *x_out, hipStream_t s);
+hipError_t launch_bb_finish(const pet_geom_s *g, double *bb, hipStream_t s);
+hipError_t launch_bb_init(double *bb, hipStream_t s);
+hipError_t launch_step_stored(const pet_geom_s *g, const float *x, const float *D, const float *est, float tau,
+                              const double *tau_bb, float *x_out, hipStream_t s);
+hipError_t launch_subset_norms(const pet_geom_s *g, const float *ghat_i, const float *bgrad, double *out,
+                               hipStream_t s);
 enum SgmEstimator { SGM_SAGA = 1, SGM_SGD = 2 };
 hipError_t launch_saga_table_prior(const pet_geom_s *g, float *table, double *table_sum, const float *bgrad,
                                   hipStream_t s);

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import projector, rdp, recon
+from oracle import projector, rdp, recon, schedules
 from synth import configs, data
 
 pytestmark = pytest.mark.gpu
@@ -241,4 +241,95 @@ def test_saga_sgd_reconstruction_parity(case, algo):
     x_gpu, x_orc = _svrg_pair(case, epochs, algo)
     err = _rel(x_gpu, x_orc)
     print(f"[{case.cfg['name']}] {algo} {epochs} epochs: relative L2 {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
+def _gpu_start(case, bb=False, gnorm=False):
+    pm = case.pm
+    cfg, n = case.cfg, case.cfg["n_subsets"]
+    beta = configs.beta_value(cfg)
+    x = torch.ones(case.geom.n_vox, device=case.dev)
+    xmax = torch.zeros(1, device=case.dev)
+    pm.pet_osem_epoch(case.geom, x, case.y, case.r, case.a, list(range(n)), xmax)
+    mx = float(xmax.cpu())
+    sens = torch.empty(case.geom.n_vox, device=case.dev)
+    pm.pet_back(case.geom, -1, None, case.a, sens)
+    st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=beta, gamma=2.0, eps=1e-3 * mx,
+                             alpha=1.0, delta=1e-3 * mx, bb=bb, gnorm=gnorm)
+    x0 = recon.osem_epoch(case.prob, np.ones(case.prob.shape))
+    m0 = float(x0.max())
+    prob = recon.Problem(cfg, case.d["y"], case.d["r"], case.d["mult"], beta=beta, gamma=2.0, eps=1e-3 * m0,
+                         alpha=1.0, delta=1e-3 * m0)
+    return x, st, x0, prob
+
+
+def test_alg2_bb_parity(case):
+    # ALG2: preconditioner updates at the start of epochs 1, 2, 4, 6; short BB
+    # step at the end of epochs 2 and 4 (snapshots), capped by the schedule
+    pm = case.pm
+    cfg, n = case.cfg, case.cfg["n_subsets"]
+    epochs = 6
+    x, st, x0, prob = _gpu_start(case, bb=True)
+    orders = data.subset_orders(cfg, epochs)
+    upd = {0, n, 3 * n, 5 * n}
+    bb_it = {2 * n, 4 * n}
+    cap = lambda k: schedules.alg2_cap(k, n)  # noqa: E731
+    x_end = {}
+    for e in range(epochs):
+        ks = [e * n + j for j in range(n)]
+        pm.pet_svrg_epoch(case.geom, st, x, orders[e], [cap(k) for k in ks], [k in upd for k in ks],
+                          bb_update=[k in bb_it for k in ks])
+        x_end[(e + 1) * n] = x.cpu().double().numpy().reshape(prob.shape)
+    rec = []
+    x_orc = recon.svrg(prob, x0, epochs, recon.order_rule(orders), cap, upd, bb_iters=bb_it, record=rec)
+    bbs = [r for r in rec if r[0] == "bb"]
+    assert [r[1] for r in bbs] == sorted(bb_it)
+    bb_gpu = st.bb.cpu().numpy()
+    assert bb_gpu[3] == len(bb_it)
+    # the short BB step of the GPU's own snapshots (k = 2n, 4n) with the
+    # preconditioner of its last update (k = 3n), in FP64
+    xa, xb = x_end[2 * n], x_end[4 * n]
+    D = recon.precond_harmonic(x_end[3 * n], prob.sens(), prob.prior_hessdiag(x_end[3 * n]), prob.alpha, prob.delta)
+    p = xb - xa
+    q = prob.full_grad(xb) - prob.full_grad(xa)
+    tau_ref = float(np.sum(p * q) / np.sum(q * D * q))
+    print(f"[{cfg['name']}] tau_bb gpu {bb_gpu[2]:.7g}, of the gpu snapshots {tau_ref:.7g}, "
+          f"oracle run {bbs[-1][4]:.7g}", flush=True)
+    assert bb_gpu[2] == pytest.approx(tau_ref, rel=1e-4)
+    err = _rel(x.cpu().double().numpy(), x_orc.ravel())
+    print(f"[{cfg['name']}] ALG2 {epochs} epochs: relative L2 {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
+def test_importance_sampling_parity(case):
+    pm = case.pm
+    cfg, n = case.cfg, case.cfg["n_subsets"]
+    epochs = 4
+    x, st, x0, prob = _gpu_start(case, gnorm=True)
+    u = np.random.default_rng(11).random(epochs * n)
+    rec = []
+    x_orc = recon.svrg(prob, x0, epochs, None, recon.stepsize_vanishing(1.0, 0.02, n), recon.pc_update_iters(n),
+                       importance_u=u, record=rec)
+    draws = {r[1]: (r[2], r[3]) for r in rec if r[0] == "sample"}
+    snaps = {r[1]: r[2] for r in rec if r[0] == "snapshot"}
+    tau_rule = recon.stepsize_vanishing(1.0, 0.02, n)
+    upd = recon.pc_update_iters(n)
+    for e in range(epochs):
+        ks = [e * n + j for j in range(n)]
+        seq = [draws[k][0] if k in draws else 0 for k in ks]
+        w = [draws[k][1] if k in draws else float(n) for k in ks]
+        pm.pet_svrg_epoch(case.geom, st, x, seq, [tau_rule(k) for k in ks], [k in upd for k in ks], weight=w)
+        if e * n in snaps:
+            got = st.gnorm.cpu().numpy()
+            ref = np.asarray(snaps[e * n])
+            assert np.max(np.abs(got - ref) / ref) <= 1e-5
+            # the GPU norms give the same draws, except for a uniform within
+            # rounding of a boundary of the cumulative distribution
+            pr = recon.importance_probabilities(list(got))
+            c = np.cumsum(recon.importance_probabilities(list(ref)))
+            for k in range(e * n + 1, min(e * n + 2 * n, epochs * n)):
+                if np.min(np.abs(c - u[k])) > 1e-4:
+                    assert recon.sample_inverse_cdf(pr, u[k]) == draws[k][0]
+    err = _rel(x.cpu().double().numpy(), x_orc.ravel())
+    print(f"[{cfg['name']}] importance-sampled SVRG {epochs} epochs: relative L2 {err:.2e}", flush=True)
     assert err <= 1e-4
