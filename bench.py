@@ -128,8 +128,9 @@ def map_reference(cfg, geom, pm, y, r, a, sens, beta, eps, delta, x0, max_iter):
 
 
 def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_host, mask_np, level):
-    """Wall time to NRMSE < 1% of the converged MAP image x*, for each
-    estimator in `epochs` (name -> epoch function; the first is the headline).
+    """Wall time to NRMSE < 1% of the converged MAP image x*, for each run in
+    `epochs` (name -> (geometry, epoch function, BB state needed); the first
+    is the headline).
 
     Each reconstruction is fresh and timed from the first device call after the
     data upload (sensitivity, one OSEM epoch, epochs of the estimator); the NRMSE
@@ -156,7 +157,8 @@ def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_hos
         return float(torch.sqrt((dlt * dlt).sum() / nm)) / level
 
     out = {}
-    for name, epoch in epochs.items():
+    for name, (geom_run, epoch, bb) in epochs.items():
+        n_run = geom_run.n_subsets
         x1 = torch.empty(geom.n_vox, device=dev)
         xmax = torch.zeros(1, device=dev)
         sens = torch.empty(geom.n_vox, device=dev)
@@ -165,10 +167,10 @@ def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_hos
         t_epochs = 0.0
         t0 = time.perf_counter()
         x1.fill_(1.0)
-        pm.pet_back(geom, -1, None, a, sens)
-        pm.pet_osem_epoch(geom, x1, y, r, a, list(range(n)), xmax)
-        st1 = pm.SvrgStateBuffers(geom, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0,
-                                  delta=delta)
+        pm.pet_back(geom_run, -1, None, a, sens)
+        pm.pet_osem_epoch(geom_run, x1, y, r, a, list(range(n_run)), xmax)
+        st1 = pm.SvrgStateBuffers(geom_run, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0,
+                                  delta=delta, bb=bb)
         torch.cuda.synchronize()
         t_clock += time.perf_counter() - t0
         trace = [nrmse_of(x1)]
@@ -187,6 +189,7 @@ def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_hos
         log(f"[bench] {name}: NRMSE after OSEM and each epoch: {['%.4f' % v for v in trace]}")
         out[name] = {"seconds": t_clock if reached else None, "epochs": reached, "threshold": 0.01,
                      "epochs_per_s": (len(trace) - 1) / t_epochs,
+                     "subsets": n_run,
                      "includes": f"sensitivity backprojection, 1 OSEM epoch, {name.upper()} epochs "
                                  "(NRMSE evaluation excluded)",
                      "nrmse_per_epoch": [round(v, 5) for v in trace]}
@@ -364,7 +367,7 @@ def main():
                     help="L-BFGS-B iterations (at most) of the converged reference image for the NRMSE")
     ap.add_argument("--nrmse-max-epochs", type=int, default=200)
     ap.add_argument("--no-estimators", action="store_true",
-                    help="time to NRMSE for SVRG only (not SAGA and SGD)")
+                    help="time to NRMSE for SVRG only (not SAGA, SGD, ALG1, ALG2, ALG3)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable (unrolled) leg")
     ap.add_argument("--batched", action="store_true",
                     help="measure only the batched workload (24 reconstructions; prints its own JSON line)")
@@ -387,6 +390,7 @@ def main():
     import torch
 
     import paper_2506_04976_amd as pm
+    from paper_2506_04976_amd import schedules
     from synth import configs, data
 
     cfg = configs.get(args.config)
@@ -422,7 +426,7 @@ def main():
 
     def make_epoch(fn):
         # vanishing stepsize tau_k = 1 / (1 + 0.02 k / n) (Section 3) for every estimator
-        def epoch(e, st=st, x=x):
+        def epoch(e, st, x):
             ks = [e * n + j for j in range(n)]
             fn(geom, st, x, orders[e], [1.0 / (1.0 + 0.02 * k / n) for k in ks], [k in upd_iters for k in ks])
         return epoch
@@ -437,7 +441,7 @@ def main():
         del src, dst
     log("[bench] OSEM done; warmup epochs ...")
     for e in range(args.warmup):
-        epoch(e)
+        epoch(e, st, x)
     torch.cuda.synchronize()
     pm.pet_profile_enable(geom, True)
     for kern in (pm.PET_KERNEL_GRAD,):
@@ -446,7 +450,7 @@ def main():
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for e in range(args.warmup, total):
-        epoch(e)
+        epoch(e, st, x)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     grad_ms, grad_launches = pm.pet_profile_read(geom, pm.PET_KERNEL_GRAD)
@@ -495,11 +499,28 @@ def main():
     estimators = None
     if not args.no_nrmse:
         del st
-        algos = {"svrg": epoch}
+        algos = {"svrg": (geom, epoch, False)}
+        extra_geoms = []
         if not args.no_estimators:
-            algos.update(saga=make_epoch(pm.pet_saga_epoch), sgd=make_epoch(pm.pet_sgd_epoch))
+            algos.update(saga=(geom, make_epoch(pm.pet_saga_epoch), False),
+                         sgd=(geom, make_epoch(pm.pet_sgd_epoch), False))
+            # the submitted algorithms, each with its own subset count
+            for alg, target in (("ALG1", 25.0), ("ALG2", 25.0), ("ALG3", 24.2)):
+                n_alg = schedules.subsets_for(cfg["n_views"], target)
+                g_alg = pm.Geometry(configs.get(cfg["name"], n_subsets=n_alg))
+                extra_geoms.append(g_alg)
+                plan = schedules.algorithm_plan(alg, n_alg, args.nrmse_max_epochs,
+                                                np.random.default_rng(data.seeds(cfg)[1]))
+
+                def alg_epoch(e, st, x, g_alg=g_alg, plan=plan):
+                    pe = plan[e]
+                    pm.pet_svrg_epoch(g_alg, st, x, pe["subset_seq"], pe["tau"], pe["update_pc"],
+                                      bb_update=pe["bb_update"])
+                algos[alg.lower()] = (g_alg, alg_epoch, alg != "ALG1")
         nrmse_all = time_to_nrmse(args, cfg, geom, pm, algos, y, r, a, beta, eps, delta, x0_host,
                                   nrmse_mask, nrmse_level)
+        for g_alg in extra_geoms:
+            g_alg.close()
         nrmse = nrmse_all.pop("svrg")
         estimators = nrmse_all or None
 
@@ -542,7 +563,7 @@ def main():
         "hbm_gbps_epoch": epoch_bytes * value / 1e9,
         "objective_final": objective,
         "time_to_nrmse": nrmse,
-        "time_to_nrmse_other_estimators": estimators,
+        "time_to_nrmse_other_algorithms": estimators,
         "differentiable": diff,
         "cpu_baseline": cpu,
     }

@@ -88,6 +88,13 @@ typedef struct {
     int n_tof;
     double tof_bin_mm, tof_sigma_mm, tof_nsigma;
     int n_subsets;
+    /* Image-space resolution model (Section 3.1): A = P G with G an isotropic
+     * Gaussian of this FWHM in mm (0: none).  G is separable, with sampled
+     * weights exp(-d^2 / (2 sigma_a^2)) over |d| <= floor(4 sigma_a + 1/2)
+     * voxels of axis a, normalised to sum 1, and zero outside the grid (so G
+     * is symmetric and A^T = G P^T); 2D grids (nz = 1) blur in x and y only.
+     * At most 16 voxels of radius. */
+    double psf_fwhm_mm;
 } pet_geom_desc;
 
 typedef struct pet_geom_s *pet_geom;
@@ -334,7 +341,9 @@ typedef struct pet_batch_s *pet_batch;
  * pet_svrg_epoch; their buffers and the images x[r] must stay alive, and the
  * geometries' scratch belongs to the batch while it runs) and images (device,
  * in/out).  Allocates gradient-sheet slots for every subset of every member,
- * the device schedule and a stream of its own.  At most 64 members. */
+ * the device schedule and a stream of its own.  At most 64 members;
+ * geometries with a resolution model (psf_fwhm_mm > 0) are refused
+ * (PET_E_ARG). */
 pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *const *states, float *const *x,
                             int n_members, pet_batch *out);
 pet_status pet_batch_destroy(pet_batch b);

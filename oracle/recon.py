@@ -10,7 +10,7 @@ v = i, i + n, i + 2n, ... (Section 2.4).
 import numpy as np
 
 from synth import configs
-from . import poisson, projector, rdp
+from . import poisson, projector, psf, rdp
 
 
 class Problem:
@@ -41,12 +41,14 @@ class Problem:
 
     # --- data term -------------------------------------------------------
     def fwd(self, x, i):
+        """P_i G x (G: the resolution model, the identity without one)."""
         p1, p2 = self.lors[i]
-        return projector.fwd(self.cfg, x, p1, p2)
+        return projector.fwd(self.cfg, psf.blur(np.asarray(x, np.float64).reshape(self.shape), self.cfg), p1, p2)
 
     def back(self, s, i):
+        """G P_i^T s."""
         p1, p2 = self.lors[i]
-        return projector.back(self.cfg, s, p1, p2)
+        return psf.blur(projector.back(self.cfg, s, p1, p2), self.cfg)
 
     def ybar(self, x, i):
         """Expected data A_i x + r_i of subset i, [N_i, T]."""

@@ -47,7 +47,8 @@ class GeomDesc(ctypes.Structure):
                 ("n_crystals", ctypes.c_int), ("n_rings", ctypes.c_int), ("ring_pitch_mm", ctypes.c_double),
                 ("max_ring_diff", ctypes.c_int), ("rad_spacing_mm", ctypes.c_double),
                 ("half_length_mm", ctypes.c_double), ("n_tof", ctypes.c_int), ("tof_bin_mm", ctypes.c_double),
-                ("tof_sigma_mm", ctypes.c_double), ("tof_nsigma", ctypes.c_double), ("n_subsets", ctypes.c_int)]
+                ("tof_sigma_mm", ctypes.c_double), ("tof_nsigma", ctypes.c_double), ("n_subsets", ctypes.c_int),
+                ("psf_fwhm_mm", ctypes.c_double)]
 
 
 class SvrgState(ctypes.Structure):
@@ -175,6 +176,7 @@ def desc_from_config(cfg):
     d.tof_bin_mm = float(cfg.get("tof_bin", 0.0))
     d.tof_sigma_mm = float(cfg.get("tof_sigma", 0.0))
     d.tof_nsigma = float(cfg.get("tof_nsigma", 0.0))
+    d.psf_fwhm_mm = float(cfg.get("psf_fwhm", 0.0))
     return d
 
 

@@ -133,6 +133,8 @@ extern "C" pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *co
         for (int q = 0; q < r; ++q)
             if (geoms[q] == geoms[r]) return fail(PET_E_ARG, "pet_batch_create: members need distinct geometries");
         if (geoms[r]->device != geoms[0]->device) return fail(PET_E_ARG, "pet_batch_create: members on one device");
+        if (geoms[r]->psf_passes)
+            return fail(PET_E_ARG, "pet_batch_create: geometries with a resolution model are not batched");
     }
     pet_batch_s *b = new (std::nothrow) pet_batch_s();
     if (!b) return fail(PET_E_OOM, "pet_batch_create: host allocation");

@@ -61,7 +61,25 @@ pet_status validate(const pet_geom_desc &d) {
         if (!(d.rad_spacing_mm > 0) || !(d.half_length_mm > 0))
             return fail(PET_E_ARG, "pet_geom_create: parallel-beam needs rad_spacing_mm, half_length_mm > 0");
     }
+    if (!(d.psf_fwhm_mm >= 0) || !std::isfinite(d.psf_fwhm_mm))
+        return fail(PET_E_ARG, "pet_geom_create: psf_fwhm_mm must be finite and >= 0");
     return PET_OK;
+}
+
+// Separable Gaussian of the resolution model, one axis: sigma in voxels,
+// radius floor(4 sigma + 1/2), weights normalised to sum 1 over -r..r.
+bool make_psf_axis(double sigma_vox, int axis, PsfAxis &k) {
+    const int r = (int)(4.0 * sigma_vox + 0.5);
+    if (r > PSF_RMAX) return false;
+    double w[PSF_RMAX + 1], sum = 0.0;
+    for (int i = 0; i <= r; ++i) {
+        w[i] = std::exp(-0.5 * (double)i * i / (sigma_vox * sigma_vox));
+        sum += i == 0 ? w[i] : 2.0 * w[i];
+    }
+    k.r = r;
+    k.axis = axis;
+    for (int i = 0; i <= PSF_RMAX; ++i) k.w[i] = i <= r ? (float)(w[i] / sum) : 0.f;
+    return true;
 }
 
 }  // namespace
@@ -75,6 +93,16 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     pet_geom_s *g = new (std::nothrow) pet_geom_s();
     if (!g) return fail(PET_E_OOM, "pet_geom_create: host allocation failed");
     g->d = d;
+    if (d.psf_fwhm_mm > 0) {
+        const double sig = d.psf_fwhm_mm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        const double vox[3] = {d.vx, d.vy, d.vz};
+        g->psf_passes = d.nz > 1 ? 3 : 2;
+        for (int a = 0; a < g->psf_passes; ++a)
+            if (!make_psf_axis(sig / vox[a], a, g->psf[a])) {
+                delete g;
+                return fail(PET_E_ARG, "pet_geom_create: resolution kernel wider than 16 voxels");
+            }
+    }
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
         return fail(PET_E_HIP, "pet_geom_create: no HIP device");
@@ -296,6 +324,8 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
               alloc((void **)&g->num, sizeof(float) * g->n_vox) && alloc((void **)&g->sensi, sizeof(float) * g->n_vox) &&
               alloc((void **)&g->partial, sizeof(double) * g->n_partial) && alloc((void **)&g->dscratch, sizeof(double) * 16) &&
               alloc((void **)&g->fscratch, sizeof(float) * 16);
+    if (ok && g->psf_passes)
+        ok = alloc((void **)&g->psf_a, sizeof(float) * g->n_vox) && alloc((void **)&g->psf_b, sizeof(float) * g->n_vox);
     if (!ok) {
         pet_geom_destroy(g);
         return fail(PET_E_OOM, "pet_geom_create: device allocation failed");
@@ -326,7 +356,7 @@ extern "C" pet_status pet_geom_destroy(pet_geom g) {
         hipEventDestroy(e.second);
     }
     void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
-                    g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch};
+                    g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch, g->psf_a, g->psf_b};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete g;

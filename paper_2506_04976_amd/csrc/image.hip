@@ -260,6 +260,32 @@ __global__ void k_saga_table_prior(float *__restrict__ table, double *__restrict
     }
 }
 
+// One axis of the resolution model: out (+)= sum_{|d| <= r} w[|d|] in[v + d e_axis]
+// with zero outside the grid (Section 3.1: image-space Gaussian).
+__global__ void __launch_bounds__(IMG_BLOCK) k_psf_axis(const float *__restrict__ in, float *__restrict__ out, int nx,
+                                                       int ny, int nz, PsfAxis k, int accumulate) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t stride = k.axis == 0 ? 1 : (k.axis == 1 ? nx : (int64_t)nx * ny);
+    const int len = k.axis == 0 ? nx : (k.axis == 1 ? ny : nz);
+    for (int64_t v = blockIdx.x * (int64_t)IMG_BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * IMG_BLOCK) {
+        const int c = (int)((v / stride) % len);
+        const int lo = -min(c, k.r), hi = min(len - 1 - c, k.r);
+        float acc = 0.f;
+        for (int d = lo; d <= hi; ++d) acc = fmaf(k.w[d < 0 ? -d : d], in[v + d * stride], acc);
+        out[v] = accumulate ? out[v] + acc : acc;
+    }
+}
+
+// x -> FP64 running sum of subset gradients (snapshot with a resolution model)
+__global__ void k_accum_image(const float *__restrict__ img, double *__restrict__ ghat, float *__restrict__ gcopy,
+                              int64_t n, int first) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const float s = img[v];
+        if (gcopy) gcopy[v] = s;
+        ghat[v] = first ? (double)s : ghat[v] + (double)s;
+    }
+}
+
 // Short Barzilai-Borwein step from the block partials of p.q and q.D q:
 // bb = {p.q, q.D q, tau_bb, number of updates}; tau_bb is kept when either
 // dot is not positive.
@@ -383,8 +409,33 @@ hipError_t rdp_launch(const RdpArgs &a, int64_t n, hipStream_t s) {
 
 }  // namespace
 
+// G in -> out through the work buffers psf_a / psf_b: pass p reads `in` (p = 0)
+// or the previous pass's buffer and writes buffer p % 2, the last pass writes
+// `out` (accumulating if asked).  `in` may be psf_b; `out` must not be the
+// buffer the last pass reads (psf_b for three passes, psf_a for two).
+hipError_t launch_psf(const pet_geom_s *g, const float *in, float *out, int accumulate, hipStream_t s) {
+    if (!g->psf_passes) return hipErrorInvalidValue;
+    float *buf[2] = {g->psf_a, g->psf_b};
+    for (int p = 0; p < g->psf_passes; ++p) {
+        const float *src = p == 0 ? in : buf[(p - 1) % 2];
+        const bool last = p == g->psf_passes - 1;
+        float *dst = last ? out : buf[p % 2];
+        hipLaunchKernelGGL(k_psf_axis, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, src, dst, g->d.nx, g->d.ny,
+                           g->d.nz, g->psf[p], last ? accumulate : 0);
+    }
+    return hipGetLastError();
+}
+
+// The line kernels read x (or G x with a resolution model) through the sheets.
 hipError_t launch_to_sheets(const pet_geom_s *g, const float *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, g->T0, g->T1, g->d.nx, g->d.ny,
+    const float *src = x;
+    if (g->psf_passes) {
+        float *gx = g->psf_passes == 3 ? g->psf_a : g->psf_b;
+        const hipError_t e = launch_psf(g, x, gx, 0, s);
+        if (e != hipSuccess) return e;
+        src = gx;
+    }
+    hipLaunchKernelGGL(k_to_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, src, g->T0, g->T1, g->d.nx, g->d.ny,
                        g->d.nz, g->d.nz + 2 * PADZ);
     return hipGetLastError();
 }
@@ -395,7 +446,14 @@ hipError_t launch_zero_sheets(const pet_geom_s *g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Gradient sheets -> image (then G^T = G with a resolution model).
 hipError_t launch_from_sheets(const pet_geom_s *g, float *out, int accumulate, hipStream_t s) {
+    if (g->psf_passes) {
+        hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, g->psf_b, g->d.nx,
+                           g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, 0);
+        const hipError_t e = hipGetLastError();
+        return e != hipSuccess ? e : launch_psf(g, g->psf_b, out, accumulate, s);
+    }
     hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, out, g->d.nx, g->d.ny,
                        g->d.nz, g->d.nz + 2 * PADZ, accumulate);
     return hipGetLastError();
@@ -601,6 +659,13 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
 
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
                                  hipStream_t s) {
+    if (g->psf_passes) {
+        hipError_t e = launch_from_sheets(g, ghat_i, 0, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_accum_image, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, ghat_i, ghat, gcopy, g->n_vox,
+                           first);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_snapshot_accum, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, ghat_i, ghat, gcopy,
                        g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first);
     return hipGetLastError();

@@ -120,8 +120,22 @@ struct BMember {
 
 }  // namespace pet
 
+namespace pet {
+constexpr int PSF_RMAX = 16;  // resolution model: kernel radius limit (voxels)
+// One axis of the separable resolution kernel: weights w[0..r] of offsets 0..r
+// (symmetric), and the axis (0 = x, 1 = y, 2 = z).
+struct PsfAxis {
+    int r, axis;
+    float w[PSF_RMAX + 1];
+};
+}  // namespace pet
+
 struct pet_geom_s {
     pet_geom_desc d;
+    // resolution model: passes (x, y[, z]) and two image-sized work buffers
+    int psf_passes = 0;
+    pet::PsfAxis psf[3]{};
+    float *psf_a = nullptr, *psf_b = nullptr;
     int device;
     int n_planes;
     int64_t n_vox;
@@ -204,6 +218,8 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
                            float n_sub, float tau, float *x_out, hipStream_t s);
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
                                  hipStream_t s);
+// resolution model G (no-op pass-through when the geometry has none)
+hipError_t launch_psf(const pet_geom_s *g, const float *in, float *out, int accumulate, hipStream_t s);
 int rdp_blocks(const pet_geom_s *g);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_fill(float *dst, int64_t n, float val, hipStream_t s);

@@ -100,6 +100,11 @@ CONFIGS = {
     ),
 }
 
+# Test geometries with the image-space resolution model (Section 3.1): a
+# Gaussian of 6 mm FWHM on ~4 mm voxels (kernel radius 3 voxels in x and y).
+CONFIGS["mini_tof_psf"] = dict(CONFIGS["mini_tof"], name="mini_tof_psf", psf_fwhm=6.0)
+CONFIGS["mini_2d_psf"] = dict(CONFIGS["mini_2d"], name="mini_2d_psf", psf_fwhm=6.0)
+
 
 MID_PITCH = 48 * 2.03 / 43  # 43 rings spanning the 48-slice image
 

@@ -16,12 +16,12 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import projector, rdp, recon, schedules
+from oracle import projector, psf, rdp, recon, schedules
 from synth import configs, data
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["mini_tof", "mini_nontof", "mini_2d", "c0_2d"]
+CASES = ["mini_tof", "mini_nontof", "mini_2d", "c0_2d", "mini_tof_psf", "mini_2d_psf"]
 
 
 def _rel(a, b):
@@ -68,7 +68,7 @@ def test_fwd_parity(case):
         got = out.cpu().numpy().reshape(case.shape4)
         views = case.views(subset)
         p1, p2 = projector.view_lors(case.cfg, views)
-        ref = (projector.fwd(case.cfg, case.x_np, p1, p2) * case.d["mult"][views].reshape(-1, 1) +
+        ref = (projector.fwd(case.cfg, psf.blur(case.x_np, case.cfg), p1, p2) * case.d["mult"][views].reshape(-1, 1) +
                case.d["r"][views].reshape(-1, case.T)).reshape(len(views), *case.shape4[1:])
         g = got[views]
         assert _rel(g, ref) <= 1e-5
@@ -79,7 +79,7 @@ def test_fwd_parity(case):
     out = torch.empty(case.geom.n_bins, device=case.dev)
     pm.pet_fwd(case.geom, -1, case.x, None, None, out)
     p1, p2 = projector.view_lors(case.cfg, case.views(-1))
-    ref = projector.fwd(case.cfg, case.x_np, p1, p2).ravel()
+    ref = projector.fwd(case.cfg, psf.blur(case.x_np, case.cfg), p1, p2).ravel()
     assert _rel(out.cpu().numpy(), ref) <= 1e-5
 
 
@@ -94,7 +94,7 @@ def test_back_parity(case):
         views = case.views(subset)
         p1, p2 = projector.view_lors(case.cfg, views)
         s_sub = sino.reshape(case.shape4)[views].reshape(-1, case.T) * case.d["mult"][views].reshape(-1, 1)
-        ref = projector.back(case.cfg, s_sub, p1, p2).ravel()
+        ref = psf.blur(projector.back(case.cfg, s_sub, p1, p2), case.cfg).ravel()
         assert _rel(out.cpu().numpy(), ref) <= 1e-5
     # sensitivity (sino = NULL) and accumulate
     sens = torch.empty(case.geom.n_vox, device=case.dev)
