@@ -74,6 +74,8 @@ enum { PET_Y_F32 = 0, PET_Y_U16 = 1, PET_Y_U8 = 2 };
  *   LOR (signed distance from the LOR centre towards the second endpoint);
  *   weight of a point at t: the Gaussian kernel (sigma tof_sigma) truncated to
  *   |t' - t| <= tof_nsigma sigma, integrated over the bin [t_b -/+ tof_bin/2].
+ *   At most 32 bins, and at most 8 of them may overlap one point's window
+ *   (PET_E_ARG otherwise); a TOF segment holds at most 64 planes.
  */
 typedef struct {
     int kind;

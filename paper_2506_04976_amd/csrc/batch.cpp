@@ -204,7 +204,7 @@ extern "C" pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *co
         size_t pw = 0;
         if (m.is_tof) {
             const int e1 = g->tof_ws > 4 ? g->tof_ws - 4 : 0;
-            pw = (((size_t)g->rows_max * (4 + e1) + CUTS_PAD + 3) & ~(size_t)3) * sizeof(float);
+            pw = (((size_t)g->rows_max * (4 + e1) + tof_cuts_pad(g->tof.n_int) + 3) & ~(size_t)3) * sizeof(float);
         }
         b->lds_per_wave.push_back(pw);
         b->tof_waves.push_back(m.tof_waves);

@@ -47,7 +47,7 @@ pet_status validate(const pet_geom_desc &d) {
     if (d.n_views < 1 || d.n_rad < 1) return fail(PET_E_ARG, "pet_geom_create: n_views and n_rad must be >= 1");
     if (d.n_subsets < 1 || d.n_subsets > d.n_views)
         return fail(PET_E_ARG, "pet_geom_create: need 1 <= n_subsets <= n_views");
-    if (d.n_tof < 1 || d.n_tof > NT_MAX) return fail(PET_E_ARG, "pet_geom_create: n_tof must be in [1, 16]");
+    if (d.n_tof < 1 || d.n_tof > NT_MAX) return fail(PET_E_ARG, "pet_geom_create: n_tof must be in [1, 32]");
     if (d.n_tof > 1 && (!(d.tof_bin_mm > 0) || !(d.tof_sigma_mm > 0) || !(d.tof_nsigma > 0)))
         return fail(PET_E_ARG, "pet_geom_create: TOF needs tof_bin_mm, tof_sigma_mm, tof_nsigma > 0");
     if (d.kind == PET_SCANNER_CYLINDER) {
@@ -292,7 +292,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     size_t need = 3 * sheet * sizeof(float);
     if (d.n_tof > 1) {
         int e1 = g->tof_ws > 4 ? g->tof_ws - 4 : 0;
-        size_t per_wave = (((size_t)rows_max * (4 + e1) + CUTS_PAD + 3) & ~(size_t)3) * sizeof(float);
+        size_t per_wave = (((size_t)rows_max * (4 + e1) + tof_cuts_pad(g->tof.n_int) + 3) & ~(size_t)3) * sizeof(float);
         if (need + per_wave <= (size_t)max_lds) {
             int fit = (int)(((size_t)max_lds - need) / per_wave);
             if (fit < g->tof_waves) g->tof_waves = fit;

@@ -18,13 +18,15 @@ namespace pet {
 // outside the grid (conservative sample ranges); padded zeros make them exact.
 constexpr int PADA = 2;
 constexpr int PADZ = 2;
-constexpr int NT_MAX = 16;     // TOF bins supported
-constexpr int NINT_MAX = 2 * NT_MAX + 1;
+constexpr int NT_MAX = 32;     // TOF bins supported
+constexpr int NT_BLK = 16;     // TOF bins a lane holds in registers at once
+constexpr int NINT_MAX = 2 * NT_MAX - 1;  // intervals between the 2 n_tof window edges
 constexpr int NT_BLOCK = 768;   // non-TOF line kernel: threads per workgroup
 constexpr int IMG_BLOCK = 256;  // image-space kernels: threads per workgroup
 constexpr int TOF_MAX_WAVES = 16;  // TOF line kernel: at most 16 segment waves
 constexpr int WS_MAX = 8;       // TOF bins overlapping one point
-constexpr int CUTS_PAD = 36;    // per-wave TOF interval cut indices (>= NINT_MAX + 1, multiple of 4)
+// per-wave TOF interval cut indices: n_int + 1 of them, padded to 4
+__host__ __device__ inline int tof_cuts_pad(int n_int) { return (n_int + 1 + 3) & ~3; }
 
 // One transaxial line (view, radial): sample i along the principal axis m sits
 // at lambda(i) = lam0 + i dlam on the LOR; its coordinate along the other

@@ -31,14 +31,14 @@ __device__ __forceinline__ float load_y(const void *y, int dt, int64_t idx) {
     return ((const float *)y)[idx];
 }
 
-// The nt values src[base .. base + nt) of one LOR, all loads issued before the
-// first use (zero above nt).
+// The nt values src[base .. base + nt) of one LOR (one block of at most
+// NT_BLK TOF bins), all loads issued before the first use (zero above nt).
 template <typename T>
-__device__ __forceinline__ void load_row(const T *src, int64_t base, int nt, float (&v)[NT_MAX]) {
+__device__ __forceinline__ void load_row(const T *src, int64_t base, int nt, float (&v)[NT_BLK]) {
 #pragma unroll
-    for (int b = 0; b < NT_MAX; ++b) v[b] = b < nt ? (float)src[base + b] : 0.f;
+    for (int b = 0; b < NT_BLK; ++b) v[b] = b < nt ? (float)src[base + b] : 0.f;
 }
-__device__ __forceinline__ void load_y_row(const void *y, int dt, int64_t base, int nt, float (&v)[NT_MAX]) {
+__device__ __forceinline__ void load_y_row(const void *y, int dt, int64_t base, int nt, float (&v)[NT_BLK]) {
     if (dt == PET_Y_U8)
         load_row((const uint8_t *)y, base, nt, v);
     else if (dt == PET_Y_U16)
@@ -407,43 +407,51 @@ __device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, dou
     }
 }
 
-// Bin window <-> per-bin accumulators. The first bin BF is a template
-// argument so that every register index is static: indexing a register array
-// by a run-time value compiles to indexed register moves, which the compiler
-// may execute speculatively for indices the source guards out and which then
-// write registers past the array.
-template <int BF>
-__device__ __forceinline__ void add_window(float (&acc)[NT_MAX], const float (&win)[WS_MAX], int na) {
+// Bin window <-> the per-bin accumulators of one block of NT_BLK bins.  The
+// window's first bin relative to the block, REL (from -(WS_MAX - 1) to
+// NT_BLK - 1), is a template argument so that every register index is static:
+// indexing a register array by a run-time value compiles to indexed register
+// moves, which the compiler may execute speculatively for indices the source
+// guards out and which then write registers past the array.
+template <int REL>
+__device__ __forceinline__ void add_window(float (&acc)[NT_BLK], const float (&win)[WS_MAX], int na) {
 #pragma unroll
     for (int j = 0; j < WS_MAX; ++j)
-        if (BF + j < NT_MAX && j < na) acc[BF + j] += win[j];
+        if (REL + j >= 0 && REL + j < NT_BLK && j < na) acc[REL + j] += win[j];
 }
 
-template <int BF>
-__device__ __forceinline__ void get_window(const float (&acc)[NT_MAX], float (&win)[WS_MAX], int na) {
+template <int REL>
+__device__ __forceinline__ void get_window(const float (&acc)[NT_BLK], float (&win)[WS_MAX], int na) {
 #pragma unroll
-    for (int j = 0; j < WS_MAX; ++j) win[j] = (BF + j < NT_MAX && j < na) ? acc[BF + j] : 0.f;
+    for (int j = 0; j < WS_MAX; ++j) win[j] = (REL + j >= 0 && REL + j < NT_BLK && j < na) ? acc[REL + j] : 0.f;
 }
 
-static_assert(NT_MAX == 16, "the first-bin switch below covers bins 0 .. 15");
-#define PET_BF_SWITCH(FN, ...)                \
-    switch (bf) {                             \
-        case 0: FN<0>(__VA_ARGS__); break;    \
-        case 1: FN<1>(__VA_ARGS__); break;    \
-        case 2: FN<2>(__VA_ARGS__); break;    \
-        case 3: FN<3>(__VA_ARGS__); break;    \
-        case 4: FN<4>(__VA_ARGS__); break;    \
-        case 5: FN<5>(__VA_ARGS__); break;    \
-        case 6: FN<6>(__VA_ARGS__); break;    \
-        case 7: FN<7>(__VA_ARGS__); break;    \
-        case 8: FN<8>(__VA_ARGS__); break;    \
-        case 9: FN<9>(__VA_ARGS__); break;    \
-        case 10: FN<10>(__VA_ARGS__); break;  \
-        case 11: FN<11>(__VA_ARGS__); break;  \
-        case 12: FN<12>(__VA_ARGS__); break;  \
-        case 13: FN<13>(__VA_ARGS__); break;  \
-        case 14: FN<14>(__VA_ARGS__); break;  \
-        default: FN<15>(__VA_ARGS__); break;  \
+static_assert(NT_BLK == 16 && WS_MAX == 8, "the window switch below covers first bins -7 .. 15 of a block");
+#define PET_REL_SWITCH(FN, ...)                \
+    switch (rel) {                             \
+        case -7: FN<-7>(__VA_ARGS__); break;   \
+        case -6: FN<-6>(__VA_ARGS__); break;   \
+        case -5: FN<-5>(__VA_ARGS__); break;   \
+        case -4: FN<-4>(__VA_ARGS__); break;   \
+        case -3: FN<-3>(__VA_ARGS__); break;   \
+        case -2: FN<-2>(__VA_ARGS__); break;   \
+        case -1: FN<-1>(__VA_ARGS__); break;   \
+        case 0: FN<0>(__VA_ARGS__); break;     \
+        case 1: FN<1>(__VA_ARGS__); break;     \
+        case 2: FN<2>(__VA_ARGS__); break;     \
+        case 3: FN<3>(__VA_ARGS__); break;     \
+        case 4: FN<4>(__VA_ARGS__); break;     \
+        case 5: FN<5>(__VA_ARGS__); break;     \
+        case 6: FN<6>(__VA_ARGS__); break;     \
+        case 7: FN<7>(__VA_ARGS__); break;     \
+        case 8: FN<8>(__VA_ARGS__); break;     \
+        case 9: FN<9>(__VA_ARGS__); break;     \
+        case 10: FN<10>(__VA_ARGS__); break;   \
+        case 11: FN<11>(__VA_ARGS__); break;   \
+        case 12: FN<12>(__VA_ARGS__); break;   \
+        case 13: FN<13>(__VA_ARGS__); break;   \
+        case 14: FN<14>(__VA_ARGS__); break;   \
+        default: FN<15>(__VA_ARGS__); break;   \
     }
 
 #define PET_NA_SWITCH(FN, ...)              \
@@ -478,7 +486,7 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     // LDS: X sheet (float) | Z sheet (double) | per wave: w4 [rows][4], w1 [rows][e1], cuts
     const int sheet = (a.rows_max * rz + 3) & ~3;
     const int e1 = a.ws > 4 ? a.ws - 4 : 0;
-    const int per_wave = a.rows_max * (4 + e1) + CUTS_PAD;
+    const int per_wave = a.rows_max * (4 + e1) + tof_cuts_pad(a.tof.n_int);
     float *X = smem;
     double *Z = reinterpret_cast<double *>(smem + (NEED_X ? sheet : 0));
     float *wave_mem = smem + (NEED_X ? sheet : 0) + (NEED_Z ? 2 * sheet : 0) + wave * ((per_wave + 3) & ~3);
@@ -538,80 +546,90 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                 qa = min(qa, __shfl_xor(qa, o, 64));
                 qb = max(qb, __shfl_xor(qb, o, 64));
             }
-            const bool live = nrow > 0 && na_l > 0 && max(cut, qa) < min(cut_next, qb + 1);
-            const uint64_t live_mask = __ballot(live);
-            float acc[NT_MAX];
-#pragma unroll
-            for (int b = 0; b < NT_MAX; ++b) acc[b] = 0.f;
+            const bool meets = nrow > 0 && na_l > 0 && max(cut, qa) < min(cut_next, qb + 1);
+            const float m = has ? (a.mult ? a.mult[lor] : 1.f) : 0.f;
+            const int64_t base = lor * nt;
 
-            // ---- forward projection ----
-            if (NEED_X) {
-                for (uint64_t m = live_mask; m; m &= m - 1) {
-                    const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
-                    const int na = __builtin_amdgcn_readlane(na_l, s);
-                    const int c0 = __builtin_amdgcn_readlane(cut, s);
-                    const int c1 = __builtin_amdgcn_readlane(cut_next, s);
-                    const int bf = __builtin_amdgcn_readlane(bf_l, s);
-                    float win[WS_MAX];
+            // TOF bins in blocks of NT_BLK held in registers (one block unless
+            // the geometry has more bins); an interval whose bins straddle two
+            // blocks is walked once per block
+            for (int b0 = 0; b0 < nt; b0 += NT_BLK) {
+                const int nb = min(NT_BLK, nt - b0);
+                const uint64_t live_mask = __ballot(meets && bf_l < b0 + NT_BLK && bf_l + na_l > b0);
+                float acc[NT_BLK];
 #pragma unroll
-                    for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
-                    const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
-                    PET_NA_SWITCH(tof_fwd_run, zAf, zBf, zmax, X + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
-                                  w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, win)
-                    PET_BF_SWITCH(add_window, acc, win, na)
+                for (int b = 0; b < NT_BLK; ++b) acc[b] = 0.f;
+
+                // ---- forward projection ----
+                if (NEED_X) {
+                    for (uint64_t mk = live_mask; mk; mk &= mk - 1) {
+                        const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mk));
+                        const int na = __builtin_amdgcn_readlane(na_l, s);
+                        const int c0 = __builtin_amdgcn_readlane(cut, s);
+                        const int c1 = __builtin_amdgcn_readlane(cut_next, s);
+                        const int rel = __builtin_amdgcn_readlane(bf_l, s) - b0;
+                        float win[WS_MAX];
+#pragma unroll
+                        for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
+                        const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                        PET_NA_SWITCH(tof_fwd_run, zAf, zBf, zmax, X + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
+                                      w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, win)
+                        PET_REL_SWITCH(add_window, acc, win, na)
+                    }
                 }
-            }
 
-            // ---- ratio / output ----
-            if (has) {
-                const float m = a.mult ? a.mult[lor] : 1.f;
-                const int64_t base = lor * nt;
-                if constexpr (MODE == M_BACK) {
-                    float sv[NT_MAX];
-                    if (a.sino) load_row(a.sino, base, nt, sv);
+                // ---- ratio / output ----
+                if (has) {
+                    const int64_t bb = base + b0;
+                    if constexpr (MODE == M_BACK) {
+                        float sv[NT_BLK];
+                        if (a.sino) load_row(a.sino, bb, nb, sv);
 #pragma unroll
-                    for (int b = 0; b < NT_MAX; ++b) acc[b] = (a.sino ? sv[b] : 1.f) * m * ell;
-                } else if constexpr (MODE == M_HVP) {
-                    float yb[NT_MAX], yv[NT_MAX];
-                    load_row(a.ybar, base, nt, yb);
-                    load_y_row(a.y, a.y_dtype, base, nt, yv);
+                        for (int b = 0; b < NT_BLK; ++b) acc[b] = (a.sino ? sv[b] : 1.f) * m * ell;
+                    } else if constexpr (MODE == M_HVP) {
+                        float yb[NT_BLK], yv[NT_BLK];
+                        load_row(a.ybar, bb, nb, yb);
+                        load_y_row(a.y, a.y_dtype, bb, nb, yv);
 #pragma unroll
-                    for (int b = 0; b < NT_MAX; ++b)
-                        acc[b] = (b < nt && yv[b] != 0.f) ? m * m * yv[b] / (yb[b] * yb[b]) * (acc[b] * ell) * ell : 0.f;
-                } else {
-                    float ad[NT_MAX], yv[NT_MAX];
+                        for (int b = 0; b < NT_BLK; ++b)
+                            acc[b] = (b < nb && yv[b] != 0.f) ? m * m * yv[b] / (yb[b] * yb[b]) * (acc[b] * ell) * ell
+                                                              : 0.f;
+                    } else {
+                        float ad[NT_BLK], yv[NT_BLK];
 #pragma unroll
-                    for (int b = 0; b < NT_MAX; ++b) ad[b] = 0.f;
-                    if (a.add) load_row(a.add, base, nt, ad);
-                    if constexpr (MODE != M_FWD) load_y_row(a.y, a.y_dtype, base, nt, yv);
+                        for (int b = 0; b < NT_BLK; ++b) ad[b] = 0.f;
+                        if (a.add) load_row(a.add, bb, nb, ad);
+                        if constexpr (MODE != M_FWD) load_y_row(a.y, a.y_dtype, bb, nb, yv);
 #pragma unroll
-                    for (int b = 0; b < NT_MAX; ++b) {
-                        if (b >= nt) continue;
-                        const float ybar = fmaf(m, acc[b] * ell, ad[b]);
-                        if constexpr (MODE == M_FWD) {
-                            a.out[base + b] = ybar;
-                        } else {
-                            if (a.partial) kl += kl_term(ybar, yv[b]);
-                            if constexpr (MODE == M_GRAD) acc[b] = m * fmaf(-yv[b], __builtin_amdgcn_rcpf(ybar), 1.f) * ell;
-                            if constexpr (MODE == M_EM) acc[b] = m * (yv[b] * __builtin_amdgcn_rcpf(ybar)) * ell;
+                        for (int b = 0; b < NT_BLK; ++b) {
+                            if (b >= nb) continue;
+                            const float ybar = fmaf(m, acc[b] * ell, ad[b]);
+                            if constexpr (MODE == M_FWD) {
+                                a.out[bb + b] = ybar;
+                            } else {
+                                if (a.partial) kl += kl_term(ybar, yv[b]);
+                                if constexpr (MODE == M_GRAD)
+                                    acc[b] = m * fmaf(-yv[b], __builtin_amdgcn_rcpf(ybar), 1.f) * ell;
+                                if constexpr (MODE == M_EM) acc[b] = m * (yv[b] * __builtin_amdgcn_rcpf(ybar)) * ell;
+                            }
                         }
                     }
                 }
-            }
 
-            // ---- adjoint into the LDS gradient sheet ----
-            if (NEED_Z) {
-                for (uint64_t m = live_mask; m; m &= m - 1) {
-                    const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
-                    const int na = __builtin_amdgcn_readlane(na_l, s);
-                    const int c0 = __builtin_amdgcn_readlane(cut, s);
-                    const int c1 = __builtin_amdgcn_readlane(cut_next, s);
-                    const int bf = __builtin_amdgcn_readlane(bf_l, s);
-                    float win[WS_MAX];
-                    PET_BF_SWITCH(get_window, acc, win, na)
-                    const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
-                    PET_NA_SWITCH(tof_back_run, zA, zB, zmax, Z + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
-                                  w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, c0 - qlo_b, span, win)
+                // ---- adjoint into the LDS gradient sheet ----
+                if (NEED_Z) {
+                    for (uint64_t mk = live_mask; mk; mk &= mk - 1) {
+                        const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mk));
+                        const int na = __builtin_amdgcn_readlane(na_l, s);
+                        const int c0 = __builtin_amdgcn_readlane(cut, s);
+                        const int c1 = __builtin_amdgcn_readlane(cut_next, s);
+                        const int rel = __builtin_amdgcn_readlane(bf_l, s) - b0;
+                        float win[WS_MAX];
+                        PET_REL_SWITCH(get_window, acc, win, na)
+                        const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                        PET_NA_SWITCH(tof_back_run, zA, zB, zmax, Z + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
+                                      w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, c0 - qlo_b, span, win)
+                    }
                 }
             }
             // the next segment overwrites this wave's table

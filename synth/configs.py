@@ -100,6 +100,24 @@ CONFIGS = {
     ),
 }
 
+# The paper's own simulation geometry (Section 3.1): 600 mm diameter, 17 rings
+# over 80 mm, 36 modules x 12 detectors, span-1 sinograms of 289 planes x 216
+# views x 353 radial bins x 25 TOF bins (390 ps), 161x161x33 image at 2.5 mm,
+# 4 mm FWHM image-space resolution model, 27 subsets.  The TOF bin width is
+# not given; 24 mm makes the 25 bins span the scanner diameter.
+CONFIGS["c5_sim"] = dict(
+    name="c5_sim", kind="cylinder",
+    nx=161, ny=161, nz=33, vx=2.5, vy=2.5, vz=2.5,
+    radius=300.0, n_crystals=432, n_views=216, n_rad=353,
+    n_rings=17, ring_pitch=80.0 / 17, max_ring_diff=16,
+    n_tof=25, tof_bin=24.0, tof_sigma=0.390 * 299.792458 / 2 * FWHM_TO_SIGMA, tof_nsigma=3.0,
+    psf_fwhm=4.0,
+    n_subsets=27, phantom="sim_ellipses", counts=1e7, bg_fraction_of_prompts=0.2,
+    beta_tilde=4.0, gamma=2.0, seed=0, epochs=30,
+)
+# Test geometry with more TOF bins than a lane holds at once (two bin blocks).
+CONFIGS["mini_tof_many"] = dict(CONFIGS["mini_tof"], name="mini_tof_many", n_tof=20, tof_bin=7.0, tof_sigma=6.0)
+
 # Test geometries with the image-space resolution model (Section 3.1): a
 # Gaussian of 6 mm FWHM on ~4 mm voxels (kernel radius 3 voxels in x and y).
 CONFIGS["mini_tof_psf"] = dict(CONFIGS["mini_tof"], name="mini_tof_psf", psf_fwhm=6.0)

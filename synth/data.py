@@ -77,6 +77,13 @@ def shapes(cfg):
         for i, diam in enumerate((5.0, 7.5, 10.0, 12.5, 15.0)):
             ang = d(72 * i)
             rows.append((35 * math.cos(ang), 35 * math.sin(ang), 0, diam / 2, diam / 2, diam / 2, 0, 2.0))
+    elif ph == "sim_ellipses":
+        # elliptical body inside the 80 mm axial field of the simulated
+        # scanner, with hot and cold inserts
+        rows = [(0, 0, 0, 130, 90, 36, 0, 1.0),
+                (40, 20, 0, 25, 15, 15, d(30), 3.0),
+                (-45, -10, 0, 20, 20, 15, 0, -1.0),
+                (0, 50, 0, 8, 8, 8, 0, 2.0)]
     elif ph == "head_small":
         rows = [(0, 0, 0, 36, 30, 14, 0, 4.0), (0, 0, 0, 30, 24, 10, 0, -3.0),
                 (12, 0, 0, 5, 5, 5, 0, 2.0), (-10, 6, 1, 3, 3, 3, 0, 2.0)]
