@@ -336,8 +336,9 @@ __device__ __forceinline__ void read_w(const float *w4, const float *w1, int e1,
 
 // Sample loops of one TOF interval: n rows walked in t order from row pointer
 // xr / zr (row of the first sample, z padding skipped), principal-plane index
-// fi stepping by dfi and row stride drz. The weights of a row are the same
-// for every lane (broadcast LDS reads); the axial position of a sample in
+// fi stepping by dfi and row stride drz, taking every wstep-th row of the
+// interval (a lane's row chunk).  The weights of a row are the same for every
+// lane of a chunk (broadcast LDS reads); the axial position of a sample in
 // plane i is zA * i + zB (voxel units).
 template <int NA>
 __device__ __forceinline__ void read_wq(const float *wq, const float *w1q, float (&w)[NA]) {
@@ -356,7 +357,7 @@ __device__ __forceinline__ void read_wq(const float *wq, const float *w1q, float
 // a plane (zA = 0, zB = -2).
 template <int NA>
 __device__ __forceinline__ void tof_fwd_run(float zA, float zB, float zmax, const float *xr, int drz, float fi,
-                                            float dfi, const float *wq, const float *w1q, int e1, int n,
+                                            float dfi, const float *wq, const float *w1q, int e1, int wstep, int n,
                                             float *win) {
 #pragma unroll 2
     for (; n > 0; --n) {
@@ -372,16 +373,16 @@ __device__ __forceinline__ void tof_fwd_run(float zA, float zB, float zmax, cons
         for (int b = 0; b < NA; ++b) win[b] = fmaf(v, w[b], win[b]);
         xr += drz;
         fi += dfi;
-        wq += 4;
-        w1q += e1;
+        wq += 4 * wstep;
+        w1q += e1 * wstep;
     }
 }
 
 // Adjoint: a lane adds its samples k = q - qlo in [0, span] only.
 template <int NA>
 __device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, double *zr, int drz, float fi, float dfi,
-                                             const float *wq, const float *w1q, int e1, int n, int k, unsigned span,
-                                             const float *win) {
+                                             const float *wq, const float *w1q, int e1, int wstep, int n, int k,
+                                             unsigned span, const float *win) {
 #pragma unroll 2
     for (; n > 0; --n) {
         float w[NA];
@@ -401,9 +402,9 @@ __device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, dou
         }
         zr += drz;
         fi += dfi;
-        wq += 4;
-        w1q += e1;
-        ++k;
+        wq += 4 * wstep;
+        w1q += e1 * wstep;
+        k += wstep;
     }
 }
 
@@ -504,8 +505,15 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     pairs = 0.0;
     for (int sg = wave; wave < nwaves && sg < a.n_seg; sg += nwaves) {
         const SegP S = a.segs[sg];
-        const bool has = lane < S.np;
-        const int p = S.p0 + (has ? lane : 0);
+        // lanes: plane pl of the segment and row chunk ch; a segment of at most
+        // 32 planes splits the rows of every interval over C = 64 / np_pad
+        // chunks (np_pad the planes rounded up to a power of two)
+        int lg = 0;
+        while ((1 << lg) < S.np) ++lg;
+        lg = __builtin_amdgcn_readfirstlane(lg);
+        const int np_pad = 1 << lg, C = 64 >> lg;
+        const bool has = (lane & (np_pad - 1)) < S.np;
+        const int p = S.p0 + (has ? (lane & (np_pad - 1)) : 0);
         const PlaneP P = a.planes[p];
         const int64_t lor = (int64_t)line * a.n_planes + p;
         const float len = sqrtf(L.lt2 + S.dz2);
@@ -517,7 +525,7 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
         const int qhi = L.dlam > 0.f ? ie - L.i_lo : L.i_hi - is;
 
         if constexpr (MODE == M_COUNT) {
-            if (nrow > 0 && ie >= is) {
+            if (nrow > 0 && ie >= is && lane < np_pad) {
                 kl += (double)(ie - is + 1);
                 for (int s = 0; s < a.tof.n_int; ++s) {
                     const int na = a.tof.na[s];
@@ -571,10 +579,18 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                         float win[WS_MAX];
 #pragma unroll
                         for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
-                        const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
-                        PET_NA_SWITCH(tof_fwd_run, zAf, zBf, zmax, X + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
-                                      w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, win)
+                        // rows c0 + k, c0 + k + C, ... below c1 (row chunk k = lane >> lg)
+                        const int q0 = c0 + (lane >> lg);
+                        const int nl = q0 < c1 ? (c1 - q0 + C - 1) >> (6 - lg) : 0;
+                        const int i0 = L.dlam > 0.f ? L.i_lo + q0 : L.i_hi - q0;
+                        PET_NA_SWITCH(tof_fwd_run, zAf, zBf, zmax, X + (i0 - L.i_lo) * rz + PADZ, drz * C, (float)i0,
+                                      dfi * C, w4 + 4 * q0, w1 + q0 * e1, e1, C, nl, win)
                         PET_REL_SWITCH(add_window, acc, win, na)
+                    }
+                    // the chunks of a plane hold partial sums over their rows
+                    for (int o = np_pad; o < 64; o <<= 1) {
+#pragma unroll
+                        for (int b = 0; b < NT_BLK; ++b) acc[b] += __shfl_xor(acc[b], o, 64);
                     }
                 }
 
@@ -605,9 +621,9 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                             if (b >= nb) continue;
                             const float ybar = fmaf(m, acc[b] * ell, ad[b]);
                             if constexpr (MODE == M_FWD) {
-                                a.out[bb + b] = ybar;
+                                if (lane < np_pad) a.out[bb + b] = ybar;
                             } else {
-                                if (a.partial) kl += kl_term(ybar, yv[b]);
+                                if (a.partial && lane < np_pad) kl += kl_term(ybar, yv[b]);
                                 if constexpr (MODE == M_GRAD)
                                     acc[b] = m * fmaf(-yv[b], __builtin_amdgcn_rcpf(ybar), 1.f) * ell;
                                 if constexpr (MODE == M_EM) acc[b] = m * (yv[b] * __builtin_amdgcn_rcpf(ybar)) * ell;
@@ -626,9 +642,11 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                         const int rel = __builtin_amdgcn_readlane(bf_l, s) - b0;
                         float win[WS_MAX];
                         PET_REL_SWITCH(get_window, acc, win, na)
-                        const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
-                        PET_NA_SWITCH(tof_back_run, zA, zB, zmax, Z + (i0 - L.i_lo) * rz + PADZ, drz, (float)i0, dfi,
-                                      w4 + 4 * c0, w1 + c0 * e1, e1, c1 - c0, c0 - qlo_b, span, win)
+                        const int q0 = c0 + (lane >> lg);
+                        const int nl = q0 < c1 ? (c1 - q0 + C - 1) >> (6 - lg) : 0;
+                        const int i0 = L.dlam > 0.f ? L.i_lo + q0 : L.i_hi - q0;
+                        PET_NA_SWITCH(tof_back_run, zA, zB, zmax, Z + (i0 - L.i_lo) * rz + PADZ, drz * C, (float)i0,
+                                      dfi * C, w4 + 4 * q0, w1 + q0 * e1, e1, C, nl, q0 - qlo_b, span, win)
                     }
                 }
             }
