@@ -351,22 +351,26 @@ __device__ __forceinline__ void read_wq(const float *wq, const float *w1q, float
     for (int j = 4; j < NA; ++j) w[j] = w1q[j - 4];
 }
 
-// Forward: no lane predicate. The axial position is clamped to [-2, nz]; a
-// sample outside the z-valid range [-1.5, nz + 0.5] then interpolates between
-// two cells of the zero padding and adds exactly zero, as does a lane without
-// a plane (zA = 0, zB = -2).
+// Axial positions are taken in padded-row cells, u = z + PADZ: a sample at
+// axial position z interpolates cells floor(u) and floor(u) + 1 of its sheet
+// row (the row pointer is the row start).  u is clamped to [0, nz + 2], where
+// the truncating conversion is the floor and v_fract the fraction.
+
+// Forward: no lane predicate.  A sample outside the z-valid range
+// [-1.5, nz + 0.5] (u outside [0.5, nz + 2.5]) interpolates between two cells
+// of the zero padding and adds exactly zero, as does a lane without a plane
+// (zA = 0, zB = 0).
 template <int NA>
-__device__ __forceinline__ void tof_fwd_run(float zA, float zB, float zmax, const float *xr, int drz, float fi,
+__device__ __forceinline__ void tof_fwd_run(float zA, float zB, float umax, const float *xr, int drz, float fi,
                                             float dfi, const float *wq, const float *w1q, int e1, int wstep, int n,
                                             float *win) {
 #pragma unroll 2
     for (; n > 0; --n) {
         float w[NA];
         read_wq<NA>(wq, w1q, w);
-        const float xz = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), -2.f, zmax);
-        const float jf = floorf(xz);
-        const float f = xz - jf;
-        const int j = (int)jf;
+        const float u = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), 0.f, umax);
+        const int j = (int)u;
+        const float f = __builtin_amdgcn_fractf(u);
         const float x0 = xr[j], x1 = xr[j + 1];
         const float v = fmaf(f, x1 - x0, x0);
 #pragma unroll
@@ -380,7 +384,7 @@ __device__ __forceinline__ void tof_fwd_run(float zA, float zB, float zmax, cons
 
 // Adjoint: a lane adds its samples k = q - qlo in [0, span] only.
 template <int NA>
-__device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, double *zr, int drz, float fi, float dfi,
+__device__ __forceinline__ void tof_back_run(float zA, float zB, float umax, double *zr, int drz, float fi, float dfi,
                                              const float *wq, const float *w1q, int e1, int wstep, int n, int k,
                                              unsigned span, const float *win) {
 #pragma unroll 2
@@ -392,11 +396,9 @@ __device__ __forceinline__ void tof_back_run(float zA, float zB, float zmax, dou
         for (int b = 0; b < NA; ++b) Q = fmaf(win[b], w[b], Q);
         if ((unsigned)k <= span) {
             // (the clamp only guards the LDS bounds; valid samples lie inside)
-            const float xz = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), -2.f, zmax);
-            const float jf = floorf(xz);
-            const float f = xz - jf;
-            const float a1 = Q * f;
-            const int j = (int)jf;
+            const float u = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), 0.f, umax);
+            const int j = (int)u;
+            const float a1 = Q * __builtin_amdgcn_fractf(u);
             atomicAdd(&zr[j], (double)(Q - a1));
             atomicAdd(&zr[j + 1], (double)a1);
         }
@@ -538,8 +540,9 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
         } else {
             const int cut = nrow > 0 ? fill_table(a, L, len, cuts, w4, w1) : 0;
             // axial sample position of row i: xz = zA * i + zB
-            const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb);
-            const float zAf = has ? zA : 0.f, zBf = has ? zB : -2.f, zmax = (float)a.nz;
+            // padded axial cell of row i: u = zA * i + zB (z + PADZ)
+            const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
+            const float zAf = has ? zA : 0.f, zBf = has ? zB : 0.f, umax = (float)(a.nz + PADZ);
             const int drz = L.dlam > 0.f ? rz : -rz;
             const float dfi = L.dlam > 0.f ? 1.f : -1.f;
             // back-projection predicate: k = q - qlo_b in [0, span]; a lane with
@@ -583,8 +586,16 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                         const int q0 = c0 + (lane >> lg);
                         const int nl = q0 < c1 ? (c1 - q0 + C - 1) >> (6 - lg) : 0;
                         const int i0 = L.dlam > 0.f ? L.i_lo + q0 : L.i_hi - q0;
-                        PET_NA_SWITCH(tof_fwd_run, zAf, zBf, zmax, X + (i0 - L.i_lo) * rz + PADZ, drz * C, (float)i0,
-                                      dfi * C, w4 + 4 * q0, w1 + q0 * e1, e1, C, nl, win)
+                        const float *xr0 = X + (i0 - L.i_lo) * rz;
+                        if (C == 1) {
+                            // every lane walks the same rows: a scalar loop
+                            const int nu = __builtin_amdgcn_readfirstlane(nl);
+                            PET_NA_SWITCH(tof_fwd_run, zAf, zBf, umax, xr0, drz, (float)i0, dfi, w4 + 4 * q0,
+                                          w1 + q0 * e1, e1, 1, nu, win)
+                        } else {
+                            PET_NA_SWITCH(tof_fwd_run, zAf, zBf, umax, xr0, drz * C, (float)i0, dfi * C, w4 + 4 * q0,
+                                          w1 + q0 * e1, e1, C, nl, win)
+                        }
                         PET_REL_SWITCH(add_window, acc, win, na)
                     }
                     // the chunks of a plane hold partial sums over their rows
@@ -645,8 +656,15 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                         const int q0 = c0 + (lane >> lg);
                         const int nl = q0 < c1 ? (c1 - q0 + C - 1) >> (6 - lg) : 0;
                         const int i0 = L.dlam > 0.f ? L.i_lo + q0 : L.i_hi - q0;
-                        PET_NA_SWITCH(tof_back_run, zA, zB, zmax, Z + (i0 - L.i_lo) * rz + PADZ, drz * C, (float)i0,
-                                      dfi * C, w4 + 4 * q0, w1 + q0 * e1, e1, C, nl, q0 - qlo_b, span, win)
+                        double *zr0 = Z + (i0 - L.i_lo) * rz;
+                        if (C == 1) {
+                            const int nu = __builtin_amdgcn_readfirstlane(nl);
+                            PET_NA_SWITCH(tof_back_run, zA, zB, umax, zr0, drz, (float)i0, dfi, w4 + 4 * q0,
+                                          w1 + q0 * e1, e1, 1, nu, q0 - qlo_b, span, win)
+                        } else {
+                            PET_NA_SWITCH(tof_back_run, zA, zB, umax, zr0, drz * C, (float)i0, dfi * C, w4 + 4 * q0,
+                                          w1 + q0 * e1, e1, C, nl, q0 - qlo_b, span, win)
+                        }
                     }
                 }
             }
