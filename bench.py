@@ -365,7 +365,7 @@ def main():
     ap.add_argument("--no-nrmse", action="store_true", help="skip the time-to-NRMSE measurement")
     ap.add_argument("--ref-iters", type=int, default=500,
                     help="L-BFGS-B iterations (at most) of the converged reference image for the NRMSE")
-    ap.add_argument("--nrmse-max-epochs", type=int, default=200)
+    ap.add_argument("--nrmse-max-epochs", type=int, default=300)
     ap.add_argument("--no-estimators", action="store_true",
                     help="time to NRMSE for SVRG only (not SAGA, SGD, ALG1, ALG2, ALG3)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable (unrolled) leg")
