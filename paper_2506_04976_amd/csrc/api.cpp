@@ -244,6 +244,8 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             return fail(PET_E_ARG, nm + ": weights must be positive and finite");
         if (opt && opt->bb_update && opt->bb_update[j] && (st->k + j) % om != 0)
             return fail(PET_E_ARG, nm + ": bb_update only at snapshot iterations");
+        if (opt && opt->bb_update && opt->bb_update[j] && !st->bb)
+            return fail(PET_E_ARG, nm + ": bb_update needs state->bb");
     }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;

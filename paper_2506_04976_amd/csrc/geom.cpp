@@ -287,7 +287,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     int rz = d.nz + 2 * PADZ;
     size_t sheet = ((size_t)rows_max * rz + 3) & ~(size_t)3;
     int max_lds = 0;
-    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device);
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) != hipSuccess) max_lds = 0;
     if (max_lds <= 0) max_lds = 64 * 1024;
     size_t need = 3 * sheet * sizeof(float);
     if (d.n_tof > 1) {
@@ -348,17 +348,17 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
 
 extern "C" pet_status pet_geom_destroy(pet_geom g) {
     if (!g) return PET_OK;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();  // best effort: destruction goes on whatever it returns
     for (auto &v : g->prof_events)
         for (auto &e : v) g->prof_pool.push_back(e);
     for (auto &e : g->prof_pool) {
-        hipEventDestroy(e.first);
-        hipEventDestroy(e.second);
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
     }
     void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
                     g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch, g->psf_a, g->psf_b};
     for (void *p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     delete g;
     return PET_OK;
 }

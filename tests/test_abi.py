@@ -44,6 +44,11 @@ def test_argument_errors_without_gpu_work():
     assert b"null" in L.pet_last_error()
     assert L.pet_geom_create(None, None) == 1
     assert L.pet_geom_info(None, 0, None, None, None) == 1
+    for fn in (L.pet_saga_epoch, L.pet_sgd_epoch):
+        assert fn(None, None, None, None, None, None, None, None) == 1
+    assert L.pet_svrg_epoch_ex(None, None, None, None, None, None, None, None, None) == 1
+    assert L.pet_batch_set_launch(None, 64, 8, 0) == 1
+    assert b"null" in L.pet_last_error()
 
 
 @pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU refusal")
