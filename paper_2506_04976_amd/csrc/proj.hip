@@ -192,16 +192,19 @@ __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, floa
             if (ie >= is) kl += (double)(ie - is + 1);
             continue;
         }
+        // padded axial cell of sample i: u = zA i + zB = z + PADZ, clamped to
+        // [0, nz + 2] (the clamp only guards the LDS bounds; z-clipped samples
+        // lie inside), where truncation is the floor
+        const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
+        const float umax = (float)(a.nz + PADZ);
         float s = 0.f;
         if (NEED_X) {
-            for (int i = is; i <= ie; ++i) {
-                float lam = fmaf((float)i, L.dlam, L.lam0);
-                float xz = fmaf(lam, P.zs, P.zb);
-                float jf = floorf(xz);
-                float f = xz - jf;
-                int r = (i - L.i_lo) * rz + (int)jf + PADZ;
-                float x0 = X[r], x1 = X[r + 1];
-                s += fmaf(f, x1 - x0, x0);
+            const float *xr = X + (is - L.i_lo) * rz;
+            for (int i = is; i <= ie; ++i, xr += rz) {
+                const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+                const int j = (int)u;
+                const float x0 = xr[j], x1 = xr[j + 1];
+                s += fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
             }
         }
         const float m = a.mult ? a.mult[lor] : 1.f;
@@ -226,15 +229,13 @@ __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, floa
             }
         }
         if constexpr (NEED_Z) {
-            for (int i = is; i <= ie; ++i) {
-                float lam = fmaf((float)i, L.dlam, L.lam0);
-                float xz = fmaf(lam, P.zs, P.zb);
-                float jf = floorf(xz);
-                float f = xz - jf;
-                int r = (i - L.i_lo) * rz + (int)jf + PADZ;
-                float a1 = Q * f;
-                atomicAdd(&Z[r], (double)(Q - a1));
-                atomicAdd(&Z[r + 1], (double)a1);
+            double *zr = Z + (is - L.i_lo) * rz;
+            for (int i = is; i <= ie; ++i, zr += rz) {
+                const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+                const int j = (int)u;
+                const float a1 = Q * __builtin_amdgcn_fractf(u);
+                atomicAdd(&zr[j], (double)(Q - a1));
+                atomicAdd(&zr[j + 1], (double)a1);
             }
         }
     }
