@@ -9,6 +9,9 @@ J_i = D_i + (beta / n) S.  Every operation is a plain definition:
 
 * the Joseph pair of the oracle projector is a linear operator whose adjoint is
   the oracle back projection (and vice versa);
+* the image-space resolution model G (Section 3.1; oracle.psf) is a symmetric
+  linear operator, its own adjoint, applied before the forward projection and
+  after the back projection (A = P G);
 * the prior gradient and Hessian diagonal are the closed forms of Appendix A,
   written with grid shifts over the in-grid neighbours;
 * the preconditioner is eq. (preconditioner) with the harmonic combination,
@@ -23,7 +26,7 @@ import numpy as np
 import torch
 import torch.nn.functional as F
 
-from . import projector, rdp
+from . import projector, psf, rdp
 
 
 class _Fwd(torch.autograd.Function):
@@ -53,6 +56,20 @@ class _Back(torch.autograd.Function):
     def backward(ctx, g):
         out = projector.fwd(ctx.cfg, g.detach().contiguous().numpy(), ctx.p1, ctx.p2)
         return torch.from_numpy(out).reshape(ctx.shape), None, None, None
+
+
+class _Blur(torch.autograd.Function):
+    """G x (the resolution model of cfg, the identity without one); G is
+    symmetric, so the adjoint is G again."""
+
+    @staticmethod
+    def forward(ctx, x, cfg):
+        ctx.cfg = cfg
+        return torch.from_numpy(psf.blur(x.detach().numpy(), cfg))
+
+    @staticmethod
+    def backward(ctx, g):
+        return torch.from_numpy(psf.blur(g.detach().contiguous().numpy(), ctx.cfg)), None
 
 
 def _embed(c, shape, I):
@@ -110,10 +127,10 @@ class Unrolled:
         self.kappa = None if prob.kappa is None else torch.from_numpy(prob.kappa)
 
     def data_grad(self, x, i):
-        """grad D_i(x) = P_i^T [a (1 - y / (a P_i x + r))]."""
+        """grad D_i(x) = G P_i^T [a (1 - y / (a P_i G x + r))]."""
         p1, p2 = self.prob.lors[i]
-        yb = self.a[i] * _Fwd.apply(x, self.cfg, p1, p2) + self.r[i]
-        return _Back.apply(self.a[i] * (1.0 - self.y[i] / yb), self.cfg, p1, p2)
+        yb = self.a[i] * _Fwd.apply(_Blur.apply(x, self.cfg), self.cfg, p1, p2) + self.r[i]
+        return _Blur.apply(_Back.apply(self.a[i] * (1.0 - self.y[i] / yb), self.cfg, p1, p2), self.cfg)
 
     def grad_J(self, x, i, beta):
         p = self.prob

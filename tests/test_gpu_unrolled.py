@@ -3,7 +3,8 @@ products, the preconditioner's vector-Jacobian product, and gradients of a loss
 of the unrolled preconditioned-SVRG reconstruction with respect to the initial
 image and log(beta), all through the C ABI against the FP64 oracle (torch
 autograd over oracle operations), plus central finite differences on the
-3D workload of the differentiable configuration.
+3D workload of the differentiable configuration.  One case carries the
+image-space resolution model (A = P G).
 
 Tolerances: Hessian-vector products (summands of both signs) use a
 cancellation-aware denominator, ||hv_gpu - hv_orc|| <= 1e-5 ||sum of |summands|||;
@@ -14,7 +15,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import projector, rdp, recon, unrolled
+from oracle import projector, psf, rdp, recon, unrolled
 from synth import configs, data
 
 pytestmark = pytest.mark.gpu
@@ -52,7 +53,7 @@ class Case:
         return list(range(self.cfg["n_views"])) if subset < 0 else configs.subset_views(self.cfg, subset)
 
 
-@pytest.fixture(scope="module", params=["mini_tof", "mini_nontof", "c0_2d"])
+@pytest.fixture(scope="module", params=["mini_tof", "mini_nontof", "c0_2d", "mini_tof_psf"])
 def case(request):
     _say(f"\n[gpu unrolled case {request.param}]")
     return Case(request.param)
@@ -71,10 +72,13 @@ def test_subset_hvp_parity(case):
         p1, p2 = projector.view_lors(case.cfg, views)
         a = case.d["mult"][views].reshape(-1, 1).astype(np.float64)
         y = case.d["y"][views].reshape(-1, case.T).astype(np.float64)
-        yb = a * projector.fwd(case.cfg, case.x_np, p1, p2) + case.d["r"][views].reshape(-1, case.T)
+        # A = P G with G the resolution model (the identity without one)
+        G = lambda img: psf.blur(np.asarray(img, np.float64).reshape(case.shape), case.cfg)  # noqa: E731
+        yb = a * projector.fwd(case.cfg, G(case.x_np), p1, p2) + case.d["r"][views].reshape(-1, case.T)
         c = a * a * y / yb ** 2
-        ref = projector.back(case.cfg, c * projector.fwd(case.cfg, v_np, p1, p2), p1, p2).ravel()
-        scale = np.linalg.norm(projector.back(case.cfg, c * projector.fwd(case.cfg, np.abs(v_np), p1, p2), p1, p2))
+        ref = G(projector.back(case.cfg, c * projector.fwd(case.cfg, G(v_np), p1, p2), p1, p2)).ravel()
+        scale = np.linalg.norm(G(projector.back(case.cfg, c * projector.fwd(case.cfg, G(np.abs(v_np)), p1, p2), p1,
+                                                p2)))
         err = np.linalg.norm(hv.cpu().numpy() - ref) / scale
         _say(f"[{case.cfg['name']}] subset {subset} data HVP error {err:.2e}")
         assert err <= 1e-5

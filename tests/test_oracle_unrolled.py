@@ -1,7 +1,8 @@
 """Pins for the oracle's reverse-mode pieces: the FP64 torch prior against the
 numpy closed forms, the unrolled forward pass against the oracle's Algorithm 1,
-autograd gradients of the unrolled reconstruction against central finite
-differences of its forward pass, the data-term Hessian-vector product against
+autograd gradients of the unrolled reconstruction (with and without the
+image-space resolution model) against central finite differences of its
+forward pass, the data-term Hessian-vector product against
 finite differences of the data gradient, and the preconditioner's
 vector-Jacobian product against finite differences."""
 
@@ -13,9 +14,9 @@ from oracle import poisson, projector, rdp, recon, unrolled
 from synth import configs, data
 
 
-def _tiny(beta=0.5, n_subsets=3, seed=0):
+def _tiny(beta=0.5, n_subsets=3, seed=0, psf_fwhm=0.0):
     cfg = configs.get("mini_2d", nx=8, ny=8, n_views=12, n_rad=15, rad_spacing=4.0,
-                      n_subsets=n_subsets, seed=seed, phantom="c0_small", counts_total=5e4)
+                      n_subsets=n_subsets, seed=seed, phantom="c0_small", counts_total=5e4, psf_fwhm=psf_fwhm)
     d = data.make_dataset(cfg)
     prob = recon.Problem(cfg, d["y"].astype(np.float64), d["r"], d["mult"], beta=beta,
                          gamma=2.0, eps=1e-2, alpha=1.0, delta=1e-3)
@@ -43,8 +44,9 @@ def test_torch_prior_matches_numpy_closed_forms():
         assert np.allclose(h, rdp.hessdiag(x, w, 2.0, 0.01, kappa), rtol=1e-13, atol=1e-14)
 
 
-def test_unrolled_forward_matches_algorithm1():
-    cfg, d, prob = _tiny()
+@pytest.mark.parametrize("psf_fwhm", [0.0, 6.0])
+def test_unrolled_forward_matches_algorithm1(psf_fwhm):
+    cfg, d, prob = _tiny(psf_fwhm=psf_fwhm)
     n = prob.n
     orders, taus, upd = _schedule(cfg, 3)
     x0 = recon.osem_epoch(prob, np.ones(prob.shape))
@@ -56,8 +58,10 @@ def test_unrolled_forward_matches_algorithm1():
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-def test_unrolled_gradient_matches_finite_differences():
-    cfg, d, prob = _tiny()
+@pytest.mark.parametrize("psf_fwhm", [0.0, 6.0])
+def test_unrolled_gradient_matches_finite_differences(psf_fwhm):
+    # with a resolution model this also pins the blur's adjoint in autograd
+    cfg, d, prob = _tiny(psf_fwhm=psf_fwhm)
     orders, taus, upd = _schedule(cfg, 3)
     x0 = recon.osem_epoch(prob, np.ones(prob.shape))
     target = d["x_true"].astype(np.float64)
