@@ -266,6 +266,26 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
         if (hsegs.empty() || planes[p].seg != planes[p - 1].seg) hsegs.push_back({(int)p, 0, hplanes[p].dz2, 0});
         hsegs.back().np++;
     }
+    if (d.n_tof > 1) {
+        // segments -k and +k (adjacent in the plane order) have the same
+        // oblique length and so the same TOF weight table: one segment wave
+        // takes both when their planes fit in its 64 lanes
+        std::vector<SegP> merged;
+        for (const SegP &sg : hsegs) {
+            const int k = std::abs(planes[sg.p0].r2 - planes[sg.p0].r1);
+            if (!merged.empty()) {
+                SegP &m = merged.back();
+                // (the last group must still be a single segment)
+                if (k > 0 && std::abs(planes[m.p0].r2 - planes[m.p0].r1) == k && m.p0 + m.np == sg.p0 &&
+                    planes[m.p0].seg == planes[m.p0 + m.np - 1].seg && m.np + sg.np <= 64) {
+                    m.np += sg.np;
+                    continue;
+                }
+            }
+            merged.push_back(sg);
+        }
+        hsegs.swap(merged);
+    }
     g->n_seg = (int)hsegs.size();
     g->rows_max = rows_max;
     if (d.n_tof > 1) {
