@@ -9,13 +9,17 @@ benchmark uses (whole subsets of the 3D geometries).
 * 3D image after 10 SVRG epochs on the small 3D geometry (96x96x32, 268 planes,
   8 subsets): relative L2 <= 1e-4 against the oracle.
 * The GPU adjoint identity on a whole TOF subset.
+
+The cases are the non-TOF and TOF brain-sized workloads and the paper's own
+simulation geometry (17 rings, 25 TOF bins, 4 mm resolution model): with a
+resolution model the references use A = P G.
 """
 
 import numpy as np
 import pytest
 import torch
 
-from oracle import poisson, projector, recon
+from oracle import poisson, projector, psf, recon
 from synth import configs, data, scanner
 
 pytestmark = pytest.mark.gpu
@@ -25,7 +29,7 @@ def _say(msg):
     print(msg, flush=True)
 
 
-@pytest.fixture(scope="module", params=["c1_3d", "c2_tof"])
+@pytest.fixture(scope="module", params=["c1_3d", "c2_tof", "c5_sim"])
 def big(request):
     import paper_2506_04976_amd as pm
     name = request.param
@@ -42,6 +46,8 @@ def big(request):
     x = d["x_true"] * rng.uniform(0.8, 1.2, d["x_true"].shape) + 0.05 * d["x_true"].max()
     out["x_np"] = x.astype(np.float32)
     out["x"] = torch.from_numpy(out["x_np"].ravel()).to(dev)
+    # G x in FP64 (the image itself without a resolution model)
+    out["gx"] = psf.blur(out["x_np"].astype(np.float64), cfg)
     yield out
     geom.close()
 
@@ -61,7 +67,7 @@ def test_fullsize_fwd_sampled(big):
     k = rng.integers(0, cfg["n_rad"], ns)
     p = rng.integers(0, n_pl, ns)
     p1, p2 = scanner.lor_endpoints(cfg, v, k, p)
-    ref = projector.fwd(cfg, big["x_np"], p1, p2) * big["d"]["mult"][v, k, p][:, None] + big["d"]["r"][v, k, p]
+    ref = projector.fwd(cfg, big["gx"], p1, p2) * big["d"]["mult"][v, k, p][:, None] + big["d"]["r"][v, k, p]
     g = got[torch.from_numpy(v), torch.from_numpy(k), torch.from_numpy(p)].cpu().numpy()
     err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     _say(f"[{cfg['name']}] sampled fwd relative L2 {err:.2e}")
@@ -87,10 +93,9 @@ def test_fullsize_subset_grad_one_view(big):
     a = d["mult"][view].reshape(-1, 1).astype(np.float64)
     r = d["r"][view].reshape(-1, T).astype(np.float64)
     y = d["y"][view].reshape(-1, T).astype(np.float64)
-    xo = big["x_np"].astype(np.float64)
-    yb = a * projector.fwd(cfg, xo, p1, p2) + r
-    ref = projector.back(cfg, a * (1.0 - y / yb), p1, p2).ravel()
-    scale = np.linalg.norm(projector.back(cfg, a * (1.0 + y / yb), p1, p2))
+    yb = a * projector.fwd(cfg, big["gx"], p1, p2) + r
+    ref = psf.blur(projector.back(cfg, a * (1.0 - y / yb), p1, p2), cfg).ravel()
+    scale = np.linalg.norm(psf.blur(projector.back(cfg, a * (1.0 + y / yb), p1, p2), cfg))
     err = np.linalg.norm(g_gpu - ref) / scale
     _say(f"[{cfg['name']}] one-view fused gradient, cancellation-aware error {err:.2e}")
     assert err <= 1e-5
