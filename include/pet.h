@@ -343,9 +343,11 @@ typedef struct pet_batch_s *pet_batch;
  * pet_svrg_epoch; their buffers and the images x[r] must stay alive, and the
  * geometries' scratch belongs to the batch while it runs) and images (device,
  * in/out).  Allocates gradient-sheet slots for every subset of every member,
- * the device schedule and a stream of its own.  At most 64 members;
- * geometries with a resolution model (psf_fwhm_mm > 0) are refused
- * (PET_E_ARG). */
+ * the device schedule and a stream of its own.  At most 64 members.  A
+ * member with a resolution model (psf_fwhm_mm > 0) passes its image through G
+ * before the sheets and its gathered gradients through G after them, as
+ * pet_svrg_epoch does; the extra passes are launched only when some member
+ * has one. */
 pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *const *states, float *const *x,
                             int n_members, pet_batch *out);
 pet_status pet_batch_destroy(pet_batch b);

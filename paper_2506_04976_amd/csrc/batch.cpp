@@ -33,6 +33,7 @@ struct pet_batch_s {
     int max_steps = 0;
     int *d_order = nullptr, *d_counter = nullptr;
     int blocks = 0, waves = TOF_MAX_WAVES, order_kind = 0;
+    int psf_max = 0;  // most resolution-model passes of any member
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -64,11 +65,11 @@ void drop_graph(pet_batch_s *b) {
 }
 
 hipError_t enqueue_step(pet_batch_s *b, int j, hipStream_t s) {
-    hipError_t e = launch_b_prep(b->d_mem, b->n, j, b->d_counter, s);
+    hipError_t e = launch_b_prep(b->d_mem, b->n, j, b->d_counter, b->psf_max, s);
     if (e == hipSuccess)
         e = launch_line_batched(b->d_mem, b->d_order, b->n, j, b->d_counter, b->blocks, b->waves,
                                 batch_lds(b, b->waves), s);
-    if (e == hipSuccess) e = launch_b_gather(b->d_mem, b->n, j, s);
+    if (e == hipSuccess) e = launch_b_gather(b->d_mem, b->n, j, b->psf_max, s);
     if (e == hipSuccess) e = launch_b_step(b->d_mem, b->n, j, s);
     if (e == hipSuccess) e = launch_b_commit(b->d_mem, b->n, j, s);
     return e;
@@ -133,8 +134,6 @@ extern "C" pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *co
         for (int q = 0; q < r; ++q)
             if (geoms[q] == geoms[r]) return fail(PET_E_ARG, "pet_batch_create: members need distinct geometries");
         if (geoms[r]->device != geoms[0]->device) return fail(PET_E_ARG, "pet_batch_create: members on one device");
-        if (geoms[r]->psf_passes)
-            return fail(PET_E_ARG, "pet_batch_create: geometries with a resolution model are not batched");
     }
     pet_batch_s *b = new (std::nothrow) pet_batch_s();
     if (!b) return fail(PET_E_OOM, "pet_batch_create: host allocation");
@@ -197,6 +196,14 @@ extern "C" pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *co
         m.alpha = st->alpha;
         m.delta = st->delta;
         m.n_subf = (float)g->d.n_subsets;
+        // resolution model: G x in the geometry's work images, G over gathered
+        // images with two work images in each gradient-sheet slot
+        m.psf_passes = g->psf_passes;
+        for (int p = 0; p < 3; ++p) m.psf[p] = g->psf[p];
+        m.psf_a = g->psf_a;
+        m.psf_b = g->psf_b;
+        b->psf_max = std::max(b->psf_max, g->psf_passes);
+        if (g->psf_passes && slot < 2 * (int64_t)g->n_vox) e = hipErrorInvalidValue;
         // LDS of the line bodies: sheets, plus one TOF table per wave
         const int rz = g->d.nz + 2 * PADZ;
         const size_t sheet = ((size_t)g->rows_max * rz + 3) & ~(size_t)3;
@@ -339,7 +346,7 @@ extern "C" pet_status pet_batch_autotune(pet_batch b, int *config_out, double *b
                 e = upload_order(b);
                 float ms = 0.f;
                 for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-                    e = launch_b_prep(b->d_mem, b->n, 0, b->d_counter, b->stream);
+                    e = launch_b_prep(b->d_mem, b->n, 0, b->d_counter, b->psf_max, b->stream);
                     if (e == hipSuccess) e = hipEventRecord(b->ev_t0, b->stream);
                     if (e == hipSuccess)
                         e = launch_line_batched(b->d_mem, b->d_order, b->n, 0, b->d_counter, b->blocks, b->waves,

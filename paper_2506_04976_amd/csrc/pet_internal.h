@@ -92,6 +92,14 @@ struct ProjArgs {
 };
 
 // ---- batches of reconstructions -------------------------------------------
+constexpr int PSF_RMAX = 16;  // resolution model: kernel radius limit (voxels)
+// One axis of the separable resolution kernel: weights w[0..r] of offsets 0..r
+// (symmetric), and the axis (0 = x, 1 = y, 2 = z).
+struct PsfAxis {
+    int r, axis;
+    float w[PSF_RMAX + 1];
+};
+
 constexpr int BATCH_MAX = 64;
 enum BStepFlags { B_ACTIVE = 1, B_SNAP = 2, B_UPDATE = 4 };
 
@@ -118,19 +126,15 @@ struct BMember {
     float w[27];
     float beta, gamma, eps, alpha, delta, n_subf;
     const BStep *steps;        // [max_steps] of the current round
+    // resolution model (psf_passes = 0: none): axis passes, and two image-sized
+    // work buffers for G x
+    int psf_passes;
+    PsfAxis psf[3];
+    float *psf_a, *psf_b;
 };
 
 }  // namespace pet
 
-namespace pet {
-constexpr int PSF_RMAX = 16;  // resolution model: kernel radius limit (voxels)
-// One axis of the separable resolution kernel: weights w[0..r] of offsets 0..r
-// (symmetric), and the axis (0 = x, 1 = y, 2 = z).
-struct PsfAxis {
-    int r, axis;
-    float w[PSF_RMAX + 1];
-};
-}  // namespace pet
 
 struct pet_geom_s {
     pet_geom_desc d;
@@ -226,8 +230,9 @@ int rdp_blocks(const pet_geom_s *g);
 hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_fill(float *dst, int64_t n, float val, hipStream_t s);
 // batched image-space kernels (batch.hip): one launch each for all active members of a step
-hipError_t launch_b_prep(const BMember *mem, int n_mem, int step, int *counter, hipStream_t s);
-hipError_t launch_b_gather(const BMember *mem, int n_mem, int step, hipStream_t s);
+// psf_max: the most resolution-model passes of any member (0: no member has one)
+hipError_t launch_b_prep(const BMember *mem, int n_mem, int step, int *counter, int psf_max, hipStream_t s);
+hipError_t launch_b_gather(const BMember *mem, int n_mem, int step, int psf_max, hipStream_t s);
 hipError_t launch_b_step(const BMember *mem, int n_mem, int step, hipStream_t s);
 hipError_t launch_b_commit(const BMember *mem, int n_mem, int step, hipStream_t s);
 // reverse-mode kernels (adjoint.hip)

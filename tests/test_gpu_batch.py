@@ -3,8 +3,8 @@ TOF settings, count levels, beta and subset counts advanced by pet_batch_epochs
 (persistent subset-gradient launch, with and without HIP-graph replay) match
 the same members advanced one by one with pet_svrg_epoch on the same schedule
 (relative L2 <= 1e-5 per member; the two differ only in the summation order
-of floating-point atomics), and one member matches the FP64 oracle's
-Algorithm 1 (relative L2 <= 1e-4)."""
+of floating-point atomics), and members with and without the image-space
+resolution model match the FP64 oracle's Algorithm 1 (relative L2 <= 1e-4)."""
 
 import numpy as np
 import pytest
@@ -15,7 +15,9 @@ from synth import configs, data
 
 pytestmark = pytest.mark.gpu
 
-MEMBERS = [("mini_tof", 1.0), ("mini_nontof", 3.0), ("mini_2d", 0.5), ("c0_2d", 1.0)]
+# the last two carry the image-space resolution model (3D: three passes, 2D: two)
+MEMBERS = [("mini_tof", 1.0), ("mini_nontof", 3.0), ("mini_2d", 0.5), ("c0_2d", 1.0), ("mini_tof_psf", 1.0),
+           ("mini_2d_psf", 2.0)]
 
 
 def _say(msg):
@@ -105,18 +107,20 @@ def test_batch_member_matches_oracle(members):
     b.epochs([[int(v) for e in range(E) for v in s[0][e]] for s in scheds],
              [[v for e in range(E) for v in s[1][e]] for s in scheds],
              [[v for e in range(E) for v in s[2][e]] for s in scheds])
-    m = members[0]
-    n = m.cfg["n_subsets"]
-    x_gpu = runs[0][2].cpu().double().numpy()
-    prob = recon.Problem(m.cfg, m.d["y"], m.d["r"], m.d["mult"], beta=m.beta, gamma=2.0, eps=m.eps, alpha=1.0,
-                         delta=m.eps)
-    orders, taus, _ = scheds[0]
-    x0 = m.x0.cpu().double().numpy().reshape(prob.shape)
-    x_orc = recon.svrg(prob, x0, E, recon.order_rule(orders), lambda k: taus[k // n][k % n],
-                       recon.pc_update_iters(n)).ravel()
-    err = np.linalg.norm(x_gpu - x_orc) / np.linalg.norm(x_orc)
-    _say(f"[batch] {m.cfg['name']} after {E} rounds vs oracle: relative L2 {err:.2e}")
-    assert err <= 1e-4
+    psf_member = next(i for i, m in enumerate(members) if m.cfg.get("psf_fwhm", 0.0) > 0)
+    for idx in (0, psf_member):
+        m = members[idx]
+        n = m.cfg["n_subsets"]
+        x_gpu = runs[idx][2].cpu().double().numpy()
+        prob = recon.Problem(m.cfg, m.d["y"], m.d["r"], m.d["mult"], beta=m.beta, gamma=2.0, eps=m.eps, alpha=1.0,
+                             delta=m.eps)
+        orders, taus, _ = scheds[idx]
+        x0 = m.x0.cpu().double().numpy().reshape(prob.shape)
+        x_orc = recon.svrg(prob, x0, E, recon.order_rule(orders), lambda k: taus[k // n][k % n],
+                           recon.pc_update_iters(n)).ravel()
+        err = np.linalg.norm(x_gpu - x_orc) / np.linalg.norm(x_orc)
+        _say(f"[batch] {m.cfg['name']} after {E} rounds vs oracle: relative L2 {err:.2e}")
+        assert err <= 1e-4
     b.close()
 
 

@@ -51,17 +51,3 @@ def test_epoch_option_errors(pm):
     assert st.k == 0 and stb.k == 0, "a refused call must not advance the state"
     torch.cuda.synchronize()
     g.close()
-
-
-def test_batch_refuses_resolution_model(pm):
-    cfg = configs.get("mini_tof_psf")
-    g = pm.Geometry(cfg)
-    dev = torch.device("cuda:0")
-    y = torch.zeros(g.n_bins, dtype=torch.uint8, device=dev)
-    r = torch.full((g.n_bins,), 0.1, device=dev)
-    a = torch.ones(g.n_lors, device=dev)
-    sens = torch.ones(g.n_vox, device=dev)
-    st = pm.SvrgStateBuffers(g, y, r, a, sens, beta=0.1, gamma=2.0, eps=1e-3)
-    with pytest.raises(pm.PetError, match="resolution"):
-        pm.Batch([(g, st, torch.ones(g.n_vox, device=dev))])
-    g.close()
