@@ -470,6 +470,18 @@ static_assert(NT_BLK == 16 && WS_MAX == 8, "the window switch below covers first
         default: FN<8>(__VA_ARGS__); break; \
     }
 
+// Live intervals of a segment wave as a bit mask (bit s: interval s).  With the
+// rows split over C chunks, chunk k takes the k-th set bit (-1 if there are
+// fewer), and the wave then drops the lowest C.
+__device__ __forceinline__ int kth_interval(uint64_t mk, int k) {
+    for (int i = 0; i < k && mk; ++i) mk &= mk - 1;
+    return mk ? (int)__builtin_ctzll(mk) : -1;
+}
+__device__ __forceinline__ uint64_t drop_intervals(uint64_t mk, int c) {
+    for (int i = 0; i < c && mk; ++i) mk &= mk - 1;
+    return mk;
+}
+
 // One transaxial line of a TOF geometry by the whole workgroup, segments
 // spread over the first nwaves waves (the others only help with the sheets);
 // returns this thread's FP64 partials (KL or samples, and sample-bin pairs).
@@ -489,7 +501,8 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     const int nt = a.tof.n_tof;
     // LDS: X sheet (float) | Z sheet (double) | per wave: w4 [rows][4], w1 [rows][e1], cuts
     const int sheet = (a.rows_max * rz + 3) & ~3;
-    const int e1 = a.ws > 4 ? a.ws - 4 : 0;
+    const int ws = a.ws;  // widest bin window of any interval
+    const int e1 = ws > 4 ? ws - 4 : 0;
     const int per_wave = a.rows_max * (4 + e1) + tof_cuts_pad(a.tof.n_int);
     float *X = smem;
     double *Z = reinterpret_cast<double *>(smem + (NEED_X ? sheet : 0));
@@ -508,9 +521,9 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     pairs = 0.0;
     for (int sg = wave; wave < nwaves && sg < a.n_seg; sg += nwaves) {
         const SegP S = a.segs[sg];
-        // lanes: plane pl of the segment and row chunk ch; a segment of at most
-        // 32 planes splits the rows of every interval over C = 64 / np_pad
-        // chunks (np_pad the planes rounded up to a power of two)
+        // lanes: plane pl of the segment and chunk ch; a segment of at most 32
+        // planes splits its live intervals over C = 64 / np_pad chunks (np_pad
+        // the planes rounded up to a power of two)
         int lg = 0;
         while ((1 << lg) < S.np) ++lg;
         lg = __builtin_amdgcn_readfirstlane(lg);
@@ -574,32 +587,53 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
 
                 // ---- forward projection ----
                 if (NEED_X) {
-                    for (uint64_t mk = live_mask; mk; mk &= mk - 1) {
-                        const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mk));
-                        const int na = __builtin_amdgcn_readlane(na_l, s);
-                        const int c0 = __builtin_amdgcn_readlane(cut, s);
-                        const int c1 = __builtin_amdgcn_readlane(cut_next, s);
-                        const int rel = __builtin_amdgcn_readlane(bf_l, s) - b0;
-                        float win[WS_MAX];
+                    if (C == 1) {
+                        // every lane walks the same rows of one interval at a time: a scalar loop
+                        for (uint64_t mk = live_mask; mk; mk &= mk - 1) {
+                            const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mk));
+                            const int na = __builtin_amdgcn_readlane(na_l, s);
+                            const int c0 = __builtin_amdgcn_readlane(cut, s);
+                            const int c1 = __builtin_amdgcn_readlane(cut_next, s);
+                            const int rel = __builtin_amdgcn_readlane(bf_l, s) - b0;
+                            float win[WS_MAX];
 #pragma unroll
-                        for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
-                        // rows c0 + k, c0 + k + C, ... below c1 (row chunk k = lane >> lg)
-                        const int q0 = c0 + (lane >> lg);
-                        const int nl = q0 < c1 ? (c1 - q0 + C - 1) >> (6 - lg) : 0;
-                        const int i0 = L.dlam > 0.f ? L.i_lo + q0 : L.i_hi - q0;
-                        const float *xr0 = X + (i0 - L.i_lo) * rz;
-                        if (C == 1) {
-                            // every lane walks the same rows: a scalar loop
-                            const int nu = __builtin_amdgcn_readfirstlane(nl);
-                            PET_NA_SWITCH(tof_fwd_run, zAf, zBf, umax, xr0, drz, (float)i0, dfi, w4 + 4 * q0,
-                                          w1 + q0 * e1, e1, 1, nu, win)
-                        } else {
-                            PET_NA_SWITCH(tof_fwd_run, zAf, zBf, umax, xr0, drz * C, (float)i0, dfi * C, w4 + 4 * q0,
-                                          w1 + q0 * e1, e1, C, nl, win)
+                            for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
+                            const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                            const float *xr0 = X + (i0 - L.i_lo) * rz;
+                            PET_NA_SWITCH(tof_fwd_run, zAf, zBf, umax, xr0, drz, (float)i0, dfi, w4 + 4 * c0,
+                                          w1 + c0 * e1, e1, 1, c1 - c0, win)
+                            PET_REL_SWITCH(add_window, acc, win, na)
                         }
-                        PET_REL_SWITCH(add_window, acc, win, na)
+                    } else {
+                        // chunk k = lane >> lg takes all rows of the k-th of the next C live
+                        // intervals, with the geometry's widest window (the weights past an
+                        // interval's own bins are zero)
+                        for (uint64_t mk = live_mask; mk; mk = drop_intervals(mk, C)) {
+                            const int s = kth_interval(mk, lane >> lg);
+                            const int sc = s < 0 ? 0 : s;
+                            // every lane shuffles (a lane-permute reads zero from a lane that
+                            // is switched off), then selects
+                            const int c0 = __shfl(cut, sc, 64), c1 = __shfl(cut_next, sc, 64);
+                            const int nas = __shfl(na_l, sc, 64), bfs = __shfl(bf_l, sc, 64);
+                            const int rel = s < 0 ? 0 : bfs - b0;
+                            const int nl = s < 0 ? 0 : c1 - c0;
+                            float win[WS_MAX];
+#pragma unroll
+                            for (int j = 0; j < WS_MAX; ++j) win[j] = 0.f;
+                            const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                            const float *xr0 = X + (i0 - L.i_lo) * rz;
+                            {
+                                const int na = ws;
+                                PET_NA_SWITCH(tof_fwd_run, zAf, zBf, umax, xr0, drz, (float)i0, dfi, w4 + 4 * c0,
+                                              w1 + c0 * e1, e1, 1, nl, win)
+                            }
+                            {
+                                const int na = s < 0 ? 0 : nas;
+                                PET_REL_SWITCH(add_window, acc, win, na)
+                            }
+                        }
                     }
-                    // the chunks of a plane hold partial sums over their rows
+                    // the chunks of a plane hold partial sums over their intervals
                     for (int o = np_pad; o < 64; o <<= 1) {
 #pragma unroll
                         for (int b = 0; b < NT_BLK; ++b) acc[b] += __shfl_xor(acc[b], o, 64);
@@ -646,25 +680,43 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
 
                 // ---- adjoint into the LDS gradient sheet ----
                 if (NEED_Z) {
-                    for (uint64_t mk = live_mask; mk; mk &= mk - 1) {
-                        const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mk));
-                        const int na = __builtin_amdgcn_readlane(na_l, s);
-                        const int c0 = __builtin_amdgcn_readlane(cut, s);
-                        const int c1 = __builtin_amdgcn_readlane(cut_next, s);
-                        const int rel = __builtin_amdgcn_readlane(bf_l, s) - b0;
-                        float win[WS_MAX];
-                        PET_REL_SWITCH(get_window, acc, win, na)
-                        const int q0 = c0 + (lane >> lg);
-                        const int nl = q0 < c1 ? (c1 - q0 + C - 1) >> (6 - lg) : 0;
-                        const int i0 = L.dlam > 0.f ? L.i_lo + q0 : L.i_hi - q0;
-                        double *zr0 = Z + (i0 - L.i_lo) * rz;
-                        if (C == 1) {
-                            const int nu = __builtin_amdgcn_readfirstlane(nl);
-                            PET_NA_SWITCH(tof_back_run, zA, zB, umax, zr0, drz, (float)i0, dfi, w4 + 4 * q0,
-                                          w1 + q0 * e1, e1, 1, nu, q0 - qlo_b, span, win)
-                        } else {
-                            PET_NA_SWITCH(tof_back_run, zA, zB, umax, zr0, drz * C, (float)i0, dfi * C, w4 + 4 * q0,
-                                          w1 + q0 * e1, e1, C, nl, q0 - qlo_b, span, win)
+                    if (C == 1) {
+                        for (uint64_t mk = live_mask; mk; mk &= mk - 1) {
+                            const int s = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mk));
+                            const int na = __builtin_amdgcn_readlane(na_l, s);
+                            const int c0 = __builtin_amdgcn_readlane(cut, s);
+                            const int c1 = __builtin_amdgcn_readlane(cut_next, s);
+                            const int rel = __builtin_amdgcn_readlane(bf_l, s) - b0;
+                            float win[WS_MAX];
+                            PET_REL_SWITCH(get_window, acc, win, na)
+                            const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                            double *zr0 = Z + (i0 - L.i_lo) * rz;
+                            PET_NA_SWITCH(tof_back_run, zA, zB, umax, zr0, drz, (float)i0, dfi, w4 + 4 * c0,
+                                          w1 + c0 * e1, e1, 1, c1 - c0, c0 - qlo_b, span, win)
+                        }
+                    } else {
+                        // the intervals split over the chunks as in the forward pass
+                        for (uint64_t mk = live_mask; mk; mk = drop_intervals(mk, C)) {
+                            const int s = kth_interval(mk, lane >> lg);
+                            const int sc = s < 0 ? 0 : s;
+                            // every lane shuffles (a lane-permute reads zero from a lane that
+                            // is switched off), then selects
+                            const int c0 = __shfl(cut, sc, 64), c1 = __shfl(cut_next, sc, 64);
+                            const int nas = __shfl(na_l, sc, 64), bfs = __shfl(bf_l, sc, 64);
+                            const int rel = s < 0 ? 0 : bfs - b0;
+                            const int nl = s < 0 ? 0 : c1 - c0;
+                            float win[WS_MAX];
+                            {
+                                const int na = s < 0 ? 0 : nas;
+                                PET_REL_SWITCH(get_window, acc, win, na)
+                            }
+                            const int i0 = L.dlam > 0.f ? L.i_lo + c0 : L.i_hi - c0;
+                            double *zr0 = Z + (i0 - L.i_lo) * rz;
+                            {
+                                const int na = ws;
+                                PET_NA_SWITCH(tof_back_run, zA, zB, umax, zr0, drz, (float)i0, dfi, w4 + 4 * c0,
+                                              w1 + c0 * e1, e1, 1, nl, c0 - qlo_b, span, win)
+                            }
                         }
                     }
                 }
