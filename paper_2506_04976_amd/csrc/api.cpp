@@ -54,6 +54,7 @@ ProjArgs base_args(pet_geom g, int subset) {
     a.G0 = g->G0;
     a.G1 = g->G1;
     a.tof = g->tof;
+    a.order = g->line_order + g->order_off[subset < 0 ? g->d.n_subsets : subset];
     return a;
 }
 

@@ -215,6 +215,20 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     for (int i = 0; i < d.n_subsets; ++i)
         for (size_t j = 0; j < g->subset_views[i].size(); ++j) hviews[(size_t)i * d.n_views + j] = g->subset_views[i][j];
     for (int v = 0; v < d.n_views; ++v) hviews[(size_t)d.n_subsets * d.n_views + v] = v;
+    // TOF line launches: the lines of each subset (then of all views),
+    // longest first (a line's work grows with its rows), so that the last
+    // workgroups of a launch run short lines
+    std::vector<int> horder;
+    horder.reserve(2 * (size_t)d.n_views * d.n_rad);
+    for (int row = 0; row <= d.n_subsets; ++row) {
+        g->order_off.push_back((int64_t)horder.size());
+        const size_t start = horder.size();
+        const int nvr = row < d.n_subsets ? (int)g->subset_views[row].size() : d.n_views;
+        for (int j = 0; j < nvr; ++j)
+            for (int k = 0; k < d.n_rad; ++k) horder.push_back(hviews[(size_t)row * d.n_views + j] * d.n_rad + k);
+        auto rows_of = [&](int l) { return std::max(0, hlines[l].i_hi - hlines[l].i_lo + 1); };
+        std::stable_sort(horder.begin() + start, horder.end(), [&](int p, int q) { return rows_of(p) > rows_of(q); });
+    }
 
     // TOF tables
     TofTable &T = g->tof;
@@ -297,8 +311,10 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
         int ws = 1;
         for (int s = 0; s < T.n_int; ++s) ws = std::max(ws, T.na[s]);
         g->tof_ws = ws;
-        int rounds = (g->n_seg + TOF_MAX_WAVES - 1) / TOF_MAX_WAVES;
-        g->tof_waves = (g->n_seg + rounds - 1) / rounds;
+        // as many segment waves as the LDS holds (up to 16): the line body
+        // waits on LDS latency, and more resident waves hide it better than an
+        // even number of segments per wave saves
+        g->tof_waves = std::min(g->n_seg, TOF_MAX_WAVES);
     }
 
     // LDS need of the line kernels: image sheet (float) + gradient sheet
@@ -337,6 +353,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     bool ok = alloc((void **)&g->lines, sizeof(LineP) * nl) && alloc((void **)&g->planes, sizeof(PlaneP) * planes.size()) &&
               alloc((void **)&g->segs, sizeof(SegP) * hsegs.size()) &&
               alloc((void **)&g->views_dev, sizeof(int) * hviews.size()) &&
+              alloc((void **)&g->line_order, sizeof(int) * horder.size()) &&
               alloc((void **)&g->T0, sizeof(float) * g->t0_elems) && alloc((void **)&g->T1, sizeof(float) * g->t1_elems) &&
               alloc((void **)&g->G0, sizeof(float) * g->t0_elems) && alloc((void **)&g->G1, sizeof(float) * g->t1_elems) &&
               alloc((void **)&g->g, sizeof(float) * g->n_vox) && alloc((void **)&g->xtmp, sizeof(float) * g->n_vox) &&
@@ -354,6 +371,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     if (e == hipSuccess) e = hipMemcpy(g->planes, hplanes.data(), sizeof(PlaneP) * planes.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->segs, hsegs.data(), sizeof(SegP) * hsegs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->views_dev, hviews.data(), sizeof(int) * hviews.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->line_order, horder.data(), sizeof(int) * horder.size(), hipMemcpyHostToDevice);
     // padded sheet borders must be zero once; interiors are rewritten per use
     if (e == hipSuccess) e = hipMemset(g->T0, 0, sizeof(float) * g->t0_elems);
     if (e == hipSuccess) e = hipMemset(g->T1, 0, sizeof(float) * g->t1_elems);
@@ -375,7 +393,7 @@ extern "C" pet_status pet_geom_destroy(pet_geom g) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
+    void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->line_order, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
                     g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch, g->psf_a, g->psf_b};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

@@ -89,6 +89,9 @@ struct ProjArgs {
     float *out;
     double *partial;  // one double per block (KL sum), or null
     TofTable tof;
+    // TOF line kernels: workgroup b takes line order[b], the launch's lines
+    // longest first (the hardware dispatches workgroups in index order)
+    const int *order;
 };
 
 // ---- batches of reconstructions -------------------------------------------
@@ -155,6 +158,10 @@ struct pet_geom_s {
     int n_seg = 0, rows_max = 0, tof_ws = 0, tof_tstride = 0, tof_waves = 0;
     int *views_dev = nullptr;           // [n_subsets + 1][max(max_views, n_views)]; last row: all views
     int views_stride = 0;
+    // TOF line launches: per subset (then all views) the subset's lines,
+    // longest first, at line_order + order_off[row]
+    int *line_order = nullptr;
+    std::vector<int64_t> order_off;
     pet::TofTable tof{};
     size_t lds_bytes = 0;
     // scratch arena
@@ -186,6 +193,8 @@ hipError_t launch_line_batched(const BMember *mem, const int *order, int n_mem, 
 hipError_t prime_line_batched(size_t lds);
 // line-kernel argument block of a geometry (all views)
 ProjArgs geom_proj_args(pet_geom_s *g);
+// workgroups of a line launch of `subset` (-1: all views), one per line, each
+// writing one FP64 partial
 int n_line_blocks(const pet_geom_s *g, int subset);
 
 // image kernels (image.hip)

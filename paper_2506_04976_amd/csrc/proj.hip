@@ -484,7 +484,8 @@ __device__ __forceinline__ uint64_t drop_intervals(uint64_t mk, int c) {
 
 // One transaxial line of a TOF geometry by the whole workgroup, segments
 // spread over the first nwaves waves (the others only help with the sheets);
-// returns this thread's FP64 partials (KL or samples, and sample-bin pairs).
+// adds this thread's FP64 partials (KL or samples, and sample-bin pairs) to
+// kl and pairs.
 template <int MODE>
 __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float *smem, int nwaves, double &kl,
                                               double &pairs, int64_t g_off = 0) {
@@ -517,8 +518,6 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     const int na_l = lane < a.tof.n_int ? a.tof.na[lane] : 0;
     const int bf_l = lane < a.tof.n_int ? a.tof.bf[lane] : 0;
 
-    kl = 0.0;
-    pairs = 0.0;
     for (int sg = wave; wave < nwaves && sg < a.n_seg; sg += nwaves) {
         const SegP S = a.segs[sg];
         // lanes: plane pl of the segment and chunk ch; a segment of at most 32
@@ -732,13 +731,12 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     }
 }
 
+// One line per workgroup, in the order a.order (longest first).
 template <int MODE>
 __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_tof(ProjArgs a) {
     extern __shared__ float4 smem4[];
-    const int jv = blockIdx.x / a.n_rad;
-    const int k = blockIdx.x - jv * a.n_rad;
-    double kl, pairs;
-    line_tof_body<MODE>(a, a.views[jv] * a.n_rad + k, reinterpret_cast<float *>(smem4), blockDim.x >> 6, kl, pairs);
+    double kl = 0.0, pairs = 0.0;
+    line_tof_body<MODE>(a, a.order[blockIdx.x], reinterpret_cast<float *>(smem4), blockDim.x >> 6, kl, pairs);
     if (MODE != M_FWD && MODE != M_BACK && a.partial) block_sums(kl, pairs, a.partial, MODE == M_COUNT);
 }
 
@@ -785,7 +783,7 @@ __global__ void __launch_bounds__(64 * TOF_MAX_WAVES) k_line_batched(const BMemb
         const int view = snap ? jv : m.views[st.subset * m.views_stride + jv];
         const int64_t g_off = snap ? (int64_t)(jv % m.n_sub) * m.g_slot : 0;
         if (m.is_tof) {
-            double kl, pairs;
+            double kl = 0.0, pairs = 0.0;
             line_tof_body<M_GRAD>(m.pa, view * n_rad + k, smem, min(m.tof_waves, nw), kl, pairs, g_off);
         } else {
             line_nt_body<M_GRAD>(m.pa, view * n_rad + k, smem, g_off);
@@ -854,7 +852,7 @@ hipError_t launch_line_batched(const BMember *mem, const int *order, int n_mem, 
 }
 
 int n_line_blocks(const pet_geom_s *g, int subset) {
-    int nv = subset < 0 ? g->d.n_views : (int)g->subset_views[subset].size();
+    const int nv = subset < 0 ? g->d.n_views : (int)g->subset_views[subset].size();
     return nv * g->d.n_rad;
 }
 
