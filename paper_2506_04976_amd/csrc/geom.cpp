@@ -215,7 +215,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     for (int i = 0; i < d.n_subsets; ++i)
         for (size_t j = 0; j < g->subset_views[i].size(); ++j) hviews[(size_t)i * d.n_views + j] = g->subset_views[i][j];
     for (int v = 0; v < d.n_views; ++v) hviews[(size_t)d.n_subsets * d.n_views + v] = v;
-    // TOF line launches: the lines of each subset (then of all views),
+    // line launches: the lines of each subset (then of all views),
     // longest first (a line's work grows with its rows), so that the last
     // workgroups of a launch run short lines
     std::vector<int> horder;

@@ -89,7 +89,7 @@ struct ProjArgs {
     float *out;
     double *partial;  // one double per block (KL sum), or null
     TofTable tof;
-    // TOF line kernels: workgroup b takes line order[b], the launch's lines
+    // line kernels: workgroup b takes line order[b], the launch's lines
     // longest first (the hardware dispatches workgroups in index order)
     const int *order;
 };
@@ -158,8 +158,8 @@ struct pet_geom_s {
     int n_seg = 0, rows_max = 0, tof_ws = 0, tof_tstride = 0, tof_waves = 0;
     int *views_dev = nullptr;           // [n_subsets + 1][max(max_views, n_views)]; last row: all views
     int views_stride = 0;
-    // TOF line launches: per subset (then all views) the subset's lines,
-    // longest first, at line_order + order_off[row]
+    // line launches: per subset (then all views) the subset's lines, longest
+    // first, at line_order + order_off[row]
     int *line_order = nullptr;
     std::vector<int64_t> order_off;
     pet::TofTable tof{};

@@ -249,9 +249,8 @@ __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, floa
 template <int MODE>
 __global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
     extern __shared__ float4 smem4[];
-    const int jv = blockIdx.x / a.n_rad;
-    const int k = blockIdx.x - jv * a.n_rad;
-    const double kl = line_nt_body<MODE>(a, a.views[jv] * a.n_rad + k, reinterpret_cast<float *>(smem4));
+    // one line per workgroup, the launch's lines longest first
+    const double kl = line_nt_body<MODE>(a, a.order[blockIdx.x], reinterpret_cast<float *>(smem4));
     if (MODE != M_FWD && MODE != M_BACK && a.partial) block_sums(kl, kl, a.partial, MODE == M_COUNT);
 }
 
