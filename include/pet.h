@@ -363,6 +363,11 @@ pet_status pet_batch_destroy(pet_batch b);
 pet_status pet_batch_epochs(pet_batch b, int n_rounds, const int32_t *subset_seq, const float *tau,
                             const uint8_t *update_pc, int use_graph, void *stream);
 
+/* One round: pet_batch_epochs with n_rounds = 1 (member r's schedule is its
+ * n_subsets entries, members in creation order). */
+pet_status pet_batch_epoch(pet_batch b, const int32_t *subset_seq, const float *tau, const uint8_t *update_pc,
+                           int use_graph, void *stream);
+
 /* Launch-shape autotuner: times the batched subset-gradient step (subset 0 of
  * every member) for workgroup sizes of 16, 12 and 8 waves, one or two
  * workgroups per compute unit and two work-item orders (longest lines

@@ -28,7 +28,8 @@ EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "p
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
            "pet_svrg_epoch_ex", "pet_saga_epoch", "pet_sgd_epoch",
            "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
-           "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_autotune", "pet_batch_set_launch",
+           "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_epoch", "pet_batch_autotune",
+           "pet_batch_set_launch",
            "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
 PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
 PET_KERNEL_HVP = 6
@@ -114,6 +115,8 @@ def lib():
         L.pet_batch_destroy.argtypes = [P]
         L.pet_batch_epochs.argtypes = [P, I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(F),
                                        ctypes.POINTER(ctypes.c_uint8), I, P]
+        L.pet_batch_epoch.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(F), ctypes.POINTER(ctypes.c_uint8),
+                                      I, P]
         L.pet_batch_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(D), P]
         L.pet_batch_set_launch.argtypes = [P, I, I, I]
         L.pet_work_counts.argtypes = [P, I, P, P]
@@ -512,6 +515,21 @@ class Batch:
         m = len(seq)
         _check(lib().pet_batch_epochs(self.handle, n_rounds, (ctypes.c_int32 * m)(*seq), (ctypes.c_float * m)(*tau),
                                       (ctypes.c_uint8 * m)(*upd), 1 if use_graph else 0, _stream(stream)))
+
+    def epoch(self, subset_seqs, taus, update_pcs, use_graph=True, stream=None):
+        """One round (pet_batch_epoch): subset_seqs[r] (and taus[r], update_pcs[r]) hold
+        the n_subsets entries of member r."""
+        seq, tau, upd = [], [], []
+        for (g, _, _), s, t, u in zip(self.members, subset_seqs, taus, update_pcs):
+            s, t, u = list(s), list(t), list(u)
+            if not (len(s) == len(t) == len(u) == g.n_subsets):
+                raise ValueError("each member needs n_subsets schedule entries")
+            seq += [int(v) for v in s]
+            tau += [float(v) for v in t]
+            upd += [1 if v else 0 for v in u]
+        m = len(seq)
+        _check(lib().pet_batch_epoch(self.handle, (ctypes.c_int32 * m)(*seq), (ctypes.c_float * m)(*tau),
+                                     (ctypes.c_uint8 * m)(*upd), 1 if use_graph else 0, _stream(stream)))
 
     def autotune(self, stream=None):
         """(workgroups, waves per workgroup, order) of the fastest launch shape, and its step time in ms."""

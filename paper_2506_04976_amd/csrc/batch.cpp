@@ -316,6 +316,11 @@ extern "C" pet_status pet_batch_epochs(pet_batch b, int n_rounds, const int32_t 
     return hip_check(e, "pet_batch_epochs");
 }
 
+extern "C" pet_status pet_batch_epoch(pet_batch b, const int32_t *subset_seq, const float *tau,
+                                      const uint8_t *update_pc, int use_graph, void *stream) {
+    return pet_batch_epochs(b, 1, subset_seq, tau, update_pc, use_graph, stream);
+}
+
 extern "C" pet_status pet_batch_autotune(pet_batch b, int *config_out, double *best_ms_out, void *stream) {
     if (!b) return fail(PET_E_ARG, "pet_batch_autotune: null batch");
     hipStream_t cs = (hipStream_t)stream;

@@ -49,6 +49,8 @@ def test_argument_errors_without_gpu_work():
     assert L.pet_svrg_epoch_ex(None, None, None, None, None, None, None, None, None) == 1
     assert L.pet_batch_set_launch(None, 64, 8, 0) == 1
     assert b"null" in L.pet_last_error()
+    assert L.pet_batch_epoch(None, None, None, None, 1, None) == 1
+    assert b"null" in L.pet_last_error()
 
 
 @pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU refusal")

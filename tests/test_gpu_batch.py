@@ -98,6 +98,29 @@ def test_batch_matches_individual_runs(members, use_graph):
     b.close()
 
 
+def test_batch_single_rounds_match_individual_runs(members):
+    # pet_batch_epoch: one round per call, the schedule refreshed between calls
+    pm = members[0].pm
+    E = 2
+    ref = [m.runner() for m in members]
+    for m, (g, st, x) in zip(members, ref):
+        orders, taus, upd = m.schedule(E)
+        for e in range(E):
+            pm.pet_svrg_epoch(g, st, x, orders[e], taus[e], upd[e])
+    runs = [m.runner() for m in members]
+    b = pm.Batch(runs)
+    scheds = [m.schedule(E) for m in members]
+    for e in range(E):
+        b.epoch([s[0][e] for s in scheds], [s[1][e] for s in scheds], [s[2][e] for s in scheds])
+    torch.cuda.synchronize()
+    for m, (_, st1, x1), (_, st2, x2) in zip(members, ref, runs):
+        assert _rel(x2, x1) <= 1e-5, m.cfg["name"]
+        assert st2.k == st1.k == E * m.cfg["n_subsets"]
+    with pytest.raises(ValueError):
+        b.epoch([s[0][0][:-1] for s in scheds], [s[1][0] for s in scheds], [s[2][0] for s in scheds])
+    b.close()
+
+
 def test_batch_member_matches_oracle(members):
     pm = members[0].pm
     E = 3
