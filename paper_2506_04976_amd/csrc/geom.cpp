@@ -338,6 +338,54 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
         need += (size_t)g->tof_waves * per_wave;
     }
     g->lds_bytes = need;
+    // Segment order of the TOF line kernel, whose wave w takes entries w,
+    // w + W, w + 2W, ... (W waves): the two halves -k and +k of a pair of
+    // single segments have the same oblique length and so the same weight
+    // table, and go to consecutive rounds of one wave, which then fills the
+    // table once (both carry the same squared axial extent).  The other
+    // entries keep their relative order.
+    if (d.n_tof > 1 && g->tof_waves > 1) {
+        const int W = g->tof_waves, ns = (int)hsegs.size();
+        auto ring_k = [&](const SegP &sg) { return std::abs(planes[sg.p0].r2 - planes[sg.p0].r1); };
+        auto single = [&](const SegP &sg) { return planes[sg.p0].seg == planes[sg.p0 + sg.np - 1].seg; };
+        std::vector<int> cap(W);
+        for (int w = 0; w < W; ++w) cap[w] = ns / W + (w < ns % W ? 1 : 0);
+        std::vector<std::vector<int>> lists(W);
+        std::vector<int> rest;
+        int w = 0;
+        for (int i = 0; i < ns; ++i) {
+            const bool pair = i + 1 < ns && single(hsegs[i]) && single(hsegs[i + 1]) && ring_k(hsegs[i]) > 0 &&
+                              ring_k(hsegs[i]) == ring_k(hsegs[i + 1]);
+            if (!pair) {
+                rest.push_back(i);
+                continue;
+            }
+            hsegs[i + 1].dz2 = hsegs[i].dz2;
+            int tries = 0;
+            while (tries < W && (int)lists[w].size() + 2 > cap[w]) {
+                w = (w + 1) % W;
+                ++tries;
+            }
+            if (tries < W) {
+                lists[w].push_back(i);
+                lists[w].push_back(i + 1);
+                w = (w + 1) % W;
+            } else {
+                rest.push_back(i);
+                rest.push_back(i + 1);
+            }
+            ++i;
+        }
+        // the remaining entries fill the free slots in position order
+        size_t next = 0;
+        for (int r = 0; r <= ns / W; ++r)
+            for (int v = 0; v < W; ++v)
+                if (r < cap[v] && r >= (int)lists[v].size()) lists[v].push_back(rest[next++]);
+        std::vector<SegP> ordered(ns);
+        for (int v = 0; v < W; ++v)
+            for (size_t r = 0; r < lists[v].size(); ++r) ordered[r * W + v] = hsegs[lists[v][r]];
+        hsegs.swap(ordered);
+    }
     if (g->lds_bytes > (size_t)max_lds) {
         delete g;
         return fail(PET_E_ARG, "pet_geom_create: image too large for the LDS sheets of the line kernels (" +

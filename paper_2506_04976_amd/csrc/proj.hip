@@ -517,6 +517,11 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     const int na_l = lane < a.tof.n_int ? a.tof.na[lane] : 0;
     const int bf_l = lane < a.tof.n_int ? a.tof.bf[lane] : 0;
 
+    // segments -k and +k have the same oblique length and so the same weight
+    // table: the segment list puts such pairs in consecutive rounds of a wave,
+    // which then fills the table once
+    float table_dz2 = -1.f;
+    int cut = 0;
     for (int sg = wave; wave < nwaves && sg < a.n_seg; sg += nwaves) {
         const SegP S = a.segs[sg];
         // lanes: plane pl of the segment and chunk ch; a segment of at most 32
@@ -550,7 +555,10 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                 }
             }
         } else {
-            const int cut = nrow > 0 ? fill_table(a, L, len, cuts, w4, w1) : 0;
+            if (S.dz2 != table_dz2) {
+                cut = nrow > 0 ? fill_table(a, L, len, cuts, w4, w1) : 0;
+                table_dz2 = S.dz2;
+            }
             // axial sample position of row i: xz = zA * i + zB
             // padded axial cell of row i: u = zA * i + zB (z + PADZ)
             const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
@@ -719,7 +727,7 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                     }
                 }
             }
-            // the next segment overwrites this wave's table
+            // the next segment may overwrite this wave's table
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
