@@ -521,7 +521,6 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
     // table: the segment list puts such pairs in consecutive rounds of a wave,
     // which then fills the table once
     float table_dz2 = -1.f;
-    int cut = 0;
     for (int sg = wave; wave < nwaves && sg < a.n_seg; sg += nwaves) {
         const SegP S = a.segs[sg];
         // lanes: plane pl of the segment and chunk ch; a segment of at most 32
@@ -555,9 +554,12 @@ __device__ __forceinline__ void line_tof_body(const ProjArgs &a, int line, float
                 }
             }
         } else {
+            int cut = 0;
             if (S.dz2 != table_dz2) {
                 cut = nrow > 0 ? fill_table(a, L, len, cuts, w4, w1) : 0;
                 table_dz2 = S.dz2;
+            } else if (nrow > 0 && lane <= a.tof.n_int) {
+                cut = cuts[lane];  // kept in the table by the fill
             }
             // axial sample position of row i: xz = zA * i + zB
             // padded axial cell of row i: u = zA * i + zB (z + PADZ)
