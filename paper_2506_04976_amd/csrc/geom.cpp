@@ -302,6 +302,9 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     }
     g->n_seg = (int)hsegs.size();
     g->rows_max = rows_max;
+    // non-TOF: one thread per plane, in as many waves as the planes need (up to
+    // 16; more resident waves hide the LDS latency of the sample loop)
+    g->nt_threads = std::min(NT_BLOCK, std::max(64, (g->n_planes + 63) / 64 * 64));
     if (d.n_tof > 1) {
         for (auto &sg : hsegs)
             if (sg.np > 64) {

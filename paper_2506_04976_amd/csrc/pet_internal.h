@@ -21,7 +21,7 @@ constexpr int PADZ = 2;
 constexpr int NT_MAX = 32;     // TOF bins supported
 constexpr int NT_BLK = 16;     // TOF bins a lane holds in registers at once
 constexpr int NINT_MAX = 2 * NT_MAX - 1;  // intervals between the 2 n_tof window edges
-constexpr int NT_BLOCK = 768;   // non-TOF line kernel: threads per workgroup
+constexpr int NT_BLOCK = 1024;  // non-TOF line kernel: most threads per workgroup (16 waves)
 constexpr int IMG_BLOCK = 256;  // image-space kernels: threads per workgroup
 constexpr int TOF_MAX_WAVES = 16;  // TOF line kernel: at most 16 segment waves
 constexpr int WS_MAX = 8;       // TOF bins overlapping one point
@@ -156,6 +156,7 @@ struct pet_geom_s {
     pet::PlaneP *planes = nullptr;
     pet::SegP *segs = nullptr;
     int n_seg = 0, rows_max = 0, tof_ws = 0, tof_tstride = 0, tof_waves = 0;
+    int nt_threads = pet::NT_BLOCK;     // non-TOF line kernel: threads per workgroup
     int *views_dev = nullptr;           // [n_subsets + 1][max(max_views, n_views)]; last row: all views
     int views_stride = 0;
     // line launches: per subset (then all views) the subset's lines, longest

@@ -807,7 +807,7 @@ hipError_t launch_mode(const pet_geom_s *g, dim3 grid, const ProjArgs &a, hipStr
     if (g->d.n_tof > 1)
         hipLaunchKernelGGL((k_line_tof<MODE>), grid, dim3(64 * g->tof_waves), lds, s, a);
     else
-        hipLaunchKernelGGL((k_line_nt<MODE>), grid, dim3(NT_BLOCK), lds, s, a);
+        hipLaunchKernelGGL((k_line_nt<MODE>), grid, dim3(g->nt_threads), lds, s, a);
     return hipGetLastError();
 }
 
