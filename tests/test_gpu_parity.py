@@ -137,6 +137,28 @@ def test_subset_grad_and_kl_parity(case):
         assert float(kl.cpu()) == pytest.approx(kl_ref, rel=1e-5)
 
 
+def test_count_dtypes_agree(case):
+    # the same counts stored as uint8 (when they fit), uint16 and float32 give
+    # the same fused gradient and KL (the kernels convert every count to FP32)
+    pm = case.pm
+    y_np = case.d["y"].ravel()
+    ys = {"u16": torch.from_numpy(y_np.astype(np.uint16)).to(case.dev),
+          "f32": torch.from_numpy(y_np.astype(np.float32)).to(case.dev)}
+    if y_np.max() <= 255:
+        ys["u8"] = torch.from_numpy(y_np.astype(np.uint8)).to(case.dev)
+    subset = case.cfg["n_subsets"] - 1
+    out = {}
+    for name, y in ys.items():
+        g = torch.empty(case.geom.n_vox, device=case.dev)
+        kl = torch.zeros(1, dtype=torch.float64, device=case.dev)
+        pm.pet_subset_grad(case.geom, subset, case.x, y, case.r, case.a, g, kl)
+        out[name] = (g.cpu().double().numpy(), float(kl.cpu()))
+    g0, kl0 = out["f32"]
+    for name, (g, kl) in out.items():
+        assert np.linalg.norm(g - g0) <= 1e-6 * np.linalg.norm(g0), name
+        assert kl == pytest.approx(kl0, rel=1e-9), name
+
+
 def test_rdp_parity(case):
     pm = case.pm
     w27 = pm.rdp_weights27(case.cfg["vx"], case.cfg["vy"], case.cfg["vz"])
