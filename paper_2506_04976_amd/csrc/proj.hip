@@ -180,16 +180,29 @@ __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, floa
     if (nrow > 0 && MODE != M_COUNT) build_sheets<NEED_X, NEED_Z>(a, L, nrow, X, Z);
     __syncthreads();
 
+    // planes in rounds of blockDim threads; the planes of a last, partial round
+    // take c threads each (c a power of two: the threads of a plane are lanes of
+    // one wave), which split its rows and add their forward sums by shuffles
+    const int nb = blockDim.x;
+    const int full = a.n_planes / nb * nb;
+    const int rem = a.n_planes - full;
+    int c = 1;
+    while (rem > 0 && c < 64 && rem * (2 * c) <= nb) c *= 2;
     double kl = 0.0;
-    for (int p = threadIdx.x; p < a.n_planes; p += blockDim.x) {
-        const PlaneP P = a.planes[p];
+    for (int base = 0; base < a.n_planes; base += nb) {
+        const bool tail = base >= full;
+        const int cc = tail ? c : 1;
+        const int p = base + (tail ? (int)threadIdx.x / c : (int)threadIdx.x);
+        const int ch = tail ? (int)threadIdx.x % c : 0;
+        const bool act = p < a.n_planes;
+        const PlaneP P = a.planes[act ? p : 0];
         const int64_t lor = (int64_t)line * a.n_planes + p;
         const float len = sqrtf(L.lt2 + P.dz2);
         const float ell = L.vm_um * len;
         int is = 0, ie = -1;
-        if (nrow > 0) z_clip(L, P, a.nz, is, ie);
+        if (act && nrow > 0) z_clip(L, P, a.nz, is, ie);
         if constexpr (MODE == M_COUNT) {
-            if (ie >= is) kl += (double)(ie - is + 1);
+            if (ch == 0 && ie >= is) kl += (double)(ie - is + 1);
             continue;
         }
         // padded axial cell of sample i: u = zA i + zB = z + PADZ, clamped to
@@ -199,14 +212,16 @@ __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, floa
         const float umax = (float)(a.nz + PADZ);
         float s = 0.f;
         if (NEED_X) {
-            const float *xr = X + (is - L.i_lo) * rz;
-            for (int i = is; i <= ie; ++i, xr += rz) {
+            const float *xr = X + (is + ch - L.i_lo) * rz;
+            for (int i = is + ch; i <= ie; i += cc, xr += cc * rz) {
                 const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
                 const int j = (int)u;
                 const float x0 = xr[j], x1 = xr[j + 1];
                 s += fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
             }
+            for (int o = 1; o < cc; o <<= 1) s += __shfl_xor(s, o, 64);
         }
+        if (!act) continue;
         const float m = a.mult ? a.mult[lor] : 1.f;
         float Q = 0.f;
         if constexpr (MODE == M_BACK) {
@@ -219,18 +234,18 @@ __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, floa
         } else {
             float ybar = fmaf(m, s * ell, a.add ? a.add[lor] : 0.f);
             if constexpr (MODE == M_FWD) {
-                a.out[lor] = ybar;
+                if (ch == 0) a.out[lor] = ybar;
                 continue;
             } else {
                 float yv = load_y(a.y, a.y_dtype, lor);
-                if (a.partial) kl += kl_term(ybar, yv);
+                if (a.partial && ch == 0) kl += kl_term(ybar, yv);
                 if constexpr (MODE == M_GRAD) Q = m * (1.f - yv / ybar) * ell;
                 if constexpr (MODE == M_EM) Q = m * (yv / ybar) * ell;
             }
         }
         if constexpr (NEED_Z) {
-            double *zr = Z + (is - L.i_lo) * rz;
-            for (int i = is; i <= ie; ++i, zr += rz) {
+            double *zr = Z + (is + ch - L.i_lo) * rz;
+            for (int i = is + ch; i <= ie; i += cc, zr += cc * rz) {
                 const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
                 const int j = (int)u;
                 const float a1 = Q * __builtin_amdgcn_fractf(u);
