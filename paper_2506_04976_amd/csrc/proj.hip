@@ -351,10 +351,10 @@ __device__ __forceinline__ void read_w(const float *w4, const float *w1, int e1,
 
 // Sample loops of one TOF interval: n rows walked in t order from row pointer
 // xr / zr (row of the first sample, z padding skipped), principal-plane index
-// fi stepping by dfi and row stride drz, taking every wstep-th row of the
-// interval (a lane's row chunk).  The weights of a row are the same for every
-// lane of a chunk (broadcast LDS reads); the axial position of a sample in
-// plane i is zA * i + zB (voxel units).
+// fi stepping by dfi and row stride drz, taking every wstep-th row (the line
+// kernels walk every row: wstep = 1).  The weights of a row are the same for
+// every lane that walks it (broadcast LDS reads when the whole wave does); the
+// axial position of a sample in plane i is zA * i + zB (voxel units).
 template <int NA>
 __device__ __forceinline__ void read_wq(const float *wq, const float *w1q, float (&w)[NA]) {
     const float4 v = *reinterpret_cast<const float4 *>(wq);
