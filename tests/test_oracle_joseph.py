@@ -58,6 +58,86 @@ def test_delta_response_oblique_principal_axis(oracle_built):
     assert v == pytest.approx(0.7 * ell, rel=1e-13)
 
 
+def _oblique_line(cfg, centre, direction, offset_vox, half=60.0):
+    """Endpoints of a line with the given direction that crosses the principal
+    plane of `centre` (principal axis x) at `centre` + offset_vox * (0, vy, vz),
+    reaching `half` mm along x on either side; and the crossing point."""
+    c = np.array(centre, float)
+    hit = c + np.array([0.0, offset_vox[0] * cfg["vy"], offset_vox[1] * cfg["vz"]])
+    u = np.array(direction, float) / abs(direction[0])
+    return hit - half * u, hit + half * u, hit
+
+
+def test_delta_response_3d_line_varying_z(oracle_built):
+    # A 3D line with a slope in y and z (principal axis x, ring-difference-like
+    # tilt): at the x-plane of voxel column 5 it passes 0.2 voxel above the
+    # centre of voxel (5, 2, 4) in y and 0.35 voxel below it in z.  Unit deltas
+    # at the four voxels around that crossing answer with the bilinear weights
+    # (0.8 * 0.65, 0.2 * 0.65, 0.8 * 0.35, 0.2 * 0.35) times the step length
+    # l = vx |u| / |u_x|; a delta on the same plane but two voxels away in z
+    # answers 0.  The z-coordinate of the sample comes from the line parameter
+    # at that plane, so a slip in the axial interpolation changes these values.
+    cfg = _grid(9, 8, 7, 2.0, 2.5, 3.0)
+    direction = (1.0, 0.21, -0.37)  # |u_x|/vx = 0.5 > |u_z|/vz = 0.123 > |u_y|/vy = 0.084
+    p1, p2, _ = _oblique_line(cfg, _centre(cfg, 5, 2, 4), direction, (0.2, -0.35))
+    ell = 2.0 * math.sqrt(1.0 + 0.21 ** 2 + 0.37 ** 2)
+    want = {(5, 2, 4): 0.8 * 0.65, (5, 3, 4): 0.2 * 0.65, (5, 2, 3): 0.8 * 0.35, (5, 3, 3): 0.2 * 0.35,
+            (5, 2, 6): 0.0, (5, 4, 4): 0.0}
+    for (ix, iy, iz), w in want.items():
+        x = np.zeros((7, 8, 9))
+        x[iz, iy, ix] = 1.0
+        for a, b in ((p1, p2), (p2, p1)):  # either direction
+            v = projector.fwd(cfg, x, a[None], b[None])[0, 0]
+            assert v == pytest.approx(w * ell, rel=1e-13, abs=1e-15), (ix, iy, iz)
+
+
+def test_delta_response_3d_principal_y_negative_slopes(oracle_built):
+    # Principal axis y, x and z both decreasing along the line: crossing the
+    # y-plane of voxel (3, 6, 2) at +0.45 voxel in x and +0.1 voxel in z gives
+    # weights 0.55 * 0.9 at the voxel itself and 0.45 * 0.1 at (4, 6, 3).
+    cfg = _grid(8, 10, 6, 2.2, 1.8, 2.6)
+    c = np.array(_centre(cfg, 3, 6, 2))
+    hit = c + np.array([0.45 * 2.2, 0.0, 0.1 * 2.6])
+    u = np.array([-0.3, 1.0, -0.25])
+    p1, p2 = hit - 40 * u, hit + 40 * u
+    ell = 1.8 * math.sqrt(0.3 ** 2 + 1.0 + 0.25 ** 2)
+    for (ix, iy, iz), w in {(3, 6, 2): 0.55 * 0.9, (4, 6, 3): 0.45 * 0.1, (4, 6, 2): 0.45 * 0.9,
+                            (3, 6, 3): 0.55 * 0.1}.items():
+        x = np.zeros((6, 10, 8))
+        x[iz, iy, ix] = 1.0
+        assert projector.fwd(cfg, x, p1[None], p2[None])[0, 0] == pytest.approx(w * ell, rel=1e-13)
+
+
+def test_delta_response_3d_tof_hand_value(oracle_built):
+    # The same tilted line with TOF: the crossing point sits at a known signed
+    # distance t from the LOR centre (the centre is placed 31 mm before the
+    # crossing along the line), so each bin's answer is the bilinear weight,
+    # the step length and the bin's truncated-Gaussian mass
+    # 1/2 [erf(clamp((t_b + w/2 - t) / (sqrt2 sigma))) - erf(clamp((t_b - w/2 - t) / (sqrt2 sigma)))].
+    sig, wb = 9.0, 12.0
+    cfg = dict(_grid(9, 8, 7, 2.0, 2.5, 3.0), n_tof=7, tof_bin=wb, tof_sigma=sig, tof_nsigma=3.0)
+    direction = np.array([1.0, 0.21, -0.37])
+    unit = direction / np.linalg.norm(direction)
+    _, _, hit = _oblique_line(cfg, _centre(cfg, 5, 2, 4), direction, (0.2, -0.35))
+    mid = hit - 31.0 * unit
+    p1, p2 = mid - 70.0 * unit, mid + 70.0 * unit
+    ell = 2.0 * math.sqrt(1.0 + 0.21 ** 2 + 0.37 ** 2)
+    x = np.zeros((7, 8, 9))
+    x[4, 2, 5] = 1.0
+    got = projector.fwd(cfg, x, p1[None], p2[None])[0]
+    c = 3.0 / math.sqrt(2.0)
+
+    def E(d):
+        return math.erf(min(max(d / (math.sqrt(2.0) * sig), -c), c))
+
+    for b in range(7):
+        tb = (b - 3) * wb
+        w = 0.5 * (E(tb + wb / 2 - 31.0) - E(tb - wb / 2 - 31.0))
+        assert got[b] == pytest.approx(0.8 * 0.65 * ell * w, rel=1e-12, abs=1e-15), b
+    # bins 3 sigma + half a bin or more away from t = 31 mm receive nothing
+    assert got[0] == 0.0 and got[1] == 0.0
+
+
 def test_constant_image_axis_aligned(oracle_built):
     cfg = _grid(9, 8, 5, 1.5, 2.5, 3.5)
     x = np.full((5, 8, 9), 2.0)
