@@ -35,7 +35,9 @@
  *            thread-local message for the last non-OK status.  Domain
  *            preconditions (x >= 0, r > 0, y >= 0) are the caller's: values
  *            outside them give unspecified results (the paper's d(s, t) and R(x)
- *            are infinite there).
+ *            are infinite there) unless the handle's PET_CHECK flag is set
+ *            (pet_geom_set_flags), which turns them into PET_E_DOMAIN and a
+ *            non-finite objective into PET_E_NUMERIC.
  */
 #ifndef PET_H
 #define PET_H
@@ -134,6 +136,53 @@ pet_status pet_subset_grad(pet_geom g, int subset, const float *x, const void *y
                            const float *add, const float *mult, float *grad_out, double *kl_out,
                            void *stream);
 
+/* Zero-count-aware data term -------------------------------------------------
+ * The KL data fidelity has d(s, 0) = s (Section 1.2): a bin without counts
+ * adds mult P x + add to the objective and mult P^T 1 to the gradient at every
+ * x.  With sens_i = P_i^T mult (pet_back with sino = NULL on subset i),
+ *     grad D_i(x) = sens_i - P_i^T [mult y / ybar(x)],
+ *     D_i(x)      = <sens_i, x> + sum_i add - sum_i y + sum_{i, y > 0} y log(y / ybar(x)),
+ * where only bins with y > 0 enter the terms that depend on ybar.  A pet_counts
+ * object holds those bins of one data set (y, add, mult) on one geometry,
+ * compacted in sinogram order (16 bytes per bin: index within its transaxial
+ * line, y, add, mult), with per-line offsets and, per subset, its lines with
+ * counts ordered by decreasing count.  The kernels that use it take one
+ * workgroup per such line and one compacted bin per thread, walking only the
+ * samples inside the bin's TOF window.  The TOF weight of a sample at signed
+ * distance t from the LOR centre in bin b is the geometry's truncated,
+ * bin-integrated Gaussian, a function of d = t - t_b alone; it is tabulated
+ * from FP64 at 4097 nodes over its support |d| <= bin/2 + nsig sigma and
+ * interpolated linearly (C2's 40 mm bins and 60 mm FWHM: nodes 0.047 mm
+ * apart, interpolation error below 1e-6 of the largest weight).  Results equal
+ * those of the dense kernels up to rounding and that interpolation. */
+typedef struct pet_counts_s *pet_counts;
+
+/* Compact the bins with y > 0 of (y, add, mult) for geometry g (full
+ * sinograms; add, mult nullable: 0 and 1).  Synchronous; allocates the list
+ * and its index on the current device (the inputs may be freed afterwards).
+ * PET_E_ARG if the geometry's sheets and TOF table exceed the LDS; PET_E_OOM if
+ * device allocation fails. */
+pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, const float *add, const float *mult,
+                             pet_counts *out);
+pet_status pet_counts_destroy(pet_counts c);
+
+/* Bins with counts of `subset` (-1: all) and the FP64 sums of y and of add over
+ * all of its bins.  Any output pointer may be NULL. */
+pet_status pet_counts_info(pet_counts c, int subset, int64_t *n_items, double *sum_y, double *sum_add);
+
+/* Subset gradient from the compacted bins: grad_out = sens_subset -
+ * P_i^T [mult y / ybar] with ybar = mult P_i x + add, or, with sens_subset NULL,
+ * the part that depends on x, -P_i^T [mult y / ybar], alone.  kl_out (device
+ * double, nullable; needs sens_subset) receives D_i(x) in FP64 as above.
+ * PET_E_ARG if c was made for another geometry. */
+pet_status pet_subset_grad_counts(pet_geom g, pet_counts c, int subset, const float *x, const float *sens_subset,
+                                  float *grad_out, double *kl_out, void *stream);
+
+/* pet_objective from the compacted bins: D(A x + r, y) + beta S(x) in FP64
+ * (device double), with sens = P^T mult over all subsets. */
+pet_status pet_objective_counts(pet_geom g, pet_counts c, const float *x, const float *sens, const float *kappa,
+                                const float w[27], float beta, float gamma, float eps, double *out, void *stream);
+
 /* Relative difference prior (eq. (rdp)) and its derivatives (Appendix A),
  * scaled by beta: grad_out = beta dS/dx, hessdiag_out = beta d2S/dx2 (nullable),
  * value_out = beta S (device double, nullable).  w[27]: weight of neighbour
@@ -193,6 +242,15 @@ typedef struct {
     double *bb;
     float *g_prev;
     double *gnorm;
+    /* Zero-count-aware path (nullable): a pet_counts made from this state's y,
+     * add and mult on the same geometry.  When set, pet_svrg_epoch(_ex) walks
+     * only the bins with counts: the sensitivity terms P_i^T mult cancel in
+     * n (grad D_i(x) - ghat_i), so ghat_i holds -P_i^T[mult y / ybar(xhat)] and
+     * ghat = sens + sum_i ghat_i, the same full gradient as the dense path;
+     * objective_out is computed from the compacted bins.  The iterates equal
+     * the dense path's up to rounding.  Not with gnorm (PET_E_ARG).  SAGA, SGD,
+     * the reverse mode and batches use the dense kernels (PET_E_ARG if set). */
+    pet_counts counts;
 } pet_svrg_state;
 
 /* One epoch = n_subsets iterations of Algorithm 1 with the nonnegativity
@@ -381,6 +439,33 @@ pet_status pet_batch_autotune(pet_batch b, int *config_out, double *best_ms_out,
  * 1 = creation order); PET_E_ARG if the sheets do not fit. */
 pet_status pet_batch_set_launch(pet_batch b, int workgroups, int waves, int order);
 
+/* Debug checks -------------------------------------------------------------
+ * pet_geom_set_flags(g, PET_CHECK) makes the entry points of this handle check
+ * the domain of the problem on the device before their work and wait for the
+ * result (the calls become synchronous), returning PET_E_DOMAIN with a message
+ * naming the argument and the number of offending elements when
+ *   an image x (or sens, kappa, a preconditioner's Hessian diagonal) has a
+ *     negative or non-finite voxel: the prior R(x) is +inf for x < 0
+ *     (eq. (prior)), the problem's domain is x >= 0;
+ *   the counts y have a negative or non-finite bin: d(s, t) = +inf for t < 0
+ *     (Section 1.2);
+ *   the background add is negative, non-finite, or 0 in a bin with y > 0
+ *     (add NULL with any y > 0 counts as such): with x >= 0 and mult >= 0,
+ *     add > 0 is what keeps s = mult P x + add > 0 where t > 0, and
+ *     d(s, t) = +inf for s <= 0 with t > 0 (Section 1.2);
+ *   mult has a negative or non-finite entry; a sinogram passed to pet_back,
+ *     or pet_fwd's add, has a non-finite entry.
+ * Whole arrays are checked (all views).  Entry points that produce the FP64
+ * objective (pet_objective, and the epoch functions given objective_out) then
+ * wait for it and return PET_E_NUMERIC if it is not finite.  Checked:
+ * pet_fwd, pet_back, pet_subset_grad, pet_rdp_grad_hessdiag,
+ * pet_precond, pet_osem_epoch, pet_objective, pet_svrg_epoch(_ex),
+ * pet_saga_epoch, pet_sgd_epoch, pet_subset_hvp.  Without the flag (the
+ * default) nothing is checked and values outside the domain give unspecified
+ * results.  flags: 0 or PET_CHECK (PET_E_ARG otherwise). */
+enum { PET_CHECK = 1 };
+pet_status pet_geom_set_flags(pet_geom g, unsigned flags);
+
 /* Instrumentation --------------------------------------------------------
  * Work of the line kernels on `subset` (-1: all), exactly as they traverse it:
  * out[0] = Joseph samples, out[1] = sample-TOF-bin pairs with nonzero weight
@@ -392,7 +477,7 @@ pet_status pet_work_counts(pet_geom g, int subset, double *out, void *stream);
  * one kernel (PET_KERNEL_*) since the last read; reading synchronises on the
  * recorded events and resets that kernel's record. */
 enum { PET_KERNEL_FWD = 0, PET_KERNEL_BACK = 1, PET_KERNEL_GRAD = 2, PET_KERNEL_EM = 3, PET_KERNEL_OBJ = 4,
-       PET_KERNEL_HVP = 6 };
+       PET_KERNEL_HVP = 6, PET_KERNEL_COUNTS = 7 /* zero-count-aware line kernel, every mode */ };
 pet_status pet_profile_enable(pet_geom g, int enable);
 pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms, int64_t *launches);
 

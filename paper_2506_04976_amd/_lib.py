@@ -20,19 +20,24 @@ PET_SCANNER_CYLINDER = 1
 PET_BACK_AUTO = 0
 PET_BACK_SCATTER = 1
 PET_Y_F32, PET_Y_U16, PET_Y_U8 = 0, 1, 2
+PET_CHECK = 1
 
 _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "PET_E_HIP",
            5: "PET_E_NUMERIC", 6: "PET_E_STATE"}
 
 EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
+
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
            "pet_svrg_epoch_ex", "pet_saga_epoch", "pet_sgd_epoch",
            "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
            "pet_batch_create", "pet_batch_destroy", "pet_batch_epochs", "pet_batch_epoch", "pet_batch_autotune",
            "pet_batch_set_launch",
-           "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_last_error"]
+           "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_geom_set_flags",
+           "pet_counts_create", "pet_counts_destroy", "pet_counts_info", "pet_subset_grad_counts",
+           "pet_objective_counts", "pet_last_error"]
 PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
 PET_KERNEL_HVP = 6
+PET_KERNEL_COUNTS = 7
 
 
 class PetError(RuntimeError):
@@ -59,7 +64,8 @@ class SvrgState(ctypes.Structure):
                 ("kappa", ctypes.c_void_p), ("w", ctypes.c_float * 27), ("beta", ctypes.c_float),
                 ("gamma", ctypes.c_float), ("eps", ctypes.c_float), ("alpha", ctypes.c_float),
                 ("delta", ctypes.c_float), ("omega", ctypes.c_int), ("k", ctypes.c_int64),
-                ("bb", ctypes.c_void_p), ("g_prev", ctypes.c_void_p), ("gnorm", ctypes.c_void_p)]
+                ("bb", ctypes.c_void_p), ("g_prev", ctypes.c_void_p), ("gnorm", ctypes.c_void_p),
+                ("counts", ctypes.c_void_p)]
 
 
 class SvrgOptions(ctypes.Structure):
@@ -121,6 +127,12 @@ def lib():
         L.pet_batch_set_launch.argtypes = [P, I, I, I]
         L.pet_work_counts.argtypes = [P, I, P, P]
         L.pet_profile_enable.argtypes = [P, I]
+        L.pet_geom_set_flags.argtypes = [P, ctypes.c_uint]
+        L.pet_counts_create.argtypes = [P, P, I, P, P, ctypes.POINTER(P)]
+        L.pet_counts_destroy.argtypes = [P]
+        L.pet_counts_info.argtypes = [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.pet_subset_grad_counts.argtypes = [P, P, I, P, P, P, P, P]
+        L.pet_objective_counts.argtypes = [P, P, P, P, P, ctypes.POINTER(F), F, F, F, P, P]
         L.pet_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
@@ -232,6 +244,10 @@ class Geometry:
 
 
 # ---- entry points (same names as the C ABI) ---------------------------------
+
+def pet_geom_set_flags(geom, flags):
+    _check(lib().pet_geom_set_flags(geom.handle, int(flags)))
+
 
 def pet_fwd(geom, subset, x, mult, add, out, stream=None):
     _check(lib().pet_fwd(geom.handle, subset, _ptr(x, torch.float32, geom.n_vox, "x"),
@@ -404,11 +420,58 @@ def pet_profile_read(geom, kernel):
     return ms.value, n.value
 
 
+class Counts:
+    """Owns a pet_counts handle: the bins with counts of (y, add, mult) on a
+    geometry, compacted on the device."""
+
+    def __init__(self, geom, y, add, mult):
+        h = ctypes.c_void_p()
+        _check(lib().pet_counts_create(geom.handle, _ptr(y, None, geom.n_bins, "y"), y_dtype_code(y),
+                                       _ptr(add, torch.float32, geom.n_bins, "add"),
+                                       _ptr(mult, torch.float32, geom.n_lors, "mult"), ctypes.byref(h)))
+        self.handle = h
+        self.geom = geom
+
+    def info(self, subset=-1):
+        n = ctypes.c_int64()
+        sy, sa = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pet_counts_info(self.handle, subset, ctypes.byref(n), ctypes.byref(sy), ctypes.byref(sa)))
+        return n.value, sy.value, sa.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pet_counts_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pet_subset_grad_counts(geom, counts, subset, x, sens_subset, grad_out, kl_out=None, stream=None):
+    _check(lib().pet_subset_grad_counts(geom.handle, counts.handle, subset, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                        _ptr(sens_subset, torch.float32, geom.n_vox, "sens_subset"),
+                                        _ptr(grad_out, torch.float32, geom.n_vox, "grad_out"),
+                                        _ptr(kl_out, torch.float64, 1, "kl_out"), _stream(stream)))
+    return grad_out
+
+
+def pet_objective_counts(geom, counts, x, sens, kappa, w27, beta, gamma, eps, out, stream=None):
+    _check(lib().pet_objective_counts(geom.handle, counts.handle, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                      _ptr(sens, torch.float32, geom.n_vox, "sens"),
+                                      _ptr(kappa, torch.float32, geom.n_vox, "kappa"), _w27(w27), beta, gamma, eps,
+                                      _ptr(out, torch.float64, 1, "out"), _stream(stream)))
+    return out
+
+
 class SvrgStateBuffers:
-    """Device buffers + the C state struct of preconditioned SVRG."""
+    """Device buffers + the C state struct of preconditioned SVRG.  counts (a
+    Counts made from the same y, add, mult) selects the zero-count-aware path."""
 
     def __init__(self, geom, y, add, mult, sens, beta, gamma, eps, alpha=1.0, delta=0.0, w27=None, kappa=None,
-                 omega=2, bb=False, gnorm=False):
+                 omega=2, bb=False, gnorm=False, counts=None):
         dev = y.device
         n, nv = geom.n_subsets, geom.n_vox
         self.ghat_i = torch.zeros((n, nv), dtype=torch.float32, device=dev)
@@ -442,6 +505,8 @@ class SvrgStateBuffers:
         c.beta, c.gamma, c.eps, c.alpha, c.delta = float(beta), float(gamma), float(eps), float(alpha), float(delta)
         c.omega = int(omega)
         c.k = 0
+        c.counts = counts.handle.value if counts is not None else None
+        self.counts = counts
         self.c = c
 
     @property

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 
 #include "pet_internal.h"
@@ -57,6 +58,83 @@ ProjArgs base_args(pet_geom g, int subset) {
     a.order = g->line_order + g->order_off[subset < 0 ? g->d.n_subsets : subset];
     return a;
 }
+
+// ---- debug checks (PET_CHECK) ---------------------------------------------
+// One condition on one argument: p (float array of n elements; null for the
+// conditions on y alone) and the message that names it.
+struct Dom {
+    const float *p;
+    int kind;
+    int64_t n;
+    const char *what;
+};
+
+// Counts the violations of every condition on the device (one counter each),
+// waits for them and returns PET_E_DOMAIN naming the first violated one.
+// Conditions on a null array are skipped (except those on y alone).
+pet_status check_domain(unsigned *counts, hipStream_t s, const char *fn, const void *y, int ydt,
+                        std::initializer_list<Dom> list) {
+    hipError_t e = launch_fill_u32(counts, CHECK_SLOTS, 0u, s);
+    int k = 0;
+    for (const Dom &d : list) {
+        const bool y_only = d.kind == CHK_COUNTS || d.kind == CHK_NO_ADD;
+        if (e == hipSuccess && k < CHECK_SLOTS && (d.p || (y_only && y)))
+            e = launch_domain_count(d.p, d.kind, d.n, y, ydt, counts + k, s);
+        ++k;
+    }
+    unsigned h[CHECK_SLOTS] = {};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, counts, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(e, fn);
+    k = 0;
+    for (const Dom &d : list) {
+        if (k < CHECK_SLOTS && h[k]) return fail(PET_E_DOMAIN, std::string(fn) + ": " + std::to_string(h[k]) + " " + d.what);
+        ++k;
+    }
+    return PET_OK;
+}
+
+constexpr const char *MSG_X = "image voxels are negative or not finite (the prior R(x) is +inf for x < 0, eq. (prior))";
+constexpr const char *MSG_Y = "count bins are negative or not finite (d(s, t) = +inf for t < 0, Section 1.2)";
+constexpr const char *MSG_ADD = "background bins are negative, not finite, or 0 where y > 0 (r > 0 keeps d(s, t) "
+                                "finite where t > 0, Section 1.2)";
+constexpr const char *MSG_NO_ADD = "bins have counts y > 0 but no background was given (r > 0 keeps d(s, t) finite "
+                                   "where t > 0, Section 1.2)";
+constexpr const char *MSG_MULT = "multiplicative factors are negative or not finite";
+
+}  // namespace
+
+// Checks of an entry point's image x and data (y, add, mult), with the
+// counters at `counts` (CHECK_SLOTS of them).
+pet_status check_data(pet_geom g, unsigned *counts, hipStream_t s, const char *fn, const float *x, const void *y,
+                      int ydt, const float *add, const float *mult) {
+    int64_t nb = 0, nl = 0;
+    pet_geom_info(g, -1, &nb, &nl, nullptr);
+    return check_domain(counts, s, fn, y, ydt,
+                        {{x, CHK_NONNEG, g->n_vox, MSG_X},
+                         {nullptr, CHK_COUNTS, nb, MSG_Y},
+                         {add, add ? CHK_ADD : CHK_NO_ADD, nb, add ? MSG_ADD : MSG_NO_ADD},
+                         {mult, CHK_NONNEG, nl, MSG_MULT}});
+}
+
+namespace {
+
+// PET_CHECK: waits for a device FP64 objective and returns PET_E_NUMERIC if it
+// is not finite.
+pet_status check_numeric(hipStream_t s, const double *val, const char *fn) {
+    double h = 0.0;
+    hipError_t e = hipMemcpyAsync(&h, val, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(e, fn);
+    if (!std::isfinite(h)) return fail(PET_E_NUMERIC, std::string(fn) + ": the FP64 objective is not finite");
+    return PET_OK;
+}
+
+}  // namespace
+
+bool checking(const pet_geom_s *g) { return (g->flags & PET_CHECK) != 0; }
+
+namespace {
 
 // Data-term gradient of one subset into the gradient sheets (G0, G1); the
 // image sheets must already hold x.  Optionally FP64 KL sum into kl_out.
@@ -115,6 +193,35 @@ hipError_t hvp_impl(pet_geom g, int subset, const float *x, const float *v, cons
     return e;
 }
 
+// Zero-count-aware part of one subset's gradient, -P_i^T[mult y / ybar], into
+// the gradient sheets (the image sheets must hold x); optionally the FP64 sum
+// of y log(y / ybar) over the subset's bins with counts into *ylogy_out.
+hipError_t counts_grad_sheets(pet_geom g, const pet_counts_s *c, int subset, double *ylogy_out, hipStream_t s) {
+    hipError_t e = launch_zero_sheets(g, s);
+    ProjArgs a = base_args(g, subset);
+    a.partial = ylogy_out ? g->partial : nullptr;
+    if (e == hipSuccess) e = launch_line_counts(g, c, M_GRAD, subset, a, s);
+    if (e == hipSuccess && ylogy_out) e = launch_reduce_sum(g->partial, counts_blocks(c, subset), ylogy_out, 0, s);
+    return e;
+}
+
+// D(x) from the compacted bins, <sens, x> + sum add - sum y + sum y log(y / ybar)
+// (all subsets), plus beta S(x), into *out.
+hipError_t objective_counts_impl(pet_geom g, const pet_counts_s *c, const float *x, const float *sens,
+                                 const float *kappa, const float *w27, float beta, float gamma, float eps,
+                                 double *out, hipStream_t s) {
+    hipError_t e = launch_to_sheets(g, x, s);
+    ProjArgs a = base_args(g, -1);
+    a.partial = g->partial;
+    if (e == hipSuccess) e = launch_line_counts(g, c, M_OBJ, -1, a, s);
+    if (e == hipSuccess) e = launch_reduce_sum(g->partial, counts_blocks(c, -1), out, 0, s);
+    if (e == hipSuccess) e = launch_dot(sens, x, g->n_vox, g->partial, out, 1, s);
+    if (e == hipSuccess) e = launch_add_scalar(out, c->sum_add[c->n_subsets] - c->sum_y[c->n_subsets], s);
+    if (e == hipSuccess) e = launch_rdp(g, x, kappa, w27, beta, gamma, eps, nullptr, nullptr, g->partial, s);
+    if (e == hipSuccess) e = launch_reduce_sum(g->partial, rdp_blocks(g), out, 1, s);
+    return e;
+}
+
 }  // namespace
 
 ProjArgs geom_proj_args(pet_geom_s *g) { return base_args(g, -1); }
@@ -130,6 +237,15 @@ extern "C" pet_status pet_fwd(pet_geom g, int subset, const float *x, const floa
     if (!g || !x || !out) return fail(PET_E_ARG, "pet_fwd: null argument");
     if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_fwd: subset out of range");
     hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        int64_t nb = 0, nl = 0;
+        pet_geom_info(g, -1, &nb, &nl, nullptr);
+        const pet_status st = check_domain(g->check_counts, s, "pet_fwd", nullptr, 0,
+                                           {{x, CHK_NONNEG, g->n_vox, MSG_X},
+                                            {add, CHK_FINITE, nb, "background bins are not finite"},
+                                            {mult, CHK_NONNEG, nl, MSG_MULT}});
+        if (st != PET_OK) return st;
+    }
     hipError_t e = launch_to_sheets(g, x, s);
     if (e != hipSuccess) return hip_check(e, "pet_fwd");
     ProjArgs a = base_args(g, subset);
@@ -145,6 +261,14 @@ extern "C" pet_status pet_back(pet_geom g, int subset, const float *sino, const 
     if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_back: subset out of range");
     if (algo != PET_BACK_AUTO && algo != PET_BACK_SCATTER) return fail(PET_E_ARG, "pet_back: unknown algo");
     hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        int64_t nb = 0, nl = 0;
+        pet_geom_info(g, -1, &nb, &nl, nullptr);
+        const pet_status st = check_domain(g->check_counts, s, "pet_back", nullptr, 0,
+                                           {{sino, CHK_FINITE, nb, "sinogram bins are not finite"},
+                                            {mult, CHK_NONNEG, nl, MSG_MULT}});
+        if (st != PET_OK) return st;
+    }
     hipError_t e = launch_zero_sheets(g, s);
     if (e != hipSuccess) return hip_check(e, "pet_back");
     ProjArgs a = base_args(g, subset);
@@ -162,6 +286,10 @@ extern "C" pet_status pet_subset_grad(pet_geom g, int subset, const float *x, co
     if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_subset_grad: subset out of range");
     if (!valid_dtype(y_dtype)) return fail(PET_E_ARG, "pet_subset_grad: bad y dtype");
     hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        const pet_status st = check_data(g, g->check_counts, s, "pet_subset_grad", x, y, y_dtype, add, mult);
+        if (st != PET_OK) return st;
+    }
     hipError_t e = launch_to_sheets(g, x, s);
     if (e == hipSuccess) e = subset_grad_sheets(g, subset, y, y_dtype, add, mult, kl_out, 0, s);
     if (e == hipSuccess) e = launch_from_sheets(g, grad_out, 0, s);
@@ -174,6 +302,12 @@ extern "C" pet_status pet_rdp_grad_hessdiag(pet_geom g, const float *x, const fl
     if (!g || !x || !w) return fail(PET_E_ARG, "pet_rdp_grad_hessdiag: null argument");
     if (!grad_out && !hessdiag_out && !value_out) return PET_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        const pet_status st = check_domain(g->check_counts, s, "pet_rdp_grad_hessdiag", nullptr, 0,
+                                           {{x, CHK_NONNEG, g->n_vox, MSG_X},
+                                            {kappa, CHK_NONNEG, g->n_vox, "kappa voxels are negative or not finite"}});
+        if (st != PET_OK) return st;
+    }
     hipError_t e = launch_rdp(g, x, kappa, w, beta, gamma, eps, grad_out, hessdiag_out, value_out ? g->partial : nullptr, s);
     if (e == hipSuccess && value_out) e = launch_reduce_sum(g->partial, rdp_blocks(g), value_out, 0, s);
     return hip_check(e, "pet_rdp_grad_hessdiag");
@@ -182,6 +316,14 @@ extern "C" pet_status pet_rdp_grad_hessdiag(pet_geom g, const float *x, const fl
 extern "C" pet_status pet_precond(pet_geom g, const float *x, const float *sens, const float *hessdiag, float alpha,
                                   float delta, float *D_out, void *stream) {
     if (!g || !x || !sens || !hessdiag || !D_out) return fail(PET_E_ARG, "pet_precond: null argument");
+    if (checking(g)) {
+        const pet_status st =
+            check_domain(g->check_counts, (hipStream_t)stream, "pet_precond", nullptr, 0,
+                         {{x, CHK_NONNEG, g->n_vox, MSG_X},
+                          {sens, CHK_NONNEG, g->n_vox, "sensitivity voxels are negative or not finite"},
+                          {hessdiag, CHK_NONNEG, g->n_vox, "Hessian-diagonal voxels are negative or not finite"}});
+        if (st != PET_OK) return st;
+    }
     return hip_check(launch_precond(g, x, sens, hessdiag, alpha, delta, D_out, (hipStream_t)stream), "pet_precond");
 }
 
@@ -192,6 +334,10 @@ extern "C" pet_status pet_osem_epoch(pet_geom g, float *x, const void *y, int y_
     for (int j = 0; j < g->d.n_subsets; ++j)
         if (order[j] < 0 || order[j] >= g->d.n_subsets) return fail(PET_E_ARG, "pet_osem_epoch: order entry out of range");
     hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        const pet_status st = check_data(g, g->check_counts, s, "pet_osem_epoch", x, y, y_dtype, add, mult);
+        if (st != PET_OK) return st;
+    }
     hipError_t e = hipSuccess;
     for (int j = 0; j < g->d.n_subsets && e == hipSuccess; ++j) {
         int i = order[j];
@@ -222,8 +368,30 @@ extern "C" pet_status pet_objective(pet_geom g, const float *x, const void *y, i
                                     float eps, double *out, void *stream) {
     if (!g || !x || !y || !w || !out) return fail(PET_E_ARG, "pet_objective: null argument");
     if (!valid_dtype(y_dtype)) return fail(PET_E_ARG, "pet_objective: bad y dtype");
-    return hip_check(objective_impl(g, x, y, y_dtype, add, mult, kappa, w, beta, gamma, eps, out, (hipStream_t)stream),
-                     "pet_objective");
+    hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        pet_status st = check_data(g, g->check_counts, s, "pet_objective", x, y, y_dtype, add, mult);
+        if (st == PET_OK && kappa)
+            st = check_domain(g->check_counts, s, "pet_objective", nullptr, 0,
+                              {{kappa, CHK_NONNEG, g->n_vox, "kappa voxels are negative or not finite"}});
+        if (st != PET_OK) return st;
+    }
+    const pet_status st =
+        hip_check(objective_impl(g, x, y, y_dtype, add, mult, kappa, w, beta, gamma, eps, out, s), "pet_objective");
+    if (st != PET_OK || !checking(g)) return st;
+    return check_numeric(s, out, "pet_objective");
+}
+
+// PET_CHECK for the epoch functions: the image, the data of the state, its
+// sensitivity and kappa.
+static pet_status check_epoch_domain(pet_geom g, const pet_svrg_state *st, const float *x, hipStream_t s,
+                                     const char *name) {
+    pet_status cs = check_data(g, g->check_counts, s, name, x, st->y, st->y_dtype, st->add, st->mult);
+    if (cs == PET_OK)
+        cs = check_domain(g->check_counts, s, name, nullptr, 0,
+                          {{st->sens, CHK_NONNEG, g->n_vox, "sensitivity voxels are negative or not finite"},
+                           {st->kappa, CHK_NONNEG, g->n_vox, "kappa voxels are negative or not finite"}});
+    return cs;
 }
 
 static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
@@ -234,6 +402,8 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
     if (!st->ghat_i || !st->ghat || !st->x_snap || !st->D || !st->sens || !st->y)
         return fail(PET_E_ARG, nm + ": incomplete state");
     if (st->bb && !st->g_prev) return fail(PET_E_ARG, nm + ": g_prev is needed with bb");
+    if (st->counts && st->counts->g != g) return fail(PET_E_ARG, nm + ": counts were made for another geometry");
+    if (st->counts && st->gnorm) return fail(PET_E_ARG, nm + ": gnorm is not available with counts");
     if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, nm + ": bad y dtype");
     if (st->omega < 1) return fail(PET_E_ARG, nm + ": omega must be >= 1");
     if (st->k < 0) return fail(PET_E_STATE, nm + ": negative iteration counter");
@@ -249,6 +419,10 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             return fail(PET_E_ARG, nm + ": bb_update needs state->bb");
     }
     hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        const pet_status cs = check_epoch_domain(g, st, x, s, name);
+        if (cs != PET_OK) return cs;
+    }
     hipError_t e = hipSuccess;
     const int64_t nv = g->n_vox;
     const double *tau_bb = st->bb ? st->bb + 2 : nullptr;
@@ -261,8 +435,12 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
         if (e == hipSuccess) e = launch_to_sheets(g, x, s);
         if (snap) {
             for (int q = 0; q < n && e == hipSuccess; ++q) {
-                e = subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
-                if (e == hipSuccess) e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s);
+                e = st->counts ? counts_grad_sheets(g, st->counts, q, nullptr, s)
+                               : subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+                // zero-count-aware tables hold the x-dependent parts; ghat starts from sens
+                if (e == hipSuccess)
+                    e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s,
+                                              st->counts ? st->sens : nullptr);
             }
             // BB bookkeeping: 0 none, 1 keep the full gradient, 2 also recompute the step bound
             const int bb_mode = !st->bb ? 0 : (opt && opt->bb_update && opt->bb_update[j] && k > 0) ? 2 : 1;
@@ -278,7 +456,8 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             if (e == hipSuccess && st->gnorm) e = launch_subset_norms(g, st->ghat_i, g->num, st->gnorm, s);
             if (e == hipSuccess) e = launch_copy(st->x_snap, x, nv, s);
         } else {
-            e = subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+            e = st->counts ? counts_grad_sheets(g, st->counts, i, nullptr, s)
+                           : subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
             if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
             if (e == hipSuccess)
                 e = launch_svrg_step_ex(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
@@ -290,9 +469,13 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
     if (e != hipSuccess) return hip_check(e, name);
     st->k += n;
     if (objective_out)
-        e = objective_impl(g, x, st->y, st->y_dtype, st->add, st->mult, st->kappa, st->w, st->beta, st->gamma,
-                           st->eps, objective_out, s);
-    return hip_check(e, name);
+        e = st->counts ? objective_counts_impl(g, st->counts, x, st->sens, st->kappa, st->w, st->beta, st->gamma,
+                                               st->eps, objective_out, s)
+                       : objective_impl(g, x, st->y, st->y_dtype, st->add, st->mult, st->kappa, st->w, st->beta,
+                                        st->gamma, st->eps, objective_out, s);
+    const pet_status rs = hip_check(e, name);
+    if (rs != PET_OK || !objective_out || !checking(g)) return rs;
+    return check_numeric(s, objective_out, name);
 }
 
 extern "C" pet_status pet_svrg_epoch(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
@@ -318,10 +501,15 @@ static pet_status sgm_epoch(pet_geom g, pet_svrg_state *st, int estimator, float
         return fail(PET_E_ARG, nm + ": incomplete state");
     if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, nm + ": bad y dtype");
     if (st->k < 0) return fail(PET_E_STATE, nm + ": negative iteration counter");
+    if (st->counts) return fail(PET_E_ARG, nm + ": runs the dense kernels (state->counts must be NULL)");
     const int n = g->d.n_subsets;
     for (int j = 0; j < n; ++j)
         if (subset_seq[j] < 0 || subset_seq[j] >= n) return fail(PET_E_ARG, nm + ": subset_seq entry out of range");
     hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        const pet_status cs = check_epoch_domain(g, st, x, s, name);
+        if (cs != PET_OK) return cs;
+    }
     hipError_t e = hipSuccess;
     const int64_t nv = g->n_vox;
     for (int j = 0; j < n && e == hipSuccess; ++j) {
@@ -354,7 +542,9 @@ static pet_status sgm_epoch(pet_geom g, pet_svrg_state *st, int estimator, float
     if (objective_out)
         e = objective_impl(g, x, st->y, st->y_dtype, st->add, st->mult, st->kappa, st->w, st->beta, st->gamma,
                            st->eps, objective_out, s);
-    return hip_check(e, name);
+    const pet_status rs = hip_check(e, name);
+    if (rs != PET_OK || !objective_out || !checking(g)) return rs;
+    return check_numeric(s, objective_out, name);
 }
 
 extern "C" pet_status pet_saga_epoch(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
@@ -386,9 +576,16 @@ extern "C" pet_status pet_profile_enable(pet_geom g, int enable) {
     return PET_OK;
 }
 
+extern "C" pet_status pet_geom_set_flags(pet_geom g, unsigned flags) {
+    if (!g) return fail(PET_E_ARG, "pet_geom_set_flags: null handle");
+    if (flags & ~(unsigned)PET_CHECK) return fail(PET_E_ARG, "pet_geom_set_flags: unknown flag");
+    g->flags = flags;
+    return PET_OK;
+}
+
 extern "C" pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms, int64_t *launches) {
     if (!g || !total_ms || !launches) return fail(PET_E_ARG, "pet_profile_read: null argument");
-    if (kernel < 0 || kernel >= M_NMODES || kernel == M_COUNT) return fail(PET_E_ARG, "pet_profile_read: unknown kernel");
+    if (kernel < 0 || kernel > PROF_COUNTS || kernel == M_COUNT) return fail(PET_E_ARG, "pet_profile_read: unknown kernel");
     double ms = 0.0;
     auto &v = g->prof_events[kernel];
     for (auto &ev : v) {
@@ -411,6 +608,13 @@ extern "C" pet_status pet_subset_hvp(pet_geom g, int subset, const float *x, con
     if (!g || !x || !v || !y || !ybar_work || !hv_out) return fail(PET_E_ARG, "pet_subset_hvp: null argument");
     if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_subset_hvp: subset out of range");
     if (!valid_dtype(y_dtype)) return fail(PET_E_ARG, "pet_subset_hvp: bad y dtype");
+    if (checking(g)) {
+        pet_status cs = check_data(g, g->check_counts, (hipStream_t)stream, "pet_subset_hvp", x, y, y_dtype, add, mult);
+        if (cs == PET_OK)
+            cs = check_domain(g->check_counts, (hipStream_t)stream, "pet_subset_hvp", nullptr, 0,
+                              {{v, CHK_FINITE, g->n_vox, "direction voxels are not finite"}});
+        if (cs != PET_OK) return cs;
+    }
     return hip_check(hvp_impl(g, subset, x, v, y, y_dtype, add, mult, ybar_work, hv_out, accumulate,
                               (hipStream_t)stream),
                      "pet_subset_hvp");
@@ -448,6 +652,7 @@ extern "C" pet_status pet_svrg_epoch_vjp(pet_geom g, const pet_svrg_state *st, p
         !b->ybar_work || !b->v)
         return fail(PET_E_ARG, "pet_svrg_epoch_vjp: incomplete buffers");
     if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: bad y dtype");
+    if (st->counts) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: runs the dense kernels (state->counts must be NULL)");
     if (st->omega < 1 || st->k < 0) return fail(PET_E_ARG, "pet_svrg_epoch_vjp: bad omega or iteration counter");
     const int n = g->d.n_subsets;
     const int64_t nv = g->n_vox;
@@ -533,4 +738,47 @@ extern "C" pet_status pet_svrg_epoch_vjp(pet_geom g, const pet_svrg_state *st, p
         }
     }
     return hip_check(e, "pet_svrg_epoch_vjp");
+}
+
+extern "C" pet_status pet_subset_grad_counts(pet_geom g, pet_counts c, int subset, const float *x,
+                                             const float *sens_subset, float *grad_out, double *kl_out, void *stream) {
+    if (!g || !c || !x || !grad_out) return fail(PET_E_ARG, "pet_subset_grad_counts: null argument");
+    if (c->g != g) return fail(PET_E_ARG, "pet_subset_grad_counts: counts were made for another geometry");
+    if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_subset_grad_counts: subset out of range");
+    if (kl_out && !sens_subset) return fail(PET_E_ARG, "pet_subset_grad_counts: kl_out needs sens_subset");
+    hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        pet_status cs = check_domain(g->check_counts, s, "pet_subset_grad_counts", nullptr, 0,
+                                     {{x, CHK_NONNEG, g->n_vox, MSG_X},
+                                      {sens_subset, CHK_NONNEG, g->n_vox,
+                                       "sensitivity voxels are negative or not finite"}});
+        if (cs != PET_OK) return cs;
+    }
+    const int row = subset < 0 ? c->n_subsets : subset;
+    hipError_t e = launch_to_sheets(g, x, s);
+    if (e == hipSuccess) e = counts_grad_sheets(g, c, subset, kl_out, s);
+    if (e == hipSuccess) e = launch_from_sheets(g, grad_out, 0, s);
+    if (e == hipSuccess && sens_subset) e = launch_lincomb(grad_out, 1.f, grad_out, 1.f, sens_subset, g->n_vox, s);
+    if (e == hipSuccess && kl_out) e = launch_dot(sens_subset, x, g->n_vox, g->partial, kl_out, 1, s);
+    if (e == hipSuccess && kl_out) e = launch_add_scalar(kl_out, c->sum_add[row] - c->sum_y[row], s);
+    return hip_check(e, "pet_subset_grad_counts");
+}
+
+extern "C" pet_status pet_objective_counts(pet_geom g, pet_counts c, const float *x, const float *sens,
+                                           const float *kappa, const float w[27], float beta, float gamma, float eps,
+                                           double *out, void *stream) {
+    if (!g || !c || !x || !sens || !w || !out) return fail(PET_E_ARG, "pet_objective_counts: null argument");
+    if (c->g != g) return fail(PET_E_ARG, "pet_objective_counts: counts were made for another geometry");
+    hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        const pet_status cs = check_domain(g->check_counts, s, "pet_objective_counts", nullptr, 0,
+                                           {{x, CHK_NONNEG, g->n_vox, MSG_X},
+                                            {sens, CHK_NONNEG, g->n_vox, "sensitivity voxels are negative or not finite"},
+                                            {kappa, CHK_NONNEG, g->n_vox, "kappa voxels are negative or not finite"}});
+        if (cs != PET_OK) return cs;
+    }
+    const pet_status st = hip_check(objective_counts_impl(g, c, x, sens, kappa, w, beta, gamma, eps, out, s),
+                                    "pet_objective_counts");
+    if (st != PET_OK || !checking(g)) return st;
+    return check_numeric(s, out, "pet_objective_counts");
 }

@@ -128,6 +128,9 @@ extern "C" pet_status pet_batch_create(const pet_geom *geoms, pet_svrg_state *co
         const pet_svrg_state *st = states[r];
         if (!st->ghat_i || !st->ghat || !st->D || !st->sens || !st->y)
             return fail(PET_E_ARG, "pet_batch_create: incomplete state of member " + std::to_string(r));
+        if (st->counts)
+            return fail(PET_E_ARG, "pet_batch_create: batches run the dense kernels (member " + std::to_string(r) +
+                                       " has counts)");
         if (st->y_dtype != PET_Y_F32 && st->y_dtype != PET_Y_U16 && st->y_dtype != PET_Y_U8)
             return fail(PET_E_ARG, "pet_batch_create: bad y dtype");
         if (st->omega < 1) return fail(PET_E_ARG, "pet_batch_create: omega must be >= 1");

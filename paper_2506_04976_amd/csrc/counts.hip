@@ -1,0 +1,411 @@
+// Zero-count-aware data term: the bins with counts y > 0, compacted once, and
+// the line kernels that walk only them.
+//
+// The separable Kullback-Leibler data term of Section 1.2 has d(s, 0) = s, so
+// a bin without counts contributes mult P x + add to the objective and mult P^T 1
+// to the gradient, whatever x is.  The subset gradient therefore splits as
+//     grad D_i(x) = P_i^T mult - P_i^T [mult y / ybar(x)],
+// where only bins with y > 0 enter the second term, and the objective as
+//     D(x) = <P^T mult, x> + sum add - sum y + sum_{y > 0} y log(y / ybar(x)).
+// In the SVRG estimator of eq. (svrg) the first term cancels between
+// grad D_i(x) and the stored grad D_i(xhat); the full gradient at the
+// snapshot is the sensitivity P^T mult plus the sum of the second terms.  So
+// the line kernels here compute h_i(x) = -P_i^T [mult y / ybar(x)] and
+// sum_{y > 0} y log(y / ybar) from the compacted bins only.
+//
+// Work layout.  One workgroup per transaxial line with at least one count,
+// as in the dense kernels: the image sheet X[i][z] (transaxial interpolation)
+// and the FP64 gradient sheet Z[i][z] in LDS, one compacted bin per thread.
+// A thread walks the samples of its LOR inside the TOF window of its bin,
+// forward and back.  The TOF weight of a sample at signed distance t from
+// the LOR centre in bin b depends only on d = t - t_b (the kernel is shift
+// invariant): W(d) = 1/2 [E(w/2 - d) - E(-w/2 - d)], E the clamped erf.  It
+// is tabulated once per geometry at NW_TAB + 1 nodes over its support
+// |d| <= w/2 + nsig sigma (FP64 on the host) and interpolated linearly from
+// LDS.
+#include "line_sheets.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <string>
+#include <new>
+#include <vector>
+
+namespace pet {
+namespace {
+
+__device__ __forceinline__ float count_y(const void *y, int dt, int64_t idx) {
+    if (dt == PET_Y_U8) return (float)((const uint8_t *)y)[idx];
+    if (dt == PET_Y_U16) return (float)((const uint16_t *)y)[idx];
+    return ((const float *)y)[idx];
+}
+
+// Bins with y > 0 per transaxial line, and the FP64 sums of y and of add over
+// all bins of the line (add null: 0).
+__global__ void __launch_bounds__(256) k_counts_per_line(const void *__restrict__ y, int dt,
+                                                         const float *__restrict__ add, int64_t bins_per_line,
+                                                         int *__restrict__ cnt, double *__restrict__ ysum,
+                                                         double *__restrict__ asum) {
+    __shared__ int s_c[4];
+    __shared__ double s_y[4], s_a[4];
+    const int64_t base = (int64_t)blockIdx.x * bins_per_line;
+    int c = 0;
+    double sy = 0.0, sa = 0.0;
+    for (int64_t k = threadIdx.x; k < bins_per_line; k += blockDim.x) {
+        const float v = count_y(y, dt, base + k);
+        c += v > 0.f ? 1 : 0;
+        sy += (double)v;
+        if (add) sa += (double)add[base + k];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        sy += __shfl_down(sy, off, 64);
+        sa += __shfl_down(sa, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_c[w] = c;
+        s_y[w] = sy;
+        s_a[w] = sa;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ct = 0;
+        double yt = 0.0, at = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            ct += s_c[i];
+            yt += s_y[i];
+            at += s_a[i];
+        }
+        cnt[blockIdx.x] = ct;
+        ysum[blockIdx.x] = yt;
+        asum[blockIdx.x] = at;
+    }
+}
+
+// Compaction of one line's bins with y > 0, in sinogram order.
+__global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y, int dt, const float *__restrict__ add,
+                                                     const float *__restrict__ mult, int64_t bins_per_line, int n_tof,
+                                                     int n_planes, const int64_t *__restrict__ line_off,
+                                                     CountItem *__restrict__ items) {
+    __shared__ int s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * bins_per_line;
+    int64_t out = line_off[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t k0 = 0; k0 < bins_per_line; k0 += blockDim.x) {
+        const int64_t k = k0 + threadIdx.x;
+        const float v = k < bins_per_line ? count_y(y, dt, base + k) : 0.f;
+        const bool has = v > 0.f;
+        const uint64_t m = __ballot(has);
+        if (lane == 0) s_w[w] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int i = 0; i < nw; ++i) {
+            before += i < w ? s_w[i] : 0;
+            total += s_w[i];
+        }
+        if (has) {
+            const int rank = before + __popcll(m & ((1ull << lane) - 1ull));
+            const int plane = (int)(k / n_tof);
+            CountItem it;
+            it.pt = (uint32_t)k;
+            it.y = v;
+            it.add = add ? add[base + k] : 0.f;
+            it.mult = mult ? mult[(int64_t)blockIdx.x * n_planes + plane] : 1.f;
+            items[out + rank] = it;
+        }
+        out += total;
+        __syncthreads();
+    }
+}
+
+// TOF weight W(d) from the LDS table: linear interpolation between nodes;
+// the position is clamped to the table, whose end nodes are 0.
+__device__ __forceinline__ float tof_weight(const float2 *tab, float d, const CountArgs &c) {
+    const float pos = __builtin_amdgcn_fmed3f(fmaf(d, c.inv_dx, c.pos0), 0.f, c.pos_max);
+    const int k = (int)pos;
+    const float2 t = tab[k];
+    return fmaf(pos - (float)k, t.y, t.x);
+}
+
+// One workgroup per line with counts.  MODE M_GRAD: gradient sheets receive
+// -P^T [mult y / ybar] and every block writes its FP64 sum of y log(y / ybar);
+// M_OBJ: the sums only.
+template <bool TOF, int MODE>
+__global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs c) {
+    extern __shared__ float4 smem4[];
+    float *smem = reinterpret_cast<float *>(smem4);
+    constexpr bool NEED_Z = MODE == M_GRAD;
+    const int line = c.lines[blockIdx.x];
+    const LineP L = a.lines[line];
+    const int nrow = L.i_hi - L.i_lo + 1;
+    const int rz = a.rz;
+    const int sheet = (a.rows_max * rz + 3) & ~3;
+    float *X = smem;
+    double *Z = reinterpret_cast<double *>(smem + sheet);
+    float2 *tab = reinterpret_cast<float2 *>(smem + (NEED_Z ? 3 : 1) * sheet);
+    if (TOF)
+        for (int k = threadIdx.x; k < c.nw; k += blockDim.x) tab[k] = c.wtab[k];
+    if (nrow > 0) build_sheets<true, NEED_Z>(a, L, nrow, X, Z);
+    __syncthreads();
+
+    double kl = 0.0;
+    const int64_t i0 = c.line_off[line], i1 = c.line_off[line + 1];
+    const float umax = (float)(a.nz + PADZ);
+    // (a line that misses the image still has bins with counts: ybar = add there,
+    // and its y log(y / add) enters the sum; its sample ranges are empty)
+    for (int64_t it = i0 + threadIdx.x; it < i1; it += blockDim.x) {
+        const CountItem e = c.items[it];
+        const int p = TOF ? (int)(e.pt / (uint32_t)c.n_tof) : (int)e.pt;
+        const int b = TOF ? (int)(e.pt - (uint32_t)p * (uint32_t)c.n_tof) : 0;
+        const PlaneP P = a.planes[p];
+        const float len = sqrtf(L.lt2 + P.dz2);
+        const float ell = L.vm_um * len;
+        int is, ie;
+        z_clip(L, P, a.nz, is, ie);
+        // d(i) = t(i) - t_b, t(i) = (lambda(i) - 1/2) |u| the signed distance
+        // from the LOR centre; rows outside |d| <= D (one row of margin, where
+        // the table gives 0) are skipped
+        float d0 = 0.f, dd = 0.f;
+        if (TOF) {
+            d0 = fmaf(L.lam0 - 0.5f, len, -a.tof.tb[b]);
+            dd = L.dlam * len;
+            const float ia = (-c.wD - d0) / dd, ib = (c.wD - d0) / dd;
+            // clamped to [is, ie] (an empty window gives is > ie) before the conversion
+            const float lo = fminf(fmaxf(floorf(fminf(ia, ib)) - 1.f, (float)is), (float)(ie + 1));
+            const float hi = fmaxf(fminf(ceilf(fmaxf(ia, ib)) + 1.f, (float)ie), (float)(is - 1));
+            is = (int)lo;
+            ie = (int)hi;
+        }
+        const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
+        float s = 0.f;
+        const float *xr = X + (is - L.i_lo) * rz;
+        for (int i = is; i <= ie; ++i, xr += rz) {
+            const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+            const int j = (int)u;
+            const float x0 = xr[j], x1 = xr[j + 1];
+            const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
+            s = TOF ? fmaf(tof_weight(tab, fmaf((float)i, dd, d0), c), v, s) : s + v;
+        }
+        const float ybar = fmaf(e.mult, s * ell, e.add);
+        kl += (double)e.y * log((double)e.y / (double)ybar);
+        if (NEED_Z) {
+            const float Q = -e.mult * (e.y / ybar) * ell;
+            double *zr = Z + (is - L.i_lo) * rz;
+            for (int i = is; i <= ie; ++i, zr += rz) {
+                const float qw = TOF ? Q * tof_weight(tab, fmaf((float)i, dd, d0), c) : Q;
+                const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+                const int j = (int)u;
+                const float a1 = qw * __builtin_amdgcn_fractf(u);
+                atomicAdd(&zr[j], (double)(qw - a1));
+                atomicAdd(&zr[j + 1], (double)a1);
+            }
+        }
+    }
+    if (NEED_Z && nrow > 0) {
+        __syncthreads();
+        scatter_sheet(a, L, nrow, Z);
+    }
+    if (a.partial) block_sums(kl, kl, a.partial, false);
+}
+
+template <bool TOF, int MODE>
+void set_counts_lds(size_t need) {
+    static size_t granted = 64 * 1024;
+    if (need <= granted) return;
+    if (hipFuncSetAttribute((const void *)k_line_counts<TOF, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)need) == hipSuccess)
+        granted = need;
+    (void)hipGetLastError();
+}
+
+template <bool TOF, int MODE>
+hipError_t launch_counts_mode(const pet_geom_s *g, const pet_counts_s *cs, int nblk, int threads, size_t lds,
+                              const ProjArgs &a, const CountArgs &c, hipStream_t s) {
+    set_counts_lds<TOF, MODE>(lds);
+    hipLaunchKernelGGL((k_line_counts<TOF, MODE>), dim3(nblk), dim3(threads), lds, s, a, c);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t counts_lds_bytes(const pet_geom_s *g, int mode) {
+    const size_t sheet = ((size_t)g->rows_max * (g->d.nz + 2 * PADZ) + 3) & ~(size_t)3;
+    const size_t tab = g->d.n_tof > 1 ? sizeof(float2) * NW_TAB : 0;
+    return (mode == M_GRAD ? 3 : 1) * sheet * sizeof(float) + tab;
+}
+
+int counts_blocks(const pet_counts_s *cs, int subset) {
+    const int row = subset < 0 ? cs->n_subsets : subset;
+    return (int)(cs->lines_off[row + 1] - cs->lines_off[row]);
+}
+
+hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *cs, int mode, int subset, const ProjArgs &a,
+                              hipStream_t s) {
+    const int nblk = counts_blocks(cs, subset);
+    if (nblk == 0) return hipSuccess;
+    CountArgs c{};
+    c.items = cs->items;
+    c.line_off = cs->line_off;
+    c.lines = cs->lines + cs->lines_off[subset < 0 ? cs->n_subsets : subset];
+    c.wtab = cs->wtab;
+    c.nw = NW_TAB;
+    c.n_tof = g->d.n_tof;
+    c.wD = cs->wD;
+    c.inv_dx = (float)(NW_TAB / (2.0 * cs->wD));
+    c.pos0 = (float)(NW_TAB / 2);
+    c.pos_max = (float)NW_TAB - 1e-3f;
+    const size_t lds = counts_lds_bytes(g, mode);
+    const bool tof = g->d.n_tof > 1;
+    const int threads = tof ? CNT_BLOCK : CNT_BLOCK / 2;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipSuccess;
+    if (g->profiling) {
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (!g->prof_pool.empty()) {
+            ev = g->prof_pool.back();
+            g->prof_pool.pop_back();
+        } else {
+            e = hipEventCreate(&ev.first);
+            if (e == hipSuccess) e = hipEventCreate(&ev.second);
+            if (e != hipSuccess) return e;
+        }
+        e0 = ev.first;
+        e1 = ev.second;
+        g->prof_events[PROF_COUNTS].push_back(ev);
+        e = hipEventRecord(e0, s);
+    }
+    if (e == hipSuccess) {
+        if (mode == M_GRAD)
+            e = tof ? launch_counts_mode<true, M_GRAD>(g, cs, nblk, threads, lds, a, c, s)
+                    : launch_counts_mode<false, M_GRAD>(g, cs, nblk, threads, lds, a, c, s);
+        else
+            e = tof ? launch_counts_mode<true, M_OBJ>(g, cs, nblk, threads, lds, a, c, s)
+                    : launch_counts_mode<false, M_OBJ>(g, cs, nblk, threads, lds, a, c, s);
+    }
+    if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
+    return e;
+}
+
+}  // namespace pet
+
+using namespace pet;
+
+extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, const float *add, const float *mult,
+                                        pet_counts *out) {
+    if (!g || !y || !out) return fail(PET_E_ARG, "pet_counts_create: null argument");
+    if (y_dtype != PET_Y_F32 && y_dtype != PET_Y_U16 && y_dtype != PET_Y_U8)
+        return fail(PET_E_ARG, "pet_counts_create: bad y dtype");
+    const int n_lines = g->d.n_views * g->d.n_rad;
+    const int64_t bpl = (int64_t)g->n_planes * g->d.n_tof;
+    if (bpl > (int64_t)UINT32_MAX) return fail(PET_E_ARG, "pet_counts_create: too many bins per line");
+    if (counts_lds_bytes(g, M_GRAD) > g->max_lds)
+        return fail(PET_E_ARG, "pet_counts_create: the sheets and TOF table of this geometry exceed the LDS");
+    pet_counts_s *c = new (std::nothrow) pet_counts_s();
+    if (!c) return fail(PET_E_OOM, "pet_counts_create: host allocation failed");
+    c->g = g;
+    c->n_subsets = g->d.n_subsets;
+    int *d_cnt = nullptr;
+    double *d_ys = nullptr, *d_as = nullptr;
+    hipError_t e = hipMalloc(&d_cnt, sizeof(int) * n_lines);
+    if (e == hipSuccess) e = hipMalloc(&d_ys, sizeof(double) * n_lines);
+    if (e == hipSuccess) e = hipMalloc(&d_as, sizeof(double) * n_lines);
+    if (e == hipSuccess)
+        hipLaunchKernelGGL(k_counts_per_line, dim3(n_lines), dim3(256), 0, 0, y, y_dtype, add, bpl, d_cnt, d_ys, d_as);
+    if (e == hipSuccess) e = hipGetLastError();
+    std::vector<int> cnt(n_lines);
+    std::vector<double> ys(n_lines), as(n_lines);
+    if (e == hipSuccess) e = hipMemcpy(cnt.data(), d_cnt, sizeof(int) * n_lines, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ys.data(), d_ys, sizeof(double) * n_lines, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(as.data(), d_as, sizeof(double) * n_lines, hipMemcpyDeviceToHost);
+    std::vector<int64_t> off(n_lines + 1, 0);
+    for (int l = 0; l < n_lines; ++l) off[l + 1] = off[l] + cnt[l];
+    c->n_items = off[n_lines];
+    if (e == hipSuccess) e = hipMalloc(&c->line_off, sizeof(int64_t) * (n_lines + 1));
+    if (e == hipSuccess) e = hipMalloc(&c->items, sizeof(CountItem) * std::max<int64_t>(c->n_items, 1));
+    if (e == hipSuccess) e = hipMemcpy(c->line_off, off.data(), sizeof(int64_t) * (n_lines + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && c->n_items > 0)
+        hipLaunchKernelGGL(k_counts_fill, dim3(n_lines), dim3(256), 0, 0, y, y_dtype, add, mult, bpl, g->d.n_tof,
+                           g->n_planes, c->line_off, c->items);
+    if (e == hipSuccess) e = hipGetLastError();
+    // per subset (then all views): its lines with counts, most counts first,
+    // and the sums of y and add over all its bins
+    const int n = g->d.n_subsets;
+    std::vector<int> lines;
+    c->lines_off.assign(n + 2, 0);
+    c->sum_y.assign(n + 1, 0.0);
+    c->sum_add.assign(n + 1, 0.0);
+    c->items_per_subset.assign(n + 1, 0);
+    for (int row = 0; row <= n; ++row) {
+        std::vector<int> mine;
+        std::vector<int> views;
+        if (row < n) {
+            views = g->subset_views[row];
+        } else {
+            views.resize(g->d.n_views);
+            std::iota(views.begin(), views.end(), 0);
+        }
+        for (int v : views)
+            for (int k = 0; k < g->d.n_rad; ++k) {
+                const int l = v * g->d.n_rad + k;
+                c->sum_y[row] += ys[l];
+                c->sum_add[row] += as[l];
+                c->items_per_subset[row] += cnt[l];
+                if (cnt[l] > 0) mine.push_back(l);
+            }
+        std::stable_sort(mine.begin(), mine.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+        lines.insert(lines.end(), mine.begin(), mine.end());
+        c->lines_off[row + 1] = (int64_t)lines.size();
+    }
+    if (e == hipSuccess) e = hipMalloc(&c->lines, sizeof(int) * std::max<size_t>(lines.size(), 1));
+    if (e == hipSuccess && !lines.empty())
+        e = hipMemcpy(c->lines, lines.data(), sizeof(int) * lines.size(), hipMemcpyHostToDevice);
+    // TOF weight table: W at NW_TAB + 1 nodes over |d| <= D = w/2 + nsig sigma
+    if (g->d.n_tof > 1) {
+        const double h = 0.5 * g->d.tof_bin_mm, sig = g->d.tof_sigma_mm, cl = g->d.tof_nsigma / std::sqrt(2.0);
+        const double D = h + g->d.tof_nsigma * sig;
+        c->wD = (float)D;
+        auto E = [&](double u) { return std::erf(std::min(std::max(u / (std::sqrt(2.0) * sig), -cl), cl)); };
+        std::vector<double> W(NW_TAB + 1);
+        for (int k = 0; k <= NW_TAB; ++k) {
+            const double d = -D + 2.0 * D * k / NW_TAB;
+            W[k] = k == 0 || k == NW_TAB ? 0.0 : 0.5 * (E(h - d) - E(-h - d));
+        }
+        std::vector<float2> tab(NW_TAB);
+        for (int k = 0; k < NW_TAB; ++k) tab[k] = make_float2((float)W[k], (float)(W[k + 1] - W[k]));
+        if (e == hipSuccess) e = hipMalloc(&c->wtab, sizeof(float2) * NW_TAB);
+        if (e == hipSuccess) e = hipMemcpy(c->wtab, tab.data(), sizeof(float2) * NW_TAB, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (d_cnt) (void)hipFree(d_cnt);
+    if (d_ys) (void)hipFree(d_ys);
+    if (d_as) (void)hipFree(d_as);
+    if (e != hipSuccess) {
+        pet_counts_destroy(c);
+        return e == hipErrorOutOfMemory ? fail(PET_E_OOM, "pet_counts_create: device allocation failed")
+                                        : hip_check(e, "pet_counts_create");
+    }
+    *out = c;
+    return PET_OK;
+}
+
+extern "C" pet_status pet_counts_destroy(pet_counts c) {
+    if (!c) return PET_OK;
+    (void)hipDeviceSynchronize();
+    void *ptrs[] = {c->items, c->line_off, c->lines, c->wtab};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete c;
+    return PET_OK;
+}
+
+extern "C" pet_status pet_counts_info(pet_counts c, int subset, int64_t *n_items, double *sum_y, double *sum_add) {
+    if (!c) return fail(PET_E_ARG, "pet_counts_info: null handle");
+    if (subset < -1 || subset >= c->n_subsets) return fail(PET_E_ARG, "pet_counts_info: subset out of range");
+    const int row = subset < 0 ? c->n_subsets : subset;
+    if (n_items) *n_items = c->items_per_subset[row];
+    if (sum_y) *sum_y = c->sum_y[row];
+    if (sum_add) *sum_add = c->sum_add[row];
+    return PET_OK;
+}

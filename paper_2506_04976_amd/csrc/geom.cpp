@@ -328,6 +328,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     int max_lds = 0;
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) != hipSuccess) max_lds = 0;
     if (max_lds <= 0) max_lds = 64 * 1024;
+    g->max_lds = (size_t)max_lds;
     size_t need = 3 * sheet * sizeof(float);
     if (d.n_tof > 1) {
         int e1 = g->tof_ws > 4 ? g->tof_ws - 4 : 0;
@@ -411,6 +412,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
               alloc((void **)&g->grad, sizeof(float) * g->n_vox) && alloc((void **)&g->hess, sizeof(float) * g->n_vox) &&
               alloc((void **)&g->num, sizeof(float) * g->n_vox) && alloc((void **)&g->sensi, sizeof(float) * g->n_vox) &&
               alloc((void **)&g->partial, sizeof(double) * g->n_partial) && alloc((void **)&g->dscratch, sizeof(double) * 16) &&
+              alloc((void **)&g->check_counts, sizeof(unsigned) * CHECK_SLOTS) &&
               alloc((void **)&g->fscratch, sizeof(float) * 16);
     if (ok && g->psf_passes)
         ok = alloc((void **)&g->psf_a, sizeof(float) * g->n_vox) && alloc((void **)&g->psf_b, sizeof(float) * g->n_vox);
@@ -445,7 +447,8 @@ extern "C" pet_status pet_geom_destroy(pet_geom g) {
         (void)hipEventDestroy(e.second);
     }
     void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->line_order, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
-                    g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch, g->psf_a, g->psf_b};
+                    g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch, g->psf_a, g->psf_b,
+                    g->check_counts};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete g;

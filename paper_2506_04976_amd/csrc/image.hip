@@ -4,6 +4,8 @@
 // FP64, the OSEM multiplicative update and deterministic FP64 reductions.
 #include "pet_internal.h"
 
+#include <cfloat>
+
 namespace pet {
 namespace {
 
@@ -230,7 +232,7 @@ __global__ void k_precond(const float *__restrict__ x, const float *__restrict__
 // ghat_i = g (data gradient of subset i at the snapshot); ghat (+)= g in FP64.
 __global__ void k_snapshot_accum(const float *__restrict__ G0, const float *__restrict__ G1, float *__restrict__ ghat_i,
                                  double *__restrict__ ghat, float *__restrict__ gcopy, int nx, int ny, int nz, int rz,
-                                 int first) {
+                                 int first, const float *__restrict__ base) {
     int64_t n = (int64_t)nx * ny * nz;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         int ix = v % nx;
@@ -239,7 +241,7 @@ __global__ void k_snapshot_accum(const float *__restrict__ G0, const float *__re
         float s = sheet_value(G0, G1, ix, iy, iz, nx, ny, rz);
         ghat_i[v] = s;
         if (gcopy) gcopy[v] = s;
-        ghat[v] = first ? (double)s : ghat[v] + (double)s;
+        ghat[v] = (first ? (base ? (double)base[v] : 0.0) : ghat[v]) + (double)s;
     }
 }
 
@@ -278,11 +280,11 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_psf_axis(const float *__restrict_
 
 // x -> FP64 running sum of subset gradients (snapshot with a resolution model)
 __global__ void k_accum_image(const float *__restrict__ img, double *__restrict__ ghat, float *__restrict__ gcopy,
-                              int64_t n, int first) {
+                              int64_t n, int first, const float *__restrict__ base) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const float s = img[v];
         if (gcopy) gcopy[v] = s;
-        ghat[v] = first ? (double)s : ghat[v] + (double)s;
+        ghat[v] = (first ? (base ? (double)base[v] : 0.0) : ghat[v]) + (double)s;
     }
 }
 
@@ -365,6 +367,46 @@ __global__ void k_osem_update(float *__restrict__ x, const float *__restrict__ n
 }
 
 // Single-block deterministic reductions.
+// Domain checks (debug mode): count the elements of p that violate the
+// condition `kind` into *count.  y (nullable, dtype ydt) is the counts array
+// that the CHK_ADD / CHK_NO_ADD conditions refer to, element by element.
+__device__ __forceinline__ float y_at(const void *y, int dt, int64_t i) {
+    if (dt == PET_Y_U8) return (float)((const uint8_t *)y)[i];
+    if (dt == PET_Y_U16) return (float)((const uint16_t *)y)[i];
+    return ((const float *)y)[i];
+}
+
+__global__ void k_domain_count(const float *__restrict__ p, int kind, int64_t n, const void *__restrict__ y, int ydt,
+                               unsigned *__restrict__ count) {
+    unsigned bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        bool ok = true;
+        if (kind == CHK_NONNEG) {
+            const float v = p[i];
+            ok = v >= 0.f && v <= FLT_MAX;
+        } else if (kind == CHK_FINITE) {
+            const float v = p[i];
+            ok = v >= -FLT_MAX && v <= FLT_MAX;
+        } else if (kind == CHK_COUNTS) {
+            const float v = y_at(y, ydt, i);
+            ok = v >= 0.f && v <= FLT_MAX;
+        } else if (kind == CHK_ADD) {
+            const float v = p[i];
+            ok = v >= 0.f && v <= FLT_MAX && (v > 0.f || !(y_at(y, ydt, i) > 0.f));
+        } else if (kind == CHK_NO_ADD) {
+            ok = !(y_at(y, ydt, i) > 0.f);
+        }
+        bad += ok ? 0u : 1u;
+    }
+    for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+
+__global__ void k_fill_u32(unsigned *__restrict__ p, int n, unsigned val) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = val;
+}
+
 __global__ void k_reduce_sum(const double *__restrict__ p, int n, double *__restrict__ out, int accumulate) {
     __shared__ double red[1024];
     double s = 0.0;
@@ -413,9 +455,10 @@ hipError_t rdp_launch(const RdpArgs &a, int64_t n, hipStream_t s) {
 // or the previous pass's buffer and writes buffer p % 2, the last pass writes
 // `out` (accumulating if asked).  `in` may be psf_b; `out` must not be the
 // buffer the last pass reads (psf_b for three passes, psf_a for two).
-hipError_t launch_psf(const pet_geom_s *g, const float *in, float *out, int accumulate, hipStream_t s) {
+hipError_t launch_psf_b(const pet_geom_s *g, const SheetBufs &w, const float *in, float *out, int accumulate,
+                        hipStream_t s) {
     if (!g->psf_passes) return hipErrorInvalidValue;
-    float *buf[2] = {g->psf_a, g->psf_b};
+    float *buf[2] = {w.psf_a, w.psf_b};
     for (int p = 0; p < g->psf_passes; ++p) {
         const float *src = p == 0 ? in : buf[(p - 1) % 2];
         const bool last = p == g->psf_passes - 1;
@@ -426,37 +469,61 @@ hipError_t launch_psf(const pet_geom_s *g, const float *in, float *out, int accu
     return hipGetLastError();
 }
 
+hipError_t launch_psf(const pet_geom_s *g, const float *in, float *out, int accumulate, hipStream_t s) {
+    return launch_psf_b(g, geom_bufs(g), in, out, accumulate, s);
+}
+
+SheetBufs geom_bufs(const pet_geom_s *g) { return SheetBufs{g->T0, g->T1, g->G0, g->G1, g->psf_a, g->psf_b}; }
+
 // The line kernels read x (or G x with a resolution model) through the sheets.
-hipError_t launch_to_sheets(const pet_geom_s *g, const float *x, hipStream_t s) {
+hipError_t launch_to_sheets_b(const pet_geom_s *g, const SheetBufs &w, const float *x, hipStream_t s) {
     const float *src = x;
     if (g->psf_passes) {
-        float *gx = g->psf_passes == 3 ? g->psf_a : g->psf_b;
-        const hipError_t e = launch_psf(g, x, gx, 0, s);
+        float *gx = g->psf_passes == 3 ? w.psf_a : w.psf_b;
+        const hipError_t e = launch_psf_b(g, w, x, gx, 0, s);
         if (e != hipSuccess) return e;
         src = gx;
     }
-    hipLaunchKernelGGL(k_to_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, src, g->T0, g->T1, g->d.nx, g->d.ny,
+    hipLaunchKernelGGL(k_to_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, src, w.T0, w.T1, g->d.nx, g->d.ny,
                        g->d.nz, g->d.nz + 2 * PADZ);
     return hipGetLastError();
 }
 
-hipError_t launch_zero_sheets(const pet_geom_s *g, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t0_elems), dim3(IMG_BLOCK), 0, s, g->G0, (int64_t)g->t0_elems, 0.f);
-    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t1_elems), dim3(IMG_BLOCK), 0, s, g->G1, (int64_t)g->t1_elems, 0.f);
+hipError_t launch_to_sheets(const pet_geom_s *g, const float *x, hipStream_t s) {
+    return launch_to_sheets_b(g, geom_bufs(g), x, s);
+}
+
+// Whole image sheets to zero, padding included (k_to_sheets rewrites only the
+// interior; the borders of the handle's own sheets are cleared once at creation).
+hipError_t launch_clear_image_sheets(const pet_geom_s *g, const SheetBufs &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t0_elems), dim3(IMG_BLOCK), 0, s, w.T0, (int64_t)g->t0_elems, 0.f);
+    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t1_elems), dim3(IMG_BLOCK), 0, s, w.T1, (int64_t)g->t1_elems, 0.f);
     return hipGetLastError();
 }
 
+hipError_t launch_zero_sheets_b(const pet_geom_s *g, const SheetBufs &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t0_elems), dim3(IMG_BLOCK), 0, s, w.G0, (int64_t)g->t0_elems, 0.f);
+    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t1_elems), dim3(IMG_BLOCK), 0, s, w.G1, (int64_t)g->t1_elems, 0.f);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_sheets(const pet_geom_s *g, hipStream_t s) { return launch_zero_sheets_b(g, geom_bufs(g), s); }
+
 // Gradient sheets -> image (then G^T = G with a resolution model).
-hipError_t launch_from_sheets(const pet_geom_s *g, float *out, int accumulate, hipStream_t s) {
+hipError_t launch_from_sheets_b(const pet_geom_s *g, const SheetBufs &w, float *out, int accumulate, hipStream_t s) {
     if (g->psf_passes) {
-        hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, g->psf_b, g->d.nx,
+        hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, w.G0, w.G1, w.psf_b, g->d.nx,
                            g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, 0);
         const hipError_t e = hipGetLastError();
-        return e != hipSuccess ? e : launch_psf(g, g->psf_b, out, accumulate, s);
+        return e != hipSuccess ? e : launch_psf_b(g, w, w.psf_b, out, accumulate, s);
     }
-    hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, out, g->d.nx, g->d.ny,
+    hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, w.G0, w.G1, out, g->d.nx, g->d.ny,
                        g->d.nz, g->d.nz + 2 * PADZ, accumulate);
     return hipGetLastError();
+}
+
+hipError_t launch_from_sheets(const pet_geom_s *g, float *out, int accumulate, hipStream_t s) {
+    return launch_from_sheets_b(g, geom_bufs(g), out, accumulate, s);
 }
 
 hipError_t launch_rdp(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
@@ -658,16 +725,16 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
 }
 
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
-                                 hipStream_t s) {
+                                 hipStream_t s, const float *base) {
     if (g->psf_passes) {
         hipError_t e = launch_from_sheets(g, ghat_i, 0, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_accum_image, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, ghat_i, ghat, gcopy, g->n_vox,
-                           first);
+                           first, base);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_snapshot_accum, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, ghat_i, ghat, gcopy,
-                       g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first);
+                       g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first, base);
     return hipGetLastError();
 }
 
@@ -678,6 +745,55 @@ hipError_t launch_reduce_sum(const double *partial, int n, double *out, int accu
 
 hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s) {
     hipLaunchKernelGGL(k_osem_update, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, num, sens, g->n_vox);
+    return hipGetLastError();
+}
+
+// FP64 block partials of sum a[v] b[v] (IMG_BLOCK threads per block).
+__global__ void k_dot_partial(const float *__restrict__ a, const float *__restrict__ b, int64_t n,
+                              double *__restrict__ partial) {
+    __shared__ double red[IMG_BLOCK / 64];
+    double acc = 0.0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        acc += (double)a[v] * (double)b[v];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < IMG_BLOCK / 64; ++w) t += red[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+__global__ void k_add_scalar(double *__restrict__ out, double val) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out += val;
+}
+
+// *out (+)= sum a[v] b[v] in FP64 (block partials in `partial`, at least
+// dot_blocks(n) doubles, then one reduction).
+int dot_blocks(int64_t n) { return (int)grid_for(n).x; }
+
+hipError_t launch_dot(const float *a, const float *b, int64_t n, double *partial, double *out, int accumulate,
+                      hipStream_t s) {
+    const dim3 grid = grid_for(n);
+    hipLaunchKernelGGL(k_dot_partial, grid, dim3(IMG_BLOCK), 0, s, a, b, n, partial);
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_reduce_sum(partial, (int)grid.x, out, accumulate, s);
+}
+
+hipError_t launch_add_scalar(double *out, double val, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, s, out, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_domain_count(const float *p, int kind, int64_t n, const void *y, int ydt, unsigned *count,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_domain_count, grid_for(n), dim3(IMG_BLOCK), 0, s, p, kind, n, y, ydt, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned val, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, val);
     return hipGetLastError();
 }
 

@@ -94,6 +94,27 @@ struct ProjArgs {
     const int *order;
 };
 
+// ---- zero-count-aware data term (counts.hip) --------------------------------
+// One bin with y > 0: its index within its transaxial line (plane * n_tof +
+// TOF bin), count, background and the LOR's multiplicative factor.
+struct CountItem {
+    uint32_t pt;
+    float y, add, mult;
+};
+static_assert(sizeof(CountItem) == 16, "CountItem layout");
+constexpr int NW_TAB = 4096;    // intervals of the tabulated TOF weight W(d)
+constexpr int CNT_BLOCK = 512;  // threads per workgroup of the counts line kernel (TOF; non-TOF: half)
+
+struct CountArgs {
+    const CountItem *items;
+    const int64_t *line_off;  // items of line l: [line_off[l], line_off[l + 1])
+    const int *lines;         // the launch's lines (workgroup b takes lines[b])
+    const float2 *wtab;       // TOF: (W_k, W_{k+1} - W_k) at the table's nodes
+    int nw, n_tof;
+    float wD;                 // support of W: |d| <= wD
+    float inv_dx, pos0, pos_max;  // table position of d: d * inv_dx + pos0, clamped to [0, pos_max]
+};
+
 // ---- batches of reconstructions -------------------------------------------
 constexpr int PSF_RMAX = 16;  // resolution model: kernel radius limit (voxels)
 // One axis of the separable resolution kernel: weights w[0..r] of offsets 0..r
@@ -165,6 +186,7 @@ struct pet_geom_s {
     std::vector<int64_t> order_off;
     pet::TofTable tof{};
     size_t lds_bytes = 0;
+    size_t max_lds = 0;                 // the device's LDS limit per workgroup
     // scratch arena
     float *T0 = nullptr, *T1 = nullptr, *G0 = nullptr, *G1 = nullptr;
     size_t t0_elems = 0, t1_elems = 0;
@@ -173,13 +195,34 @@ struct pet_geom_s {
     size_t n_partial = 0;
     double *dscratch = nullptr;         // a few device doubles
     float *fscratch = nullptr;          // a few device floats
+    // debug flags (PET_CHECK) and the device counters of the domain checks
+    unsigned flags = 0;
+    unsigned *check_counts = nullptr;
     // optional HIP-event timing of the line kernels, per mode
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[pet::M_NMODES];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[pet::M_NMODES + 1];  // last: counts kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
 };
 
+// Compacted bins with counts y > 0 of one data set on one geometry
+// (pet_counts_create).
+struct pet_counts_s {
+    pet_geom_s *g = nullptr;
+    int n_subsets = 0;
+    int64_t n_items = 0;
+    pet::CountItem *items = nullptr;  // sinogram order
+    int64_t *line_off = nullptr;      // [n_lines + 1]
+    int *lines = nullptr;             // per subset (then all views): lines with counts, most first
+    float2 *wtab = nullptr;           // TOF weight table (NW_TAB entries)
+    float wD = 0.f;
+    std::vector<int64_t> lines_off;        // [n_subsets + 2] offsets into lines
+    std::vector<int64_t> items_per_subset; // [n_subsets + 1]
+    std::vector<double> sum_y, sum_add;    // [n_subsets + 1] over every bin of the subset (then all)
+};
+
 namespace pet {
+
+constexpr int PROF_COUNTS = M_NMODES;  // profiling slot of the counts line kernel
 
 // error state (api.cpp)
 pet_status fail(pet_status s, const std::string &msg);
@@ -194,11 +237,33 @@ hipError_t launch_line_batched(const BMember *mem, const int *order, int n_mem, 
 hipError_t prime_line_batched(size_t lds);
 // line-kernel argument block of a geometry (all views)
 ProjArgs geom_proj_args(pet_geom_s *g);
+
 // workgroups of a line launch of `subset` (-1: all views), one per line, each
 // writing one FP64 partial
 int n_line_blocks(const pet_geom_s *g, int subset);
 
+// zero-count-aware line kernels (counts.hip): mode M_GRAD (gradient sheets
+// receive -P^T[mult y / ybar], block partials of sum y log(y / ybar)) or M_OBJ
+// (partials only), over the lines with counts of `subset` (-1: all)
+hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *c, int mode, int subset, const ProjArgs &a,
+                              hipStream_t s);
+int counts_blocks(const pet_counts_s *c, int subset);
+size_t counts_lds_bytes(const pet_geom_s *g, int mode);
+
 // image kernels (image.hip)
+// Work buffers of the sheet conversions: transposed image sheets T0 / T1,
+// gradient sheets G0 / G1 (t0_elems / t1_elems floats each) and, with a
+// resolution model, two image-sized buffers.  A handle's own are geom_bufs(g).
+struct SheetBufs {
+    float *T0, *T1, *G0, *G1, *psf_a, *psf_b;
+};
+SheetBufs geom_bufs(const pet_geom_s *g);
+hipError_t launch_to_sheets_b(const pet_geom_s *g, const SheetBufs &w, const float *x, hipStream_t s);
+hipError_t launch_zero_sheets_b(const pet_geom_s *g, const SheetBufs &w, hipStream_t s);
+hipError_t launch_from_sheets_b(const pet_geom_s *g, const SheetBufs &w, float *out, int accumulate, hipStream_t s);
+hipError_t launch_clear_image_sheets(const pet_geom_s *g, const SheetBufs &w, hipStream_t s);
+hipError_t launch_psf_b(const pet_geom_s *g, const SheetBufs &w, const float *in, float *out, int accumulate,
+                        hipStream_t s);
 hipError_t launch_to_sheets(const pet_geom_s *g, const float *x, hipStream_t s);
 hipError_t launch_zero_sheets(const pet_geom_s *g, hipStream_t s);
 hipError_t launch_from_sheets(const pet_geom_s *g, float *out, int accumulate, hipStream_t s);
@@ -210,6 +275,23 @@ hipError_t launch_precond(const pet_geom_s *g, const float *x, const float *sens
 hipError_t launch_reduce_sum(const double *partial, int n, double *out, int accumulate, hipStream_t s);
 hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s);
 hipError_t launch_max(const pet_geom_s *g, const float *x, float *out, hipStream_t s);
+// domain checks (debug mode, PET_CHECK): count violations of a condition
+enum DomainKind {
+    CHK_NONNEG = 0,  // finite and >= 0 (images, mult, sensitivities)
+    CHK_FINITE = 1,  // finite
+    CHK_COUNTS = 2,  // counts y: finite and >= 0
+    CHK_ADD = 3,     // background: finite, >= 0, and > 0 where y > 0
+    CHK_NO_ADD = 4,  // no background given: every y must be 0
+};
+constexpr int CHECK_SLOTS = 8;  // counters of one call's checks
+hipError_t launch_domain_count(const float *p, int kind, int64_t n, const void *y, int ydt, unsigned *count,
+                               hipStream_t s);
+hipError_t launch_fill_u32(unsigned *p, int n, unsigned val, hipStream_t s);
+// PET_CHECK set on the handle, and the checks of an entry point's image and
+// data with the counters at `counts` (api.cpp)
+bool checking(const pet_geom_s *g);
+pet_status check_data(pet_geom_s *g, unsigned *counts, hipStream_t s, const char *fn, const float *x, const void *y,
+                      int ydt, const float *add, const float *mult);
 hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
                             float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
                             float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
@@ -232,8 +314,14 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
                            float beta, float gamma, float eps, int update_pc, const float *sens, float alpha,
                            float delta, float *D, int first, const float *gi, float *table_i, double *table_sum,
                            float n_sub, float tau, float *x_out, hipStream_t s);
+// ghat_i <- the gradient sheets' image; ghat (+)= it in FP64 (first: ghat = base + it, base nullable)
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
-                                 hipStream_t s);
+                                 hipStream_t s, const float *base = nullptr);
+// FP64 dot product into *out (accumulate: add), through `partial`
+int dot_blocks(int64_t n);
+hipError_t launch_dot(const float *a, const float *b, int64_t n, double *partial, double *out, int accumulate,
+                      hipStream_t s);
+hipError_t launch_add_scalar(double *out, double val, hipStream_t s);
 // resolution model G (no-op pass-through when the geometry has none)
 hipError_t launch_psf(const pet_geom_s *g, const float *in, float *out, int accumulate, hipStream_t s);
 int rdp_blocks(const pet_geom_s *g);

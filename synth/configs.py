@@ -118,6 +118,13 @@ CONFIGS["c5_sim"] = dict(
 # Test geometry with more TOF bins than a lane holds at once (two bin blocks).
 CONFIGS["mini_tof_many"] = dict(CONFIGS["mini_tof"], name="mini_tof_many", n_tof=20, tof_bin=7.0, tof_sigma=6.0)
 
+# Test geometry whose TOF segments hold 37-40 planes (40 rings of 1 mm,
+# ring difference <= 3): more than 32 planes per segment, so one plane per lane
+# of a segment wave, as on the 3D TOF workload, at a size the oracle finishes
+# in seconds.
+CONFIGS["mini_tof_seg40"] = dict(CONFIGS["mini_tof"], name="mini_tof_seg40", nz=11, n_rings=40, ring_pitch=1.0,
+                                 seed=4)
+
 # Test geometries with the image-space resolution model (Section 3.1): a
 # Gaussian of 6 mm FWHM on ~4 mm voxels (kernel radius 3 voxels in x and y).
 CONFIGS["mini_tof_psf"] = dict(CONFIGS["mini_tof"], name="mini_tof_psf", psf_fwhm=6.0)

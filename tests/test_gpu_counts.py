@@ -1,0 +1,166 @@
+"""GPU parity of the zero-count-aware path (pet_counts_*, pet_subset_grad_counts,
+pet_objective_counts, pet_svrg_epoch with state->counts) through the C ABI
+against the FP64 oracle, which evaluates the dense formulas over every bin
+(Section 1.2's d(s, t), eq. (svrg)).  The identity the path rests on,
+grad D_i = P_i^T mult - P_i^T[mult y / ybar], is therefore checked against an
+oracle that never splits the sum.  Tolerances as in the dense parity tests:
+cancellation-aware 1e-5 for gradients, 1e-5 relative for objectives, 1e-4 for
+images after the workload's epochs."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import poisson, recon
+from synth import configs, data
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["mini_tof", "mini_nontof", "mini_2d", "c0_2d", "mini_tof_psf", "mini_tof_many", "mini_tof_seg40"]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+class CountsCase:
+    def __init__(self, name):
+        import paper_2506_04976_amd as pm
+        self.pm = pm
+        self.cfg = configs.get(name)
+        self.d = data.make_dataset(self.cfg)
+        self.geom = pm.Geometry(self.cfg)
+        dev = torch.device("cuda:0")
+        self.dev = dev
+        rng = np.random.default_rng(42)
+        self.x_np = (self.d["x_true"] * rng.uniform(0.7, 1.3, self.d["x_true"].shape) +
+                     0.05 * self.d["x_true"].max()).astype(np.float32)
+        self.x = torch.from_numpy(self.x_np.ravel()).to(dev)
+        self.y = torch.from_numpy(self.d["y"].ravel()).to(dev)
+        self.r = torch.from_numpy(self.d["r"].ravel()).to(dev)
+        self.a = torch.from_numpy(self.d["mult"].ravel()).to(dev)
+        self.counts = pm.Counts(self.geom, self.y, self.r, self.a)
+        self.T = self.cfg["n_tof"]
+        self.prob = recon.Problem(self.cfg, self.d["y"], self.d["r"], self.d["mult"],
+                                  beta=configs.beta_value(self.cfg), gamma=2.0, eps=1e-3 * float(self.x_np.max()),
+                                  alpha=1.0, delta=1e-3 * float(self.x_np.max()))
+
+    def sens_subset(self, subset):
+        s = torch.empty(self.geom.n_vox, device=self.dev)
+        self.pm.pet_back(self.geom, subset, None, self.a, s)
+        return s
+
+
+@pytest.fixture(scope="module", params=CASES)
+def case(request):
+    print(f"\n[gpu counts case {request.param}]", flush=True)
+    return CountsCase(request.param)
+
+
+def test_counts_index(case):
+    # the compacted bins are exactly the bins with y > 0, per subset; the FP64
+    # sums over every bin of the subset match numpy's
+    y = case.d["y"].astype(np.float64)
+    r = case.d["r"].astype(np.float64)
+    for subset in list(range(case.cfg["n_subsets"])) + [-1]:
+        views = list(range(case.cfg["n_views"])) if subset < 0 else configs.subset_views(case.cfg, subset)
+        n_items, sy, sa = case.counts.info(subset)
+        assert n_items == int(np.count_nonzero(y[views]))
+        assert sy == pytest.approx(float(y[views].sum()), rel=1e-12)
+        assert sa == pytest.approx(float(r[views].sum()), rel=1e-12)
+
+
+def test_counts_subset_grad_and_kl_parity(case):
+    pm = case.pm
+    xo = case.x_np.astype(np.float64)
+    for subset in range(case.cfg["n_subsets"]):
+        sens = case.sens_subset(subset)
+        g = torch.full((case.geom.n_vox,), float("nan"), device=case.dev)
+        kl = torch.zeros(1, dtype=torch.float64, device=case.dev)
+        pm.pet_subset_grad_counts(case.geom, case.counts, subset, case.x, sens, g, kl)
+        ref = case.prob.data_grad(xo, subset).ravel()
+        yb = case.prob.ybar(xo, subset)
+        scale = np.linalg.norm(case.prob.back(case.prob.a[subset] * (1 + case.prob.y[subset] / yb), subset))
+        err = np.linalg.norm(g.cpu().double().numpy() - ref) / scale
+        assert err <= 1e-5, f"subset {subset}: {err:.3e}"
+        kl_ref = float(np.sum(poisson.kl(yb, case.prob.y[subset])))
+        assert float(kl.cpu()) == pytest.approx(kl_ref, rel=1e-5)
+        # the part that depends on x alone: grad - sens_i
+        h = torch.empty(case.geom.n_vox, device=case.dev)
+        pm.pet_subset_grad_counts(case.geom, case.counts, subset, case.x, None, h)
+        err_h = np.linalg.norm((h + sens).cpu().double().numpy() - ref) / scale
+        assert err_h <= 1e-5, f"subset {subset}: {err_h:.3e}"
+
+
+def test_counts_objective_parity(case):
+    pm = case.pm
+    sens = case.sens_subset(-1)
+    w27 = pm.rdp_weights27(case.cfg["vx"], case.cfg["vy"], case.cfg["vz"])
+    out = torch.zeros(1, dtype=torch.float64, device=case.dev)
+    pm.pet_objective_counts(case.geom, case.counts, case.x, sens, None, w27, case.prob.beta, case.prob.gamma,
+                            case.prob.eps, out)
+    assert float(out.cpu()) == pytest.approx(case.prob.objective(case.x_np.astype(np.float64)), rel=1e-5)
+
+
+def _svrg(case, counts, epochs):
+    pm = case.pm
+    cfg, n = case.cfg, case.cfg["n_subsets"]
+    beta = configs.beta_value(cfg)
+    x = torch.ones(case.geom.n_vox, device=case.dev)
+    xmax = torch.zeros(1, device=case.dev)
+    pm.pet_osem_epoch(case.geom, x, case.y, case.r, case.a, list(range(n)), xmax)
+    mx = float(xmax.cpu())
+    sens = case.sens_subset(-1)
+    st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=beta, gamma=2.0, eps=1e-3 * mx,
+                             alpha=1.0, delta=1e-3 * mx, counts=case.counts if counts else None)
+    orders = data.subset_orders(cfg, epochs)
+    tau_rule = recon.stepsize_vanishing(1.0, 0.02, n)
+    upd = recon.pc_update_iters(n)
+    obj = torch.zeros(1, dtype=torch.float64, device=case.dev)
+    for e in range(epochs):
+        ks = [e * n + j for j in range(n)]
+        pm.pet_svrg_epoch(case.geom, st, x, orders[e], [tau_rule(k) for k in ks], [k in upd for k in ks], obj)
+    return x.cpu().double().numpy(), float(obj.cpu()), (orders, tau_rule, upd, beta)
+
+
+def test_counts_svrg_reconstruction_parity(case):
+    epochs = case.cfg["epochs"]
+    x_cnt, obj_cnt, (orders, tau_rule, upd, beta) = _svrg(case, True, epochs)
+    x0 = recon.osem_epoch(case.prob, np.ones(case.prob.shape))
+    m0 = float(x0.max())
+    prob = recon.Problem(case.cfg, case.d["y"], case.d["r"], case.d["mult"], beta=beta, gamma=2.0, eps=1e-3 * m0,
+                         alpha=1.0, delta=1e-3 * m0)
+    x_orc = recon.svrg(prob, x0, epochs, recon.order_rule(orders), tau_rule, upd).ravel()
+    err = _rel(x_cnt, x_orc)
+    print(f"[{case.cfg['name']}] zero-count-aware SVRG, {epochs} epochs: relative L2 {err:.2e}", flush=True)
+    assert err <= 1e-4
+    assert obj_cnt == pytest.approx(prob.objective(x_cnt.reshape(prob.shape)), rel=1e-5)
+    # and the dense GPU path on the same schedule
+    x_dense, obj_dense, _ = _svrg(case, False, epochs)
+    assert _rel(x_cnt, x_dense) <= 1e-4
+    assert obj_cnt == pytest.approx(obj_dense, rel=1e-5)
+
+
+def test_counts_argument_errors(case):
+    pm = case.pm
+    other = pm.Geometry(case.cfg)
+    g = torch.empty(case.geom.n_vox, device=case.dev)
+    with pytest.raises(pm.PetError, match="another geometry") as ei:
+        pm.pet_subset_grad_counts(other, case.counts, 0, case.x, None, g)
+    assert ei.value.status == 1
+    with pytest.raises(pm.PetError, match="sens_subset"):
+        pm.pet_subset_grad_counts(case.geom, case.counts, 0, case.x, None, g,
+                                  torch.zeros(1, dtype=torch.float64, device=case.dev))
+    n = case.cfg["n_subsets"]
+    sens = case.sens_subset(-1)
+    st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=0.1, gamma=2.0, eps=1e-3,
+                             counts=case.counts)
+    seq, tau, upd = list(range(n)), [1.0] * n, [True] + [False] * (n - 1)
+    with pytest.raises(pm.PetError, match="dense kernels"):
+        pm.pet_saga_epoch(case.geom, st, case.x.clone(), seq, tau, upd)
+    stg = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=0.1, gamma=2.0, eps=1e-3,
+                              counts=case.counts, gnorm=True)
+    with pytest.raises(pm.PetError, match="gnorm"):
+        pm.pet_svrg_epoch(case.geom, stg, case.x.clone(), seq, tau, upd)
+    torch.cuda.synchronize()
+    other.close()

@@ -51,3 +51,107 @@ def test_epoch_option_errors(pm):
     assert st.k == 0 and stb.k == 0, "a refused call must not advance the state"
     torch.cuda.synchronize()
     g.close()
+
+
+def _mini(pm, ydtype=torch.uint8):
+    cfg = configs.get("mini_tof")
+    g = pm.Geometry(cfg)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator().manual_seed(5)
+    y = (torch.rand(g.n_bins, generator=gen) < 0.3).to(ydtype).to(dev)
+    r = torch.full((g.n_bins,), 0.05, device=dev)
+    a = torch.rand(g.n_lors, generator=gen).add_(0.5).to(dev)
+    x = torch.rand(g.n_vox, generator=gen).to(dev)
+    return cfg, g, x, y, r, a
+
+
+def test_domain_checks_return_pet_e_domain(pm):
+    # With PET_CHECK the paper's infinite cases are refused before any work:
+    # x < 0 (R = +inf, eq. (prior)), y < 0 (d = +inf), a background that is
+    # 0 where y > 0 (d = +inf once s = 0), non-finite factors.
+    cfg, g, x, y, r, a = _mini(pm)
+    dev = x.device
+    out = torch.empty(g.n_vox, device=dev)
+    w27 = pm.rdp_weights27(cfg["vx"], cfg["vy"], cfg["vz"])
+    pm.pet_geom_set_flags(g, pm.PET_CHECK)
+    # valid inputs pass
+    pm.pet_subset_grad(g, 1, x, y, r, a, out)
+    xb = x.clone()
+    xb[7] = -1e-3
+    for call in (lambda: pm.pet_subset_grad(g, 1, xb, y, r, a, out),
+                 lambda: pm.pet_rdp_grad_hessdiag(g, xb, None, w27, 0.1, 2.0, 1e-3, out),
+                 lambda: pm.pet_fwd(g, 0, xb, a, r, torch.empty(g.n_bins, device=dev))):
+        with pytest.raises(pm.PetError, match="eq. \\(prior\\)") as ei:
+            call()
+        assert ei.value.status == 2
+    yf = y.float()
+    yf[11] = -1.0
+    with pytest.raises(pm.PetError, match="t < 0") as ei:
+        pm.pet_subset_grad(g, 1, x, yf, r, a, out)
+    assert ei.value.status == 2
+    rz = r.clone()
+    rz[int(torch.nonzero(y)[0])] = 0.0
+    with pytest.raises(pm.PetError, match="background") as ei:
+        pm.pet_subset_grad(g, 1, x, y, rz, a, out)
+    assert ei.value.status == 2
+    with pytest.raises(pm.PetError, match="no background") as ei:
+        pm.pet_subset_grad(g, 1, x, y, None, a, out)
+    assert ei.value.status == 2
+    an = a.clone()
+    an[3] = float("nan")
+    with pytest.raises(pm.PetError, match="multiplicative") as ei:
+        pm.pet_subset_grad(g, 1, x, y, r, an, out)
+    assert ei.value.status == 2
+    # the same calls without the flag are not checked (unspecified results)
+    pm.pet_geom_set_flags(g, 0)
+    pm.pet_subset_grad(g, 1, xb, y, r, a, out)
+    with pytest.raises(pm.PetError, match="unknown flag"):
+        pm.pet_geom_set_flags(g, 6)
+    torch.cuda.synchronize()
+    g.close()
+
+
+def test_domain_check_of_epoch_and_numeric_objective(pm):
+    cfg, g, x, y, r, a = _mini(pm)
+    dev = x.device
+    n = g.n_subsets
+    sens = torch.empty(g.n_vox, device=dev)
+    pm.pet_back(g, -1, None, a, sens)
+    st = pm.SvrgStateBuffers(g, y, r, a, sens, beta=0.1, gamma=2.0, eps=1e-3, alpha=1.0, delta=1e-3)
+    pm.pet_geom_set_flags(g, pm.PET_CHECK)
+    seq, tau, upd = list(range(n)), [1.0] * n, [True] + [False] * (n - 1)
+    xb = x.clone()
+    xb[0] = float("inf")
+    with pytest.raises(pm.PetError, match="image voxels") as ei:
+        pm.pet_svrg_epoch(g, st, xb, seq, tau, upd)
+    assert ei.value.status == 2 and st.k == 0
+    obj = torch.zeros(1, dtype=torch.float64, device=dev)
+    w27 = pm.rdp_weights27(cfg["vx"], cfg["vy"], cfg["vz"])
+    pm.pet_objective(g, x, y, r, a, None, w27, 0.1, 2.0, 1e-3, obj)
+    assert torch.isfinite(obj).all()
+    # finite inputs in the domain whose forward model overflows FP32: the FP64
+    # objective is +inf and the call reports PET_E_NUMERIC
+    xh = torch.full_like(x, 3e38)
+    with pytest.raises(pm.PetError, match="not finite") as ei:
+        pm.pet_objective(g, xh, y, r, a, None, w27, 0.1, 2.0, 1e-3, obj)
+    assert ei.value.status == 5
+    pm.pet_geom_set_flags(g, 0)
+    torch.cuda.synchronize()
+    g.close()
+
+
+def test_zero_counts_with_zero_mean_give_the_sensitivity(pm):
+    # d(s, 0) = s has derivative 1 also where s = 0: with x = 0, no background
+    # and no counts the subset gradient is P_i^T mult, with no 0/0
+    cfg, g, x, y, r, a = _mini(pm)
+    dev = x.device
+    z = torch.zeros(g.n_vox, device=dev)
+    y0 = torch.zeros_like(y)
+    got = torch.empty(g.n_vox, device=dev)
+    pm.pet_subset_grad(g, 2, z, y0, None, a, got)
+    want = torch.empty(g.n_vox, device=dev)
+    pm.pet_back(g, 2, None, a, want)
+    torch.cuda.synchronize()
+    assert torch.isfinite(got).all()
+    assert float((got - want).norm() / want.norm()) < 1e-6
+    g.close()

@@ -21,7 +21,8 @@ from synth import configs, data
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["mini_tof", "mini_nontof", "mini_2d", "c0_2d", "mini_tof_psf", "mini_2d_psf", "mini_tof_many"]
+CASES = ["mini_tof", "mini_nontof", "mini_2d", "c0_2d", "mini_tof_psf", "mini_2d_psf", "mini_tof_many",
+         "mini_tof_seg40"]
 
 
 def _rel(a, b):

@@ -233,3 +233,29 @@ def test_saga_converges_to_dense_map_with_constant_steps(oracle_built):
     # the MAP is a fixed point of SAGA
     x_fp = recon.saga(prob, xmap, 4, rule, recon.stepsize_constant(1.0), recon.pc_update_iters(prob.n))
     assert np.linalg.norm(x_fp - xmap) / np.linalg.norm(xmap) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["mini_tof", "mini_nontof"])
+def test_zero_count_split_of_data_term(oracle_built, name):
+    # d(s, 0) = s (Section 1.2): the subset KL and its gradient split into a part
+    # linear in x through the subset sensitivity and a part over bins with y > 0
+    # only, D_i = <P_i^T a, x> + sum r - sum y + sum_{y>0} y log(y / ybar) and
+    # grad D_i = P_i^T a - P_i^T[a y / ybar] restricted to y > 0 -- the identity
+    # the zero-count-aware GPU path computes; here both sides are the oracle's
+    # dense sums, so it checks the algebra, not a kernel.
+    from oracle import poisson
+    cfg = configs.get(name)
+    d = data.make_dataset(cfg)
+    prob = recon.Problem(cfg, d["y"], d["r"], d["mult"], beta=0.1, gamma=2.0, eps=1e-3)
+    x = np.random.default_rng(3).uniform(0.1, 2.0, prob.shape)
+    for i in range(cfg["n_subsets"]):
+        yb = prob.ybar(x, i)
+        y = prob.y[i]
+        pos = y > 0
+        si = prob.sens_subset(i)
+        split = (si * x).sum() + prob.r[i].sum() - y.sum() + np.sum(y[pos] * np.log(y[pos] / yb[pos]))
+        assert split == pytest.approx(poisson.kl(yb, y).sum(), rel=1e-12)
+        q = np.where(pos, prob.a[i] * y / np.where(pos, yb, 1.0), 0.0)
+        g_split = si - prob.back(q, i)
+        g = prob.data_grad(x, i)
+        assert np.linalg.norm(g_split - g) <= 1e-12 * np.linalg.norm(si)
