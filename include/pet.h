@@ -42,6 +42,7 @@
 #ifndef PET_H
 #define PET_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -135,6 +136,26 @@ pet_status pet_back(pet_geom g, int subset, const float *sino, const float *mult
 pet_status pet_subset_grad(pet_geom g, int subset, const float *x, const void *y, int y_dtype,
                            const float *add, const float *mult, float *grad_out, double *kl_out,
                            void *stream);
+
+/* Allocation-free pet_subset_grad, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as pet_subset_grad;
+ * the call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Its work buffers (the two transposed image sheets and the two
+ * gradient sheets of the geometry, one FP64 partial per line of the subset
+ * and, with a resolution model, two image-sized buffers) are carved from one
+ * static device array of PET_NOALLOC_SCRATCH_BYTES, 256-byte aligned.  Every
+ * device holds its own copy from the library's load until the process ends
+ * (the address is looked up once per device, at pet_geom_create or at the
+ * first call).  PET_E_ARG when the geometry needs more than that (C1/C2-sized
+ * 128x128x71 geometries need about 21 MB).  All calls on one device share the
+ * array and it keeps the last call's contents: each call clears what must
+ * start at zero, and calls that overlap in time on one device (different
+ * streams, threads or handles) race on it and must be serialised. */
+#define PET_NOALLOC_SCRATCH_BYTES ((size_t)24 << 20)
+pet_status pet_subset_grad_noalloc(pet_geom g, int subset, const float *x, const void *y, int y_dtype,
+                                   const float *add, const float *mult, float *grad_out, double *kl_out,
+                                   void *stream);
 
 /* Zero-count-aware data term -------------------------------------------------
  * The KL data fidelity has d(s, 0) = s (Section 1.2): a bin without counts
@@ -458,7 +479,7 @@ pet_status pet_batch_set_launch(pet_batch b, int workgroups, int waves, int orde
  * Whole arrays are checked (all views).  Entry points that produce the FP64
  * objective (pet_objective, and the epoch functions given objective_out) then
  * wait for it and return PET_E_NUMERIC if it is not finite.  Checked:
- * pet_fwd, pet_back, pet_subset_grad, pet_rdp_grad_hessdiag,
+ * pet_fwd, pet_back, pet_subset_grad(_noalloc), pet_rdp_grad_hessdiag,
  * pet_precond, pet_osem_epoch, pet_objective, pet_svrg_epoch(_ex),
  * pet_saga_epoch, pet_sgd_epoch, pet_subset_hvp.  Without the flag (the
  * default) nothing is checked and values outside the domain give unspecified

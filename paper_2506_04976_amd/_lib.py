@@ -26,7 +26,7 @@ _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "P
            5: "PET_E_NUMERIC", 6: "PET_E_STATE"}
 
 EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "pet_back", "pet_subset_grad",
-
+           "pet_subset_grad_noalloc",
            "pet_rdp_grad_hessdiag", "pet_precond", "pet_osem_epoch", "pet_objective", "pet_svrg_epoch",
            "pet_svrg_epoch_ex", "pet_saga_epoch", "pet_sgd_epoch",
            "pet_subset_hvp", "pet_rdp_hvp", "pet_precond_vjp", "pet_svrg_epoch_vjp",
@@ -97,6 +97,7 @@ def lib():
         L.pet_fwd.argtypes = [P, I, P, P, P, P, P]
         L.pet_back.argtypes = [P, I, P, P, P, I, I, P]
         L.pet_subset_grad.argtypes = [P, I, P, P, I, P, P, P, P, P]
+        L.pet_subset_grad_noalloc.argtypes = [P, I, P, P, I, P, P, P, P, P]
         L.pet_rdp_grad_hessdiag.argtypes = [P, P, P, ctypes.POINTER(F), F, F, F, P, P, P, P]
         L.pet_precond.argtypes = [P, P, P, P, F, F, P, P]
         L.pet_osem_epoch.argtypes = [P, P, P, I, P, P, ctypes.POINTER(ctypes.c_int32), P, P]
@@ -269,6 +270,16 @@ def pet_subset_grad(geom, subset, x, y, add, mult, grad_out, kl_out=None, stream
                                  _ptr(add, torch.float32, geom.n_bins, "add"), _ptr(mult, torch.float32, geom.n_lors, "mult"),
                                  _ptr(grad_out, torch.float32, geom.n_vox, "grad_out"),
                                  _ptr(kl_out, torch.float64, 1, "kl_out"), _stream(stream)))
+    return grad_out
+
+
+def pet_subset_grad_noalloc(geom, subset, x, y, add, mult, grad_out, kl_out=None, stream=None):
+    _check(lib().pet_subset_grad_noalloc(geom.handle, subset, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                         _ptr(y, None, geom.n_bins, "y"), y_dtype_code(y),
+                                         _ptr(add, torch.float32, geom.n_bins, "add"),
+                                         _ptr(mult, torch.float32, geom.n_lors, "mult"),
+                                         _ptr(grad_out, torch.float32, geom.n_vox, "grad_out"),
+                                         _ptr(kl_out, torch.float64, 1, "kl_out"), _stream(stream)))
     return grad_out
 
 

@@ -225,6 +225,7 @@ hipError_t objective_counts_impl(pet_geom g, const pet_counts_s *c, const float 
 }  // namespace
 
 ProjArgs geom_proj_args(pet_geom_s *g) { return base_args(g, -1); }
+ProjArgs subset_proj_args(pet_geom_s *g, int subset) { return base_args(g, subset); }
 
 }  // namespace pet
 

@@ -433,6 +433,10 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
         pet_geom_destroy(g);
         return hip_check(e, "pet_geom_create");
     }
+    // set-up of the allocation-free entry point on this device (its scratch
+    // array's address; a failure is reported by that entry point itself)
+    void *scratch_addr = nullptr;
+    (void)noalloc_scratch(g->device, &scratch_addr);
     *out = g;
     return PET_OK;
 }

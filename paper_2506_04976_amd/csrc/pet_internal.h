@@ -235,9 +235,12 @@ hipError_t launch_line_batched(const BMember *mem, const int *order, int n_mem, 
                                int waves, size_t lds, hipStream_t s);
 // raise the batched kernel's dynamic-LDS limit (outside any stream capture)
 hipError_t prime_line_batched(size_t lds);
-// line-kernel argument block of a geometry (all views)
+// line-kernel argument block of a geometry (all views), and of one subset (-1: all views)
 ProjArgs geom_proj_args(pet_geom_s *g);
-
+ProjArgs subset_proj_args(pet_geom_s *g, int subset);
+// device address of the allocation-free entry point's static scratch array on
+// `device` (looked up once per device; noalloc.cpp)
+pet_status noalloc_scratch(int device, void **out);
 // workgroups of a line launch of `subset` (-1: all views), one per line, each
 // writing one FP64 partial
 int n_line_blocks(const pet_geom_s *g, int subset);

@@ -51,6 +51,8 @@ def test_argument_errors_without_gpu_work():
     assert b"null" in L.pet_last_error()
     assert L.pet_batch_epoch(None, None, None, None, 1, None) == 1
     assert b"null" in L.pet_last_error()
+    assert L.pet_subset_grad_noalloc(None, 0, None, None, 0, None, None, None, None, None) == 1
+    assert b"null" in L.pet_last_error()
     assert L.pet_geom_set_flags(None, 1) == 1
     assert b"null" in L.pet_last_error()
 

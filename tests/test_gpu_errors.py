@@ -79,6 +79,7 @@ def test_domain_checks_return_pet_e_domain(pm):
     xb = x.clone()
     xb[7] = -1e-3
     for call in (lambda: pm.pet_subset_grad(g, 1, xb, y, r, a, out),
+                 lambda: pm.pet_subset_grad_noalloc(g, 1, xb, y, r, a, out),
                  lambda: pm.pet_rdp_grad_hessdiag(g, xb, None, w27, 0.1, 2.0, 1e-3, out),
                  lambda: pm.pet_fwd(g, 0, xb, a, r, torch.empty(g.n_bins, device=dev))):
         with pytest.raises(pm.PetError, match="eq. \\(prior\\)") as ei:
