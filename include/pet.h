@@ -60,7 +60,7 @@ typedef enum {
 } pet_status;
 
 enum { PET_SCANNER_PARALLEL2D = 0, PET_SCANNER_CYLINDER = 1 };
-enum { PET_BACK_AUTO = 0, PET_BACK_SCATTER = 1 };
+enum { PET_BACK_AUTO = 0, PET_BACK_SCATTER = 1, PET_BACK_GATHER = 2 };
 enum { PET_Y_F32 = 0, PET_Y_U16 = 1, PET_Y_U8 = 2 };
 
 /* Scanner + image description.
@@ -121,11 +121,22 @@ pet_status pet_geom_info(pet_geom g, int subset, int64_t *n_bins, int64_t *n_lor
 pet_status pet_fwd(pet_geom g, int subset, const float *x, const float *mult, const float *add,
                    float *out, void *stream);
 
-/* Adjoint: x_out (+)= P_subset^T (mult * sino).  sino NULL means all ones (so
- * pet_back(g, -1, NULL, mult, sens, 0, ...) gives the sensitivity A^T 1).
- * accumulate = 0 overwrites x_out.  algo: PET_BACK_AUTO / PET_BACK_SCATTER
- * (line-driven scatter through LDS sheets with global float atomics; the sum
- * order is not deterministic). */
+/* Adjoint (Section 2.3: A^T enters the gradient of eq. (template) and A^T 1
+ * the preconditioner of eq. (preconditioner)): x_out (+)= P_subset^T (mult * sino).
+ * sino NULL means all ones (so pet_back(g, -1, NULL, mult, sens, 0, ...) gives
+ * the sensitivity A^T 1).  accumulate = 0 overwrites x_out.  algo:
+ *   PET_BACK_SCATTER  line-driven scatter: each sample of each LOR adds its two
+ *                     axial interpolation shares to an LDS sheet of its line
+ *                     with FP64 LDS atomics;
+ *   PET_BACK_GATHER   cell-driven gather: each sheet cell sums, without
+ *                     atomics, the shares of the samples that land on it,
+ *                     found from each segment's affine axial map (TOF weights
+ *                     from the tabulated bin-integrated Gaussian);
+ *   PET_BACK_AUTO     the scatter, measured faster on every workload here.
+ * Both spread the sheets over the transaxial neighbours with global float
+ * atomics, so the sum order is not deterministic; both give the same
+ * (sample, weight) pairs.  PET_E_ARG for PET_BACK_GATHER when the per-plane
+ * tables of the line exceed the LDS. */
 pet_status pet_back(pet_geom g, int subset, const float *sino, const float *mult, float *x_out,
                     int accumulate, int algo, void *stream);
 
@@ -272,6 +283,12 @@ typedef struct {
      * the dense path's up to rounding.  Not with gnorm (PET_E_ARG).  SAGA, SGD,
      * the reverse mode and batches use the dense kernels (PET_E_ARG if set). */
     pet_counts counts;
+    /* Objective at the snapshots (nullable device double): every snapshot
+     * iteration writes Phi(xhat) = D(A xhat + r, y) + beta S(xhat) in FP64,
+     * summed from the snapshot's own subset passes (their per-line KL
+     * partials; with counts, plus <sens, xhat> and the data sums) and one RDP
+     * value pass, so it costs no extra projection (eq. (1), Section 1.2). */
+    double *snap_objective;
 } pet_svrg_state;
 
 /* One epoch = n_subsets iterations of Algorithm 1 with the nonnegativity
@@ -498,7 +515,8 @@ pet_status pet_work_counts(pet_geom g, int subset, double *out, void *stream);
  * one kernel (PET_KERNEL_*) since the last read; reading synchronises on the
  * recorded events and resets that kernel's record. */
 enum { PET_KERNEL_FWD = 0, PET_KERNEL_BACK = 1, PET_KERNEL_GRAD = 2, PET_KERNEL_EM = 3, PET_KERNEL_OBJ = 4,
-       PET_KERNEL_HVP = 6, PET_KERNEL_COUNTS = 7 /* zero-count-aware line kernel, every mode */ };
+       PET_KERNEL_HVP = 6, PET_KERNEL_COUNTS = 7 /* zero-count-aware line kernel, every mode */,
+       PET_KERNEL_GATHER = 8 /* gather adjoint of pet_back */ };
 pet_status pet_profile_enable(pet_geom g, int enable);
 pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms, int64_t *launches);
 

@@ -19,6 +19,7 @@ PET_SCANNER_PARALLEL2D = 0
 PET_SCANNER_CYLINDER = 1
 PET_BACK_AUTO = 0
 PET_BACK_SCATTER = 1
+PET_BACK_GATHER = 2
 PET_Y_F32, PET_Y_U16, PET_Y_U8 = 0, 1, 2
 PET_CHECK = 1
 
@@ -38,6 +39,7 @@ EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "p
 PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
 PET_KERNEL_HVP = 6
 PET_KERNEL_COUNTS = 7
+PET_KERNEL_GATHER = 8
 
 
 class PetError(RuntimeError):
@@ -65,7 +67,7 @@ class SvrgState(ctypes.Structure):
                 ("gamma", ctypes.c_float), ("eps", ctypes.c_float), ("alpha", ctypes.c_float),
                 ("delta", ctypes.c_float), ("omega", ctypes.c_int), ("k", ctypes.c_int64),
                 ("bb", ctypes.c_void_p), ("g_prev", ctypes.c_void_p), ("gnorm", ctypes.c_void_p),
-                ("counts", ctypes.c_void_p)]
+                ("counts", ctypes.c_void_p), ("snap_objective", ctypes.c_void_p)]
 
 
 class SvrgOptions(ctypes.Structure):
@@ -482,7 +484,7 @@ class SvrgStateBuffers:
     Counts made from the same y, add, mult) selects the zero-count-aware path."""
 
     def __init__(self, geom, y, add, mult, sens, beta, gamma, eps, alpha=1.0, delta=0.0, w27=None, kappa=None,
-                 omega=2, bb=False, gnorm=False, counts=None):
+                 omega=2, bb=False, gnorm=False, counts=None, snap_objective=False):
         dev = y.device
         n, nv = geom.n_subsets, geom.n_vox
         self.ghat_i = torch.zeros((n, nv), dtype=torch.float32, device=dev)
@@ -518,6 +520,9 @@ class SvrgStateBuffers:
         c.k = 0
         c.counts = counts.handle.value if counts is not None else None
         self.counts = counts
+        # objective at the snapshots, from the snapshot's own passes
+        self.snap_objective = torch.zeros(1, dtype=torch.float64, device=dev) if snap_objective else None
+        c.snap_objective = self.snap_objective.data_ptr() if snap_objective else None
         self.c = c
 
     @property

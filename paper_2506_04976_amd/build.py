@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpetmi.so")
-SOURCES = ["geom.cpp", "api.cpp", "batch.cpp", "noalloc.cpp", "proj.hip", "counts.hip", "image.hip", "adjoint.hip", "batch.hip"]
+SOURCES = ["geom.cpp", "api.cpp", "batch.cpp", "noalloc.cpp", "proj.hip", "counts.hip", "gather.hip", "image.hip", "adjoint.hip", "batch.hip"]
 ARCH = os.environ.get("PET_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

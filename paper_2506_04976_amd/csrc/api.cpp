@@ -196,12 +196,14 @@ hipError_t hvp_impl(pet_geom g, int subset, const float *x, const float *v, cons
 // Zero-count-aware part of one subset's gradient, -P_i^T[mult y / ybar], into
 // the gradient sheets (the image sheets must hold x); optionally the FP64 sum
 // of y log(y / ybar) over the subset's bins with counts into *ylogy_out.
-hipError_t counts_grad_sheets(pet_geom g, const pet_counts_s *c, int subset, double *ylogy_out, hipStream_t s) {
+hipError_t counts_grad_sheets(pet_geom g, const pet_counts_s *c, int subset, double *ylogy_out, hipStream_t s,
+                              int accumulate = 0) {
     hipError_t e = launch_zero_sheets(g, s);
     ProjArgs a = base_args(g, subset);
     a.partial = ylogy_out ? g->partial : nullptr;
     if (e == hipSuccess) e = launch_line_counts(g, c, M_GRAD, subset, a, s);
-    if (e == hipSuccess && ylogy_out) e = launch_reduce_sum(g->partial, counts_blocks(c, subset), ylogy_out, 0, s);
+    if (e == hipSuccess && ylogy_out)
+        e = launch_reduce_sum(g->partial, counts_blocks(c, subset), ylogy_out, accumulate, s);
     return e;
 }
 
@@ -260,7 +262,10 @@ extern "C" pet_status pet_back(pet_geom g, int subset, const float *sino, const 
                                int accumulate, int algo, void *stream) {
     if (!g || !x_out) return fail(PET_E_ARG, "pet_back: null argument");
     if (!valid_subset(g, subset)) return fail(PET_E_ARG, "pet_back: subset out of range");
-    if (algo != PET_BACK_AUTO && algo != PET_BACK_SCATTER) return fail(PET_E_ARG, "pet_back: unknown algo");
+    if (algo != PET_BACK_AUTO && algo != PET_BACK_SCATTER && algo != PET_BACK_GATHER)
+        return fail(PET_E_ARG, "pet_back: unknown algo");
+    if (algo == PET_BACK_GATHER && gather_lds_bytes(g) > g->max_lds)
+        return fail(PET_E_ARG, "pet_back: the gather's plane tables exceed the LDS for this geometry");
     hipStream_t s = (hipStream_t)stream;
     if (checking(g)) {
         int64_t nb = 0, nl = 0;
@@ -275,7 +280,8 @@ extern "C" pet_status pet_back(pet_geom g, int subset, const float *sino, const 
     ProjArgs a = base_args(g, subset);
     a.sino = sino;
     a.mult = mult;
-    e = launch_line_kernel(g, M_BACK, subset, a, s);
+    // PET_BACK_AUTO takes the scatter, the faster of the two on every measured geometry
+    e = algo == PET_BACK_GATHER ? launch_line_gather(g, subset, a, s) : launch_line_kernel(g, M_BACK, subset, a, s);
     if (e == hipSuccess) e = launch_from_sheets(g, x_out, accumulate, s);
     return hip_check(e, "pet_back");
 }
@@ -435,14 +441,26 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
         if (st->bb && k == 0) e = launch_bb_init(st->bb, s);
         if (e == hipSuccess) e = launch_to_sheets(g, x, s);
         if (snap) {
+            // with snap_objective, the snapshot's own passes also sum the data
+            // term at xhat (no extra projection)
+            double *so = st->snap_objective;
             for (int q = 0; q < n && e == hipSuccess; ++q) {
-                e = st->counts ? counts_grad_sheets(g, st->counts, q, nullptr, s)
-                               : subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+                e = st->counts ? counts_grad_sheets(g, st->counts, q, so, s, q > 0)
+                               : subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, so, q > 0, s);
                 // zero-count-aware tables hold the x-dependent parts; ghat starts from sens
                 if (e == hipSuccess)
                     e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s,
                                               st->counts ? st->sens : nullptr);
             }
+            if (e == hipSuccess && so && st->counts) {
+                // D = <sens, x> + sum r - sum y + sum y log(y / ybar)
+                e = launch_dot(st->sens, x, nv, g->partial, so, 1, s);
+                const pet_counts_s *c = st->counts;
+                if (e == hipSuccess) e = launch_add_scalar(so, c->sum_add[c->n_subsets] - c->sum_y[c->n_subsets], s);
+            }
+            if (e == hipSuccess && so)
+                e = launch_rdp(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, nullptr, nullptr, g->partial, s);
+            if (e == hipSuccess && so) e = launch_reduce_sum(g->partial, rdp_blocks(g), so, 1, s);
             // BB bookkeeping: 0 none, 1 keep the full gradient, 2 also recompute the step bound
             const int bb_mode = !st->bb ? 0 : (opt && opt->bb_update && opt->bb_update[j] && k > 0) ? 2 : 1;
             float *grad_out = st->gnorm ? g->num : nullptr;
@@ -586,7 +604,7 @@ extern "C" pet_status pet_geom_set_flags(pet_geom g, unsigned flags) {
 
 extern "C" pet_status pet_profile_read(pet_geom g, int kernel, double *total_ms, int64_t *launches) {
     if (!g || !total_ms || !launches) return fail(PET_E_ARG, "pet_profile_read: null argument");
-    if (kernel < 0 || kernel > PROF_COUNTS || kernel == M_COUNT) return fail(PET_E_ARG, "pet_profile_read: unknown kernel");
+    if (kernel < 0 || kernel > PROF_GATHER || kernel == M_COUNT) return fail(PET_E_ARG, "pet_profile_read: unknown kernel");
     double ms = 0.0;
     auto &v = g->prof_events[kernel];
     for (auto &ev : v) {

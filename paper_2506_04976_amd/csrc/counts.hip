@@ -153,10 +153,22 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     double kl = 0.0;
     const int64_t i0 = c.line_off[line], i1 = c.line_off[line + 1];
     const float umax = (float)(a.nz + PADZ);
+    // C lanes per bin (a power of two, consecutive lanes of one wave) take every
+    // C-th sample of its window; C grows while the line's bins still fill the
+    // workgroup, so that lines with few bins keep every wave busy
+    const int n_it = (int)(i1 - i0);
+    int C = 1;
+    while (C < 16 && n_it * (2 * C) <= (int)blockDim.x) C *= 2;
+    const int ch = threadIdx.x & (C - 1);
+    const int nslot = blockDim.x / C;
     // (a line that misses the image still has bins with counts: ybar = add there,
     // and its y log(y / add) enters the sum; its sample ranges are empty)
-    for (int64_t it = i0 + threadIdx.x; it < i1; it += blockDim.x) {
-        const CountItem e = c.items[it];
+    for (int64_t it0 = i0; it0 < i1; it0 += nslot) {
+        // every lane runs every round: the forward sums are added across the
+        // C lanes of a bin by shuffles
+        const int64_t it = it0 + threadIdx.x / C;
+        const bool act = it < i1;
+        const CountItem e = act ? c.items[it] : CountItem{0u, 0.f, 1.f, 0.f};
         const int p = TOF ? (int)(e.pt / (uint32_t)c.n_tof) : (int)e.pt;
         const int b = TOF ? (int)(e.pt - (uint32_t)p * (uint32_t)c.n_tof) : 0;
         const PlaneP P = a.planes[p];
@@ -164,6 +176,7 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
         const float ell = L.vm_um * len;
         int is, ie;
         z_clip(L, P, a.nz, is, ie);
+        if (!act) ie = is - 1;
         // d(i) = t(i) - t_b, t(i) = (lambda(i) - 1/2) |u| the signed distance
         // from the LOR centre; rows outside |d| <= D (one row of margin, where
         // the table gives 0) are skipped
@@ -180,20 +193,22 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
         }
         const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
         float s = 0.f;
-        const float *xr = X + (is - L.i_lo) * rz;
-        for (int i = is; i <= ie; ++i, xr += rz) {
+        const float *xr = X + (is + ch - L.i_lo) * rz;
+        for (int i = is + ch; i <= ie; i += C, xr += C * rz) {
             const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
             const int j = (int)u;
             const float x0 = xr[j], x1 = xr[j + 1];
             const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
             s = TOF ? fmaf(tof_weight(tab, fmaf((float)i, dd, d0), c), v, s) : s + v;
         }
+        for (int o = 1; o < C; o <<= 1) s += __shfl_xor(s, o, 64);
+        if (!act) continue;
         const float ybar = fmaf(e.mult, s * ell, e.add);
-        kl += (double)e.y * log((double)e.y / (double)ybar);
+        if (ch == 0) kl += (double)e.y * log((double)e.y / (double)ybar);
         if (NEED_Z) {
             const float Q = -e.mult * (e.y / ybar) * ell;
-            double *zr = Z + (is - L.i_lo) * rz;
-            for (int i = is; i <= ie; ++i, zr += rz) {
+            double *zr = Z + (is + ch - L.i_lo) * rz;
+            for (int i = is + ch; i <= ie; i += C, zr += C * rz) {
                 const float qw = TOF ? Q * tof_weight(tab, fmaf((float)i, dd, d0), c) : Q;
                 const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
                 const int j = (int)u;
@@ -249,16 +264,16 @@ hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *cs, int mode, i
     c.items = cs->items;
     c.line_off = cs->line_off;
     c.lines = cs->lines + cs->lines_off[subset < 0 ? cs->n_subsets : subset];
-    c.wtab = cs->wtab;
+    c.wtab = g->wtab;
     c.nw = NW_TAB;
     c.n_tof = g->d.n_tof;
-    c.wD = cs->wD;
-    c.inv_dx = (float)(NW_TAB / (2.0 * cs->wD));
+    c.wD = g->wD;
+    c.inv_dx = (float)(NW_TAB / (2.0 * g->wD));
     c.pos0 = (float)(NW_TAB / 2);
     c.pos_max = (float)NW_TAB - 1e-3f;
     const size_t lds = counts_lds_bytes(g, mode);
     const bool tof = g->d.n_tof > 1;
-    const int threads = tof ? CNT_BLOCK : CNT_BLOCK / 2;
+    const int threads = CNT_BLOCK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipSuccess;
     if (g->profiling) {
@@ -361,22 +376,6 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
     if (e == hipSuccess) e = hipMalloc(&c->lines, sizeof(int) * std::max<size_t>(lines.size(), 1));
     if (e == hipSuccess && !lines.empty())
         e = hipMemcpy(c->lines, lines.data(), sizeof(int) * lines.size(), hipMemcpyHostToDevice);
-    // TOF weight table: W at NW_TAB + 1 nodes over |d| <= D = w/2 + nsig sigma
-    if (g->d.n_tof > 1) {
-        const double h = 0.5 * g->d.tof_bin_mm, sig = g->d.tof_sigma_mm, cl = g->d.tof_nsigma / std::sqrt(2.0);
-        const double D = h + g->d.tof_nsigma * sig;
-        c->wD = (float)D;
-        auto E = [&](double u) { return std::erf(std::min(std::max(u / (std::sqrt(2.0) * sig), -cl), cl)); };
-        std::vector<double> W(NW_TAB + 1);
-        for (int k = 0; k <= NW_TAB; ++k) {
-            const double d = -D + 2.0 * D * k / NW_TAB;
-            W[k] = k == 0 || k == NW_TAB ? 0.0 : 0.5 * (E(h - d) - E(-h - d));
-        }
-        std::vector<float2> tab(NW_TAB);
-        for (int k = 0; k < NW_TAB; ++k) tab[k] = make_float2((float)W[k], (float)(W[k + 1] - W[k]));
-        if (e == hipSuccess) e = hipMalloc(&c->wtab, sizeof(float2) * NW_TAB);
-        if (e == hipSuccess) e = hipMemcpy(c->wtab, tab.data(), sizeof(float2) * NW_TAB, hipMemcpyHostToDevice);
-    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (d_cnt) (void)hipFree(d_cnt);
     if (d_ys) (void)hipFree(d_ys);
@@ -393,7 +392,7 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
 extern "C" pet_status pet_counts_destroy(pet_counts c) {
     if (!c) return PET_OK;
     (void)hipDeviceSynchronize();
-    void *ptrs[] = {c->items, c->line_off, c->lines, c->wtab};
+    void *ptrs[] = {c->items, c->line_off, c->lines};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;

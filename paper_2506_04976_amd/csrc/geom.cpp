@@ -280,6 +280,8 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
         if (hsegs.empty() || planes[p].seg != planes[p - 1].seg) hsegs.push_back({(int)p, 0, hplanes[p].dz2, 0});
         hsegs.back().np++;
     }
+    // the plain segment list in plane order (the gather adjoint walks it)
+    const std::vector<SegP> gsegs = hsegs;
     if (d.n_tof > 1) {
         // segments -k and +k (adjacent in the plane order) have the same
         // oblique length and so the same TOF weight table: one segment wave
@@ -404,6 +406,7 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     g->n_partial = std::max<size_t>(2 * (size_t)nl, 2 * (size_t)((g->n_vox + IMG_BLOCK - 1) / IMG_BLOCK)) + 64;
     bool ok = alloc((void **)&g->lines, sizeof(LineP) * nl) && alloc((void **)&g->planes, sizeof(PlaneP) * planes.size()) &&
               alloc((void **)&g->segs, sizeof(SegP) * hsegs.size()) &&
+              alloc((void **)&g->gsegs, sizeof(SegP) * gsegs.size()) &&
               alloc((void **)&g->views_dev, sizeof(int) * hviews.size()) &&
               alloc((void **)&g->line_order, sizeof(int) * horder.size()) &&
               alloc((void **)&g->T0, sizeof(float) * g->t0_elems) && alloc((void **)&g->T1, sizeof(float) * g->t1_elems) &&
@@ -423,8 +426,26 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     hipError_t e = hipMemcpy(g->lines, hlines.data(), sizeof(LineP) * nl, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->planes, hplanes.data(), sizeof(PlaneP) * planes.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->segs, hsegs.data(), sizeof(SegP) * hsegs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(g->gsegs, gsegs.data(), sizeof(SegP) * gsegs.size(), hipMemcpyHostToDevice);
+    g->n_gseg = (int)gsegs.size();
     if (e == hipSuccess) e = hipMemcpy(g->views_dev, hviews.data(), sizeof(int) * hviews.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(g->line_order, horder.data(), sizeof(int) * horder.size(), hipMemcpyHostToDevice);
+    // TOF weight table (FP64 nodes): W at NW_TAB + 1 nodes over |d| <= D = bin/2 + nsig sigma
+    if (e == hipSuccess && d.n_tof > 1) {
+        const double h = 0.5 * d.tof_bin_mm, sig = d.tof_sigma_mm, cl = d.tof_nsigma / std::sqrt(2.0);
+        const double D = h + d.tof_nsigma * sig;
+        g->wD = (float)D;
+        auto E = [&](double u) { return std::erf(std::min(std::max(u / (std::sqrt(2.0) * sig), -cl), cl)); };
+        std::vector<double> W(NW_TAB + 1);
+        for (int k = 0; k <= NW_TAB; ++k) {
+            const double dd = -D + 2.0 * D * k / NW_TAB;
+            W[k] = k == 0 || k == NW_TAB ? 0.0 : 0.5 * (E(h - dd) - E(-h - dd));
+        }
+        std::vector<float2> tab(NW_TAB);
+        for (int k = 0; k < NW_TAB; ++k) tab[k] = make_float2((float)W[k], (float)(W[k + 1] - W[k]));
+        e = hipMalloc(&g->wtab, sizeof(float2) * NW_TAB);
+        if (e == hipSuccess) e = hipMemcpy(g->wtab, tab.data(), sizeof(float2) * NW_TAB, hipMemcpyHostToDevice);
+    }
     // padded sheet borders must be zero once; interiors are rewritten per use
     if (e == hipSuccess) e = hipMemset(g->T0, 0, sizeof(float) * g->t0_elems);
     if (e == hipSuccess) e = hipMemset(g->T1, 0, sizeof(float) * g->t1_elems);
@@ -452,7 +473,7 @@ extern "C" pet_status pet_geom_destroy(pet_geom g) {
     }
     void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->line_order, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
                     g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch, g->psf_a, g->psf_b,
-                    g->check_counts};
+                    g->check_counts, g->wtab, g->gsegs};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete g;

@@ -103,7 +103,7 @@ struct CountItem {
 };
 static_assert(sizeof(CountItem) == 16, "CountItem layout");
 constexpr int NW_TAB = 4096;    // intervals of the tabulated TOF weight W(d)
-constexpr int CNT_BLOCK = 512;  // threads per workgroup of the counts line kernel (TOF; non-TOF: half)
+constexpr int CNT_BLOCK = 1024;  // threads per workgroup of the counts line kernel
 
 struct CountArgs {
     const CountItem *items;
@@ -176,6 +176,8 @@ struct pet_geom_s {
     pet::LineP *lines = nullptr;
     pet::PlaneP *planes = nullptr;
     pet::SegP *segs = nullptr;
+    pet::SegP *gsegs = nullptr;         // plain segments in plane order (gather adjoint)
+    int n_gseg = 0;
     int n_seg = 0, rows_max = 0, tof_ws = 0, tof_tstride = 0, tof_waves = 0;
     int nt_threads = pet::NT_BLOCK;     // non-TOF line kernel: threads per workgroup
     int *views_dev = nullptr;           // [n_subsets + 1][max(max_views, n_views)]; last row: all views
@@ -185,6 +187,11 @@ struct pet_geom_s {
     int *line_order = nullptr;
     std::vector<int64_t> order_off;
     pet::TofTable tof{};
+    // TOF weight of a point at signed distance d from a bin centre,
+    // W(d) = 1/2 [E(bin/2 - d) - E(-bin/2 - d)] (E the clamped erf), at NW_TAB + 1
+    // nodes over its support |d| <= wD, as (W_k, W_{k+1} - W_k) pairs
+    float2 *wtab = nullptr;
+    float wD = 0.f;
     size_t lds_bytes = 0;
     size_t max_lds = 0;                 // the device's LDS limit per workgroup
     // scratch arena
@@ -200,7 +207,7 @@ struct pet_geom_s {
     unsigned *check_counts = nullptr;
     // optional HIP-event timing of the line kernels, per mode
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[pet::M_NMODES + 1];  // last: counts kernel
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events[pet::M_NMODES + 2];  // then: counts, gather kernels
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
 };
 
@@ -213,8 +220,6 @@ struct pet_counts_s {
     pet::CountItem *items = nullptr;  // sinogram order
     int64_t *line_off = nullptr;      // [n_lines + 1]
     int *lines = nullptr;             // per subset (then all views): lines with counts, most first
-    float2 *wtab = nullptr;           // TOF weight table (NW_TAB entries)
-    float wD = 0.f;
     std::vector<int64_t> lines_off;        // [n_subsets + 2] offsets into lines
     std::vector<int64_t> items_per_subset; // [n_subsets + 1]
     std::vector<double> sum_y, sum_add;    // [n_subsets + 1] over every bin of the subset (then all)
@@ -222,7 +227,8 @@ struct pet_counts_s {
 
 namespace pet {
 
-constexpr int PROF_COUNTS = M_NMODES;  // profiling slot of the counts line kernel
+constexpr int PROF_COUNTS = M_NMODES;      // profiling slot of the counts line kernel
+constexpr int PROF_GATHER = M_NMODES + 1;  // and of the gather adjoint
 
 // error state (api.cpp)
 pet_status fail(pet_status s, const std::string &msg);
@@ -252,6 +258,10 @@ hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *c, int mode, in
                               hipStream_t s);
 int counts_blocks(const pet_counts_s *c, int subset);
 size_t counts_lds_bytes(const pet_geom_s *g, int mode);
+
+// cell-driven (gather) adjoint into the gradient sheets (gather.hip)
+hipError_t launch_line_gather(pet_geom_s *g, int subset, const ProjArgs &a, hipStream_t s);
+size_t gather_lds_bytes(const pet_geom_s *g);
 
 // image kernels (image.hip)
 // Work buffers of the sheet conversions: transposed image sheets T0 / T1,

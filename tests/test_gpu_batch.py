@@ -28,7 +28,7 @@ class Member:
     def __init__(self, name, beta_factor):
         import paper_2506_04976_amd as pm
         self.pm = pm
-        self.cfg = configs.get(name)
+        self.cfg = configs.get(name) if isinstance(name, str) else dict(name)
         self.d = data.make_dataset(self.cfg)
         dev = torch.device("cuda:0")
         self.dev = dev
@@ -194,4 +194,37 @@ def test_batch_autotune_keeps_results(members):
              [[v for e in range(E) for v in s[2][e]] for s in scheds])
     for m, (_, _, x1), (_, _, x2) in zip(members, ref, runs):
         assert _rel(x2, x1) <= 1e-5, m.cfg["name"]
+    b.close()
+
+
+def test_batch_c4_sized_members_match_individual_runs():
+    # members at the batched workload's real sizes: a 128x128x71 TOF member
+    # (2204 planes x 13 TOF bins) beside a 96x96x32 non-TOF one
+    big = configs.batch_size_config(2, True)
+    big.update(counts=2e7, n_subsets=25, seed=2001)
+    big["beta"] = configs.beta_value(big)
+    small = configs.batch_size_config(0, False)
+    small.update(counts=3e6, n_subsets=8, seed=2002)
+    small["beta"] = configs.beta_value(small) * 2.0
+    _say("\n[batch c4 sizes] building members")
+    ms = [Member(big, 1.0), Member(small, 1.0)]
+    pm = ms[0].pm
+    E = 2
+    ref = [m.runner() for m in ms]
+    for m, (g, st, x) in zip(ms, ref):
+        orders, taus, upd = m.schedule(E)
+        for e in range(E):
+            pm.pet_svrg_epoch(g, st, x, orders[e], taus[e], upd[e])
+    runs = [m.runner() for m in ms]
+    b = pm.Batch(runs)
+    scheds = [m.schedule(E) for m in ms]
+    b.epochs([[int(v) for e in range(E) for v in s[0][e]] for s in scheds],
+             [[v for e in range(E) for v in s[1][e]] for s in scheds],
+             [[v for e in range(E) for v in s[2][e]] for s in scheds])
+    torch.cuda.synchronize()
+    for m, (_, st1, x1), (_, st2, x2) in zip(ms, ref, runs):
+        err = _rel(x2, x1)
+        _say(f"[batch c4 sizes] {m.cfg['name']}: batched vs single relative L2 {err:.2e}")
+        assert err <= 1e-5, m.cfg["name"]
+        assert st2.k == st1.k == E * m.cfg["n_subsets"]
     b.close()

@@ -164,3 +164,29 @@ def test_counts_argument_errors(case):
         pm.pet_svrg_epoch(case.geom, stg, case.x.clone(), seq, tau, upd)
     torch.cuda.synchronize()
     other.close()
+
+
+def test_snapshot_objective(case):
+    # the objective at each snapshot, summed from the snapshot's own passes
+    # (dense and zero-count-aware), against the oracle's objective at xhat
+    pm = case.pm
+    cfg, n = case.cfg, case.cfg["n_subsets"]
+    beta = configs.beta_value(cfg)
+    sens = case.sens_subset(-1)
+    x0 = torch.ones(case.geom.n_vox, device=case.dev)
+    xmax = torch.zeros(1, device=case.dev)
+    pm.pet_osem_epoch(case.geom, x0, case.y, case.r, case.a, list(range(n)), xmax)
+    eps = 1e-3 * float(xmax.cpu())
+    prob = recon.Problem(cfg, case.d["y"], case.d["r"], case.d["mult"], beta=beta, gamma=2.0, eps=eps)
+    orders = data.subset_orders(cfg, 3)
+    for counts in (None, case.counts):
+        x = x0.clone()
+        st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=beta, gamma=2.0, eps=eps,
+                                 alpha=1.0, delta=eps, counts=counts, snap_objective=True)
+        for e in range(3):
+            ks = [e * n + j for j in range(n)]
+            pm.pet_svrg_epoch(case.geom, st, x, orders[e], [1.0] * n, [k in (0, n, 2 * n) for k in ks])
+            if e % 2 == 0:  # epochs 0 and 2 start with a snapshot
+                got = float(st.snap_objective.cpu())
+                ref = prob.objective(st.x_snap.cpu().double().numpy().reshape(prob.shape))
+                assert got == pytest.approx(ref, rel=1e-5), (counts is not None, e)

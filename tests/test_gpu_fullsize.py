@@ -6,6 +6,10 @@ benchmark uses (whole subsets of the 3D geometries).
 * Fused subset gradient: the multiplicative factors of every view but one are
   zeroed, so the GPU subset gradient equals the gradient of that one view, which
   the oracle computes in full (cancellation-aware error <= 1e-5).
+* Whole-subset gradient (every view of one subset, the data's own factors),
+  dense and zero-count-aware, against the oracle computed view by view.
+* The 3D non-TOF image after OSEM + 2 SVRG epochs (dense and zero-count-aware)
+  against a stored oracle image of the same schedule (relative L2 <= 1e-4).
 * 3D image after 10 SVRG epochs on the small 3D geometry (96x96x32, 268 planes,
   8 subsets): relative L2 <= 1e-4 against the oracle.
 * The GPU adjoint identity on a whole TOF subset.
@@ -108,6 +112,52 @@ def test_fullsize_subset_grad_one_view(big):
     assert float(kl.cpu()) == pytest.approx(kl_ref, rel=1e-6)
 
 
+def test_fullsize_whole_subset_gradient(big):
+    # One whole subset (every view, the data's own mult): the dense fused
+    # gradient and the zero-count-aware gradient against the FP64 oracle's
+    # subset gradient, computed view by view (cancellation-aware <= 1e-5), and
+    # the subset KL (relative 1e-6).
+    cfg, pm, d, dev = big["cfg"], big["pm"], big["d"], big["dev"]
+    subset = 2
+    geom = big["geom"]
+    g = torch.empty(geom.n_vox, device=dev)
+    kl = torch.zeros(1, dtype=torch.float64, device=dev)
+    pm.pet_subset_grad(geom, subset, big["x"], big["y"], big["r"], big["a"], g, kl)
+    cnt = pm.Counts(geom, big["y"], big["r"], big["a"])
+    sens = torch.empty(geom.n_vox, device=dev)
+    pm.pet_back(geom, subset, None, big["a"], sens)
+    gc = torch.empty(geom.n_vox, device=dev)
+    klc = torch.zeros(1, dtype=torch.float64, device=dev)
+    pm.pet_subset_grad_counts(geom, cnt, subset, big["x"], sens, gc, klc)
+    g_gpu, gc_gpu = g.cpu().double().numpy(), gc.cpu().double().numpy()
+    cnt.close()
+    T = cfg["n_tof"]
+    ref = np.zeros(geom.n_vox)
+    absref = np.zeros(geom.n_vox)
+    kl_ref = 0.0
+    views = configs.subset_views(cfg, subset)
+    for j, view in enumerate(views):
+        p1, p2 = projector.view_lors(cfg, [view])
+        a = d["mult"][view].reshape(-1, 1).astype(np.float64)
+        r = d["r"][view].reshape(-1, T).astype(np.float64)
+        y = d["y"][view].reshape(-1, T).astype(np.float64)
+        yb = a * projector.fwd(cfg, big["gx"], p1, p2) + r
+        ref += projector.back(cfg, a * (1.0 - y / yb), p1, p2).ravel()
+        absref += projector.back(cfg, a * (1.0 + y / yb), p1, p2).ravel()
+        kl_ref += float(np.sum(poisson.kl(yb, y)))
+        _say(f"[{cfg['name']}] oracle view {j + 1}/{len(views)}")
+    ref = psf.blur(ref.reshape(geom.shape), cfg).ravel()
+    scale = np.linalg.norm(psf.blur(absref.reshape(geom.shape), cfg))
+    err = np.linalg.norm(g_gpu - ref) / scale
+    err_c = np.linalg.norm(gc_gpu - ref) / scale
+    _say(f"[{cfg['name']}] whole-subset gradient, cancellation-aware error: dense {err:.2e}, "
+         f"zero-count-aware {err_c:.2e}")
+    assert err <= 1e-5
+    assert err_c <= 1e-5
+    assert float(kl.cpu()) == pytest.approx(kl_ref, rel=1e-6)
+    assert float(klc.cpu()) == pytest.approx(kl_ref, rel=1e-6)
+
+
 def test_fullsize_adjoint_identity(big):
     pm, geom, dev = big["pm"], big["geom"], big["dev"]
     gen = torch.Generator(device=dev).manual_seed(3)
@@ -126,6 +176,53 @@ def test_fullsize_adjoint_identity(big):
     rhs = float(torch.dot(xv.double(), pty.double()))
     _say(f"[{big['cfg']['name']}] adjoint identity relative gap {abs(lhs - rhs) / abs(lhs):.2e}")
     assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
+
+
+def test_c1_osem_two_epochs_against_golden():
+    # The 3D non-TOF brain-sized workload after one OSEM epoch from x = 1 and
+    # two epochs of preconditioned SVRG, dense and zero-count-aware, against
+    # the FP64 oracle's image of the same schedule (stored by
+    # tests/golden/make_c1_osem_2epochs.py, which runs the oracle alone).
+    import os
+    import paper_2506_04976_amd as pm
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_3d_osem_2epochs.npz")
+    gold = np.load(path)
+    cfg = configs.get("c1_3d")
+    n, epochs = cfg["n_subsets"], int(gold["epochs"])
+    _say("\n[c1 golden] generating data")
+    d = data.make_dataset(cfg)
+    dev = torch.device("cuda:0")
+    geom = pm.Geometry(cfg)
+    y = torch.from_numpy(d["y"].reshape(-1)).to(dev)
+    r = torch.from_numpy(d["r"].reshape(-1)).to(dev)
+    a = torch.from_numpy(d["mult"].reshape(-1)).to(dev)
+    del d
+    beta = configs.beta_value(cfg)
+    assert beta == pytest.approx(float(gold["beta"]), rel=1e-12)
+    orders = data.subset_orders(cfg, epochs)
+    assert np.array_equal(np.asarray(orders), gold["orders"])
+    sens = torch.empty(geom.n_vox, device=dev)
+    pm.pet_back(geom, -1, None, a, sens)
+    cnt = pm.Counts(geom, y, r, a)
+    x_ref = gold["x"].astype(np.float64).ravel()
+    tau = recon.stepsize_vanishing(1.0, 0.02, n)
+    upd = recon.pc_update_iters(n)
+    for name, c in (("dense", None), ("zero-count-aware", cnt)):
+        x = torch.ones(geom.n_vox, device=dev)
+        xmax = torch.zeros(1, device=dev)
+        pm.pet_osem_epoch(geom, x, y, r, a, list(range(n)), xmax)
+        mx = float(xmax.cpu())
+        assert mx == pytest.approx(float(gold["x_osem_max"]), rel=1e-5)
+        st = pm.SvrgStateBuffers(geom, y, r, a, sens, beta=beta, gamma=2.0, eps=1e-3 * mx, alpha=1.0,
+                                 delta=1e-3 * mx, counts=c)
+        for e in range(epochs):
+            ks = [e * n + j for j in range(n)]
+            pm.pet_svrg_epoch(geom, st, x, orders[e], [tau(k) for k in ks], [k in upd for k in ks])
+        err = np.linalg.norm(x.cpu().double().numpy() - x_ref) / np.linalg.norm(x_ref)
+        _say(f"[c1 golden] {name}: OSEM + {epochs} epochs, relative L2 {err:.2e}")
+        assert err <= 1e-4
+    cnt.close()
+    geom.close()
 
 
 def test_c3_reconstruction_parity():
