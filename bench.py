@@ -8,10 +8,13 @@ at 3 sigma (2.48e9 TOF bins), head phantom with 3e7 true counts, background
 r = 20% of prompts, 25 subsets, RDP gamma = 2 with 26 neighbours, harmonic
 preconditioner updated in epochs 1-3, stepsize 1 / (1 + 0.02 k / n).
 
-A step is one SVRG epoch (n iterations of the fused subset gradient, the RDP
+A step is one SVRG epoch (n iterations of the subset gradient, the RDP
 stencil, the preconditioner (first epochs) and the clipped update; every
-second epoch starts with a full snapshot pass).  Inputs are synthetic and
-resident in HBM before timing starts.  One JSON line is printed.
+second epoch starts with a full snapshot pass).  The headline runs the
+zero-count-aware data term (only bins with counts are projected; the
+sensitivity terms cancel in the estimator); the dense path is timed on the
+same schedule beside it.  Inputs are synthetic and resident in HBM before
+timing starts.  One JSON line is printed.
 """
 
 import argparse
@@ -26,21 +29,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SVRG epochs/s (fwd+back+RDP), 3D TOF; HBM GB/s vs peak; time to NRMSE<1%"
 
-# Algorithmic floating-point work of the fused subset gradient (forward
-# projection, ratio, backprojection): per Joseph sample, the z position (2) and
-# bilinear interpolation (9) forward plus the position (2), bilinear spread (6)
-# and accumulation (4) backward; per sample-TOF-bin pair, the TOF weight as a
-# tabulated function (5) and its multiply-accumulate (2), forward and backward.
-FLOP_PER_SAMPLE = 23.0
-FLOP_PER_PAIR_TOF = 14.0
-FLOP_PER_SAMPLE_NONTOF = 2.0  # accumulate forward + scale backward
-PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
 PEAK_HBM_GBPS = 8000.0
 
-# HBM bytes per launch of the fused TOF subset gradient, from calibrated
-# FETCH_SIZE / WRITE_SIZE counter runs, valid for the kernel source with this
-# hash only (reported as null otherwise).
-MEASURED_TRAFFIC = {"c2_tof": (734.2e6, "f18974dcd45122bc")}
+# HBM bytes per launch of the zero-count-aware subset-gradient kernel, from
+# calibrated FETCH_SIZE / WRITE_SIZE counter runs, and its VALU issue fraction
+# (SQ counters), valid for the kernel source with this hash only (reported as
+# null otherwise).
+MEASURED_TRAFFIC = {"c2_tof": (192.0e6, "093b29dd7b4f34aa")}
+MEASURED_VALU = {"c2_tof": (0.63, "093b29dd7b4f34aa")}
 
 
 def log(msg):
@@ -48,46 +44,80 @@ def log(msg):
 
 
 def cpu_baseline(cfg, d, x0, beta, eps, view=0):
-    """Time the FP64 oracle's subset-gradient arithmetic on one view and scale
-    it to one SVRG epoch (data passes per epoch x views) plus the prior."""
-    import numpy as np
-    from oracle import projector, rdp
-    from synth import configs
+    """Time the FP64 oracle's subset-gradient arithmetic (forward projection,
+    ratio, backprojection) on a strided sample of one view's LORs, built with
+    gcc -O3 -march=native on this host, with 1 thread and with every core of
+    the process's affinity set: median of 5 timed runs after one warm-up each.
+    The per-LOR time is scaled to one SVRG epoch (data passes per epoch x all
+    LORs) plus n RDP gradients of the image (numpy, timed the same way)."""
+    import statistics
+    import tempfile
 
-    threads = len(os.sched_getaffinity(0))
-    os.environ["ORACLE_THREADS"] = str(threads)
-    projector._NTHREADS = threads
+    import numpy as np
+    import oracle
+    from oracle import projector, rdp
+
+    cores = len(os.sched_getaffinity(0))
+    tmp = tempfile.mkdtemp(prefix="pet_oracle_")
+    oracle.use_library(oracle.build_native(tmp))
     T = cfg["n_tof"]
     p1, p2 = projector.view_lors(cfg, [view])
     a = d["mult"][view].reshape(-1, 1).astype(np.float64)
     r = d["r"][view].reshape(-1, T).astype(np.float64)
     y = d["y"][view].reshape(-1, T).astype(np.float64)
     x = np.asarray(x0, np.float64).reshape(cfg["nz"], cfg["ny"], cfg["nx"])
-    t0 = time.perf_counter()
-    yb = a * projector.fwd(cfg, x, p1, p2) + r
-    g = projector.back(cfg, a * (1.0 - y / yb), p1, p2)
-    t_view = time.perf_counter() - t0
+    n_lor = p1.shape[0]
+
+    def timed(threads, stride, reps=5):
+        projector._NTHREADS = threads
+        sel = slice(0, None, stride)
+        q1, q2, aa, rr, yy = p1[sel], p2[sel], a[sel], r[sel], y[sel]
+
+        def once():
+            t0 = time.perf_counter()
+            yb = aa * projector.fwd(cfg, x, q1, q2) + rr
+            projector.back(cfg, aa * (1.0 - yy / yb), q1, q2)
+            return time.perf_counter() - t0
+
+        once()
+        return statistics.median(once() for _ in range(reps)) / q1.shape[0], q1.shape[0]
+
+    # samples sized for a few seconds per run: 1/64 of the view on 1 thread,
+    # 1/4 on all cores
+    t1, n1 = timed(1, 64)
+    tn, nn = timed(cores, 4)
     w = rdp.default_weights(cfg["vx"], cfg["vy"], cfg["vz"], cfg["nz"])
-    t0 = time.perf_counter()
     rdp.grad(x, w, 2.0, eps)
-    t_rdp = time.perf_counter() - t0
+    t_rdp = statistics.median(
+        (lambda t0: (rdp.grad(x, w, 2.0, eps), time.perf_counter() - t0)[1])(time.perf_counter()) for _ in range(5))
     n = cfg["n_subsets"]
     passes = (3 * n - 1) / (2 * n)  # data passes per epoch with a snapshot every 2 epochs
-    epoch_s = passes * cfg["n_views"] * t_view + n * t_rdp
-    del g
-    return {"value": 1.0 / epoch_s, "unit": "epochs/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle fused subset gradient (fwd, ratio, back) on view {view} "
-                      f"({p1.shape[0]} LORs x {T} TOF bins) in {t_view:.1f} s plus one RDP gradient in "
-                      f"{t_rdp:.2f} s, scaled by {passes:.3f} data passes x {cfg['n_views']} views and "
-                      f"{n} RDP evaluations per epoch"}
+    lors = cfg["n_views"] * n_lor
+
+    def epochs_per_s(t_lor):
+        return 1.0 / (passes * lors * t_lor + n * t_rdp)
+
+    return {"value": epochs_per_s(tn), "unit": "epochs/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": epochs_per_s(t1),
+            "sample": f"FP64 oracle (gcc -O3 -march=native) fused subset gradient (fwd, ratio, back) on every "
+                      f"4th LOR of view {view} ({nn} LORs x {T} TOF bins, {cores} threads: {1e6 * tn:.2f} us/LOR) "
+                      f"and every 64th ({n1} LORs, 1 thread: {1e6 * t1:.2f} us/LOR), median of 5 after a "
+                      f"warm-up; numpy RDP gradient {t_rdp:.2f} s; scaled by {passes:.3f} data passes x "
+                      f"{lors} LORs and {n} RDP gradients per epoch (extrapolated)"}
 
 
-def map_reference(cfg, geom, pm, y, r, a, sens, beta, eps, delta, x0, max_iter):
+def map_reference(cfg, geom, pm, cnt, sens, beta, eps, delta, x0, max_iter, target):
     """Converged MAP image x* by preconditioned L-BFGS-B (as the paper's own
     reference reconstructions): variables z with x = s z, s = sqrt(D) for the
-    harmonic preconditioner D at the initial image, bounds z >= 0, each
-    evaluation one fused full-data pass (gradient + FP64 KL) plus the RDP
-    gradient and FP64 value."""
+    harmonic preconditioner D at the initial image, bounds z >= 0.  Each
+    evaluation is one zero-count-aware pass over all views (gradient and FP64
+    KL from the bins with counts) plus the RDP gradient and FP64 value.
+    L-BFGS-B stops when its line search cannot make progress; it is restarted
+    from its last point (fresh curvature pairs) until the KKT residual
+    ||min(x, grad Phi)|| / ||grad Phi(x0)|| reaches `target`, max_iter
+    iterations are spent, or a restart gains less than 1%.  The residual's
+    floor from FP32 arithmetic is measured as the spread of two gradient
+    evaluations at the same point (different atomic summation orders)."""
     import numpy as np
     import scipy.optimize as so
     import torch
@@ -100,9 +130,7 @@ def map_reference(cfg, geom, pm, y, r, a, sens, beta, eps, delta, x0, max_iter):
     sv = torch.zeros(1, dtype=torch.float64, device=dev)
 
     def value_grad(img):
-        kl.zero_()
-        sv.zero_()
-        pm.pet_subset_grad(geom, -1, img, y, r, a, g, kl)
+        pm.pet_subset_grad_counts(geom, cnt, -1, img, sens, g, kl)
         pm.pet_rdp_grad_hessdiag(geom, img, None, w27, beta, cfg["gamma"], eps, gp, None, sv)
         return float(kl.cpu()) + float(sv.cpu()), g.double() + gp.double()
 
@@ -112,25 +140,43 @@ def map_reference(cfg, geom, pm, y, r, a, sens, beta, eps, delta, x0, max_iter):
     pm.pet_precond(geom, x0, sens, h, 1.0, delta, D)
     s = torch.sqrt(D.double())
     s_np = s.cpu().numpy()
-    z0 = np.where(s_np > 0, x0.double().cpu().numpy() / np.where(s_np > 0, s_np, 1.0), 0.0)
+    z = np.where(s_np > 0, x0.double().cpu().numpy() / np.where(s_np > 0, s_np, 1.0), 0.0)
+    g0 = value_grad(x0)[1]
+    g0n = float(g0.norm())
+    floor = float((value_grad(x0)[1] - g0).norm()) / g0n
 
-    def fun(z):
-        f, gr = value_grad((torch.from_numpy(z).to(dev) * s).float())
+    def fun(zz):
+        f, gr = value_grad((torch.from_numpy(zz).to(dev) * s).float())
         return f, (gr * s).cpu().numpy()
 
-    res = so.minimize(fun, z0, jac=True, method="L-BFGS-B", bounds=[(0.0, None)] * z0.size,
-                      options=dict(maxiter=max_iter, maxcor=10, ftol=0.0, gtol=0.0, maxfun=2 * max_iter))
-    xstar = (torch.from_numpy(res.x).to(dev) * s).float()
-    phi, gstar = value_grad(xstar)
-    kkt = float(torch.minimum(xstar.double(), gstar).norm() / value_grad(x0)[1].norm())
-    return xstar, {"method": "preconditioned L-BFGS-B", "iterations": int(res.nit), "evaluations": int(res.nfev),
-                   "kkt_residual": kkt, "objective": phi}
+    def kkt_of(xx):
+        phi, gg = value_grad(xx)
+        return float(torch.minimum(xx.double(), gg).norm()) / g0n, phi
+
+    runs, used, kkt = [], 0, None
+    while used < max_iter:
+        res = so.minimize(fun, z, jac=True, method="L-BFGS-B", bounds=[(0.0, None)] * z.size,
+                          options=dict(maxiter=max_iter - used, maxcor=10, ftol=0.0, gtol=0.0,
+                                       maxfun=2 * (max_iter - used)))
+        used += int(res.nit)
+        z = res.x
+        new_kkt, phi = kkt_of((torch.from_numpy(z).to(dev) * s).float())
+        runs.append({"iterations": int(res.nit), "kkt_residual": new_kkt, "objective": phi})
+        log(f"[bench] L-BFGS-B run {len(runs)}: {res.nit} iterations, KKT {new_kkt:.3e}, objective {phi:.10g}")
+        gain = kkt is None or new_kkt < 0.99 * kkt
+        kkt = new_kkt
+        if kkt <= target or res.nit == 0 or not gain:
+            break
+    xstar = (torch.from_numpy(z).to(dev) * s).float()
+    return xstar, {"method": "preconditioned L-BFGS-B with restarts", "iterations": used, "runs": len(runs),
+                   "kkt_residual": kkt, "kkt_target": target, "kkt_floor_fp32": floor,
+                   "objective": runs[-1]["objective"], "per_run": runs}
 
 
-def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_host, mask_np, level):
+def time_to_nrmse(args, cfg, geom, pm, cnt, epochs, y, r, a, beta, eps, delta, x0_host, mask_np, level):
     """Wall time to NRMSE < 1% of the converged MAP image x*, for each run in
-    `epochs` (name -> (geometry, epoch function, BB state needed); the first
-    is the headline).
+    `epochs` (name -> (geometry, epoch function, BB state needed, counts of
+    that geometry or None); the first is the headline).
 
     Each reconstruction is fresh and timed from the first device call after the
     data upload (sensitivity, one OSEM epoch, epochs of the estimator); the NRMSE
@@ -140,13 +186,12 @@ def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_hos
     import torch
 
     dev = y.device
-    n = cfg["n_subsets"]
     x0 = torch.from_numpy(x0_host.ravel()).to(dev)
     sens0 = torch.empty(geom.n_vox, device=dev)
     pm.pet_back(geom, -1, None, a, sens0)
     log(f"[bench] reference image (L-BFGS-B, at most {args.ref_iters} iterations) ...")
     t0 = time.perf_counter()
-    xstar, ref = map_reference(cfg, geom, pm, y, r, a, sens0, beta, eps, delta, x0, args.ref_iters)
+    xstar, ref = map_reference(cfg, geom, pm, cnt, sens0, beta, eps, delta, x0, args.ref_iters, args.kkt_target)
     del sens0
     log(f"[bench] reference done in {time.perf_counter() - t0:.1f} s: {ref}")
     mask = torch.from_numpy(mask_np.ravel()).to(dev)
@@ -157,7 +202,7 @@ def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_hos
         return float(torch.sqrt((dlt * dlt).sum() / nm)) / level
 
     out = {}
-    for name, (geom_run, epoch, bb) in epochs.items():
+    for name, (geom_run, epoch, bb, cnt_run) in epochs.items():
         n_run = geom_run.n_subsets
         x1 = torch.empty(geom.n_vox, device=dev)
         xmax = torch.zeros(1, device=dev)
@@ -170,7 +215,7 @@ def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_hos
         pm.pet_back(geom_run, -1, None, a, sens)
         pm.pet_osem_epoch(geom_run, x1, y, r, a, list(range(n_run)), xmax)
         st1 = pm.SvrgStateBuffers(geom_run, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0,
-                                  delta=delta, bb=bb)
+                                  delta=delta, bb=bb, counts=cnt_run)
         torch.cuda.synchronize()
         t_clock += time.perf_counter() - t0
         trace = [nrmse_of(x1)]
@@ -188,15 +233,13 @@ def time_to_nrmse(args, cfg, geom, pm, epochs, y, r, a, beta, eps, delta, x0_hos
                 break
         log(f"[bench] {name}: NRMSE after OSEM and each epoch: {['%.4f' % v for v in trace]}")
         out[name] = {"seconds": t_clock if reached else None, "epochs": reached, "threshold": 0.01,
-                     "epochs_per_s": (len(trace) - 1) / t_epochs,
-                     "subsets": n_run,
-                     "includes": f"sensitivity backprojection, 1 OSEM epoch, {name.upper()} epochs "
-                                 "(NRMSE evaluation excluded)",
-                     "nrmse_per_epoch": [round(v, 5) for v in trace]}
+                     "epochs_per_s": (len(trace) - 1) / t_epochs, "subsets": n_run,
+                     "path": "zero-count-aware" if cnt_run is not None else "dense",
+                     "min_nrmse": min(trace), "final_nrmse": trace[-1]}
         del st1, x1, sens
-    first = next(iter(out))
-    out[first].update({"reference": ref, "region_voxels": int(nm), "level": level})
-    return out
+    return out, {"reference": ref, "region_voxels": int(nm), "level": level,
+                 "includes": "sensitivity backprojection, 1 OSEM epoch, the estimator's epochs "
+                             "(NRMSE evaluation excluded)"}
 
 
 def differentiable_leg(pm):
@@ -363,12 +406,14 @@ def main():
     ap.add_argument("--config", default="c2_tof")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nrmse", action="store_true", help="skip the time-to-NRMSE measurement")
-    ap.add_argument("--ref-iters", type=int, default=500,
-                    help="L-BFGS-B iterations (at most) of the converged reference image for the NRMSE")
+    ap.add_argument("--ref-iters", type=int, default=2000,
+                    help="L-BFGS-B iterations (at most, over all restarts) of the reference image for the NRMSE")
+    ap.add_argument("--kkt-target", type=float, default=1e-6)
     ap.add_argument("--nrmse-max-epochs", type=int, default=300)
     ap.add_argument("--no-estimators", action="store_true",
                     help="time to NRMSE for SVRG only (not SAGA, SGD, ALG1, ALG2, ALG3)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable (unrolled) leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg's summary")
     ap.add_argument("--batched", action="store_true",
                     help="measure only the batched workload (24 reconstructions; prints its own JSON line)")
     ap.add_argument("--batch-rounds", type=int, default=3)
@@ -408,18 +453,23 @@ def main():
     del d
     geom = pm.Geometry(cfg)
     torch.cuda.synchronize()
-    log(f"[bench] uploaded; geometry ready ({geom.n_bins} bins, {geom.n_vox} voxels)")
+    t0 = time.perf_counter()
+    cnt = pm.Counts(geom, y, r, a)
+    torch.cuda.synchronize()
+    t_counts = time.perf_counter() - t0
+    n_items = cnt.info(-1)[0]
+    log(f"[bench] uploaded; geometry ready ({geom.n_bins} bins, {geom.n_vox} voxels); {n_items} bins with "
+        f"counts compacted in {t_counts:.2f} s")
 
     sens = torch.empty(geom.n_vox, device=dev)
     pm.pet_back(geom, -1, None, a, sens)
-    x = torch.ones(geom.n_vox, device=dev)
+    x_osem = torch.ones(geom.n_vox, device=dev)
     xmax = torch.zeros(1, device=dev)
-    pm.pet_osem_epoch(geom, x, y, r, a, list(range(n)), xmax)
+    pm.pet_osem_epoch(geom, x_osem, y, r, a, list(range(n)), xmax)
     mx = float(xmax.cpu())
     beta = configs.beta_value(cfg)
     eps = delta = 1e-3 * mx
-    x0_host = x.cpu().numpy()
-    st = pm.SvrgStateBuffers(geom, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0, delta=delta)
+    x0_host = x_osem.cpu().numpy()
     total = args.warmup + args.steps
     orders = data.subset_orders(cfg, max(total, args.nrmse_max_epochs))
     upd_iters = {0, n, 2 * n}
@@ -439,76 +489,88 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log("[bench] OSEM done; warmup epochs ...")
-    for e in range(args.warmup):
-        epoch(e, st, x)
-    torch.cuda.synchronize()
-    pm.pet_profile_enable(geom, True)
-    for kern in (pm.PET_KERNEL_GRAD,):
-        pm.pet_profile_read(geom, kern)
-    log(f"[bench] timing {args.steps} epochs ...")
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for e in range(args.warmup, total):
-        epoch(e, st, x)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    grad_ms, grad_launches = pm.pet_profile_read(geom, pm.PET_KERNEL_GRAD)
-    pm.pet_profile_enable(geom, False)
-    log(f"[bench] {args.steps} epochs in {elapsed:.3f} s; fused-gradient kernel {grad_launches} launches, "
-        f"{grad_ms:.1f} ms total")
 
-    # algorithmic work of the launches in the timed region
+    def timed_epochs(counts, kern):
+        """W warm-up and K timed SVRG epochs from the OSEM image; returns the
+        elapsed time, the line kernel's total time and launches, the image."""
+        x = x_osem.clone()
+        st = pm.SvrgStateBuffers(geom, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0,
+                                 delta=delta, counts=counts)
+        for e in range(args.warmup):
+            epoch(e, st, x)
+        torch.cuda.synchronize()
+        pm.pet_profile_enable(geom, True)
+        pm.pet_profile_read(geom, kern)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for e in range(args.warmup, total):
+            epoch(e, st, x)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        kms, kl = pm.pet_profile_read(geom, kern)
+        pm.pet_profile_enable(geom, False)
+        return elapsed, kms, kl, x
+
+    log(f"[bench] timing {args.steps} SVRG epochs (zero-count-aware path) ...")
+    elapsed, grad_ms, grad_launches, x = timed_epochs(cnt, pm.PET_KERNEL_COUNTS)
+    log(f"[bench] {args.steps} epochs in {elapsed:.3f} s; counts line kernel {grad_launches} launches, "
+        f"{grad_ms:.1f} ms total")
+    log("[bench] timing the dense path on the same schedule ...")
+    elapsed_d, dense_ms, dense_launches, x_dense = timed_epochs(None, pm.PET_KERNEL_GRAD)
+    log(f"[bench] dense: {args.steps} epochs in {elapsed_d:.3f} s; fused line kernel {dense_launches} launches, "
+        f"{dense_ms:.1f} ms total")
+    paths_rel_diff = float((x.double() - x_dense.double()).norm() / x_dense.double().norm())
+    del x_dense
+
+    # algorithmic work of the line-kernel launches in the timed region
     launched = []
     for e in range(args.warmup, total):
         for j in range(n):
             k = e * n + j
             launched += list(range(n)) if k % (2 * n) == 0 else [int(orders[e][j])]
-    assert len(launched) == grad_launches, (len(launched), grad_launches)
-    counts = {}
-    cnt = torch.zeros(2, dtype=torch.float64, device=dev)
-    for i in range(n):
-        pm.pet_work_counts(geom, i, cnt)
-        counts[i] = tuple(float(v) for v in cnt.cpu())
-    tof = cfg["n_tof"] > 1
-    flops = 0.0
+    assert len(launched) == grad_launches == dense_launches, (len(launched), grad_launches, dense_launches)
+    # HBM bytes per unit (Section 8(d)'s dense data pass): per bin y (its storage
+    # type) + r (FP32), per LOR mult (FP32); plus the image in and the gradient out
     hbm = 0.0
+    items = 0
     for i in launched:
-        s, p = counts[i]
-        flops += FLOP_PER_SAMPLE * s + (FLOP_PER_PAIR_TOF * p if tof else FLOP_PER_SAMPLE_NONTOF * s)
         nb, nl, _ = geom.info(i)
         hbm += nb * (y.element_size() + 4) + nl * 4 + 4 * geom.n_vox * 2
+        items += cnt.info(i)[0]
+    compulsory = 16.0 * items + 4 * geom.n_vox * 2 * len(launched)
     import hashlib
-    src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_2506_04976_amd", "csrc", "proj.hip"), "rb").read()).hexdigest()[:16]
+    src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_2506_04976_amd", "csrc", "counts.hip"),
+                                   "rb").read()).hexdigest()[:16]
     traffic = None
     if cfg["name"] in MEASURED_TRAFFIC and MEASURED_TRAFFIC[cfg["name"]][1] == src_hash:
         traffic = MEASURED_TRAFFIC[cfg["name"]][0]
+    valu = None
+    if cfg["name"] in MEASURED_VALU and MEASURED_VALU[cfg["name"]][1] == src_hash:
+        valu = MEASURED_VALU[cfg["name"]][0]
     grad_s = grad_ms / 1e3
-    achieved = flops / grad_s / 1e12
     kernel_gbps = hbm / grad_s / 1e9
-    # whole-epoch algorithmic HBM traffic: sinogram data of every subset
-    # gradient plus the image-space passes (RDP stencil and update)
-    epoch_bytes = hbm / args.steps + n * 7 * 4 * geom.n_vox
 
+    w27 = pm.rdp_weights27(cfg["vx"], cfg["vy"], cfg["vz"])
     obj = torch.zeros(1, dtype=torch.float64, device=dev)
-    pm.pet_objective(geom, x, y, r, a, None, pm.rdp_weights27(cfg["vx"], cfg["vy"], cfg["vz"]), beta,
-                     cfg["gamma"], eps, obj)
+    pm.pet_objective_counts(geom, cnt, x, sens, None, w27, beta, cfg["gamma"], eps, obj)
     objective = float(obj.cpu())
+    pm.pet_objective(geom, x, y, r, a, None, w27, beta, cfg["gamma"], eps, obj)
+    objective_dense = float(obj.cpu())
 
     nrmse = None
-    estimators = None
     if not args.no_nrmse:
-        del st
-        algos = {"svrg": (geom, epoch, False)}
-        extra_geoms = []
+        algos = {"svrg": (geom, epoch, False, cnt)}
+        extra = []
         if not args.no_estimators:
-            algos.update(saga=(geom, make_epoch(pm.pet_saga_epoch), False),
-                         sgd=(geom, make_epoch(pm.pet_sgd_epoch), False))
+            algos.update(svrg_dense=(geom, epoch, False, None),
+                         saga=(geom, make_epoch(pm.pet_saga_epoch), False, None),
+                         sgd=(geom, make_epoch(pm.pet_sgd_epoch), False, None))
             # the submitted algorithms, each with its own subset count
             for alg, target in (("ALG1", 25.0), ("ALG2", 25.0), ("ALG3", 24.2)):
                 n_alg = schedules.subsets_for(cfg["n_views"], target)
                 g_alg = pm.Geometry(configs.get(cfg["name"], n_subsets=n_alg))
-                extra_geoms.append(g_alg)
+                c_alg = pm.Counts(g_alg, y, r, a)
+                extra.append((g_alg, c_alg))
                 plan = schedules.algorithm_plan(alg, n_alg, args.nrmse_max_epochs,
                                                 np.random.default_rng(data.seeds(cfg)[1]))
 
@@ -516,13 +578,13 @@ def main():
                     pe = plan[e]
                     pm.pet_svrg_epoch(g_alg, st, x, pe["subset_seq"], pe["tau"], pe["update_pc"],
                                       bb_update=pe["bb_update"])
-                algos[alg.lower()] = (g_alg, alg_epoch, alg != "ALG1")
-        nrmse_all = time_to_nrmse(args, cfg, geom, pm, algos, y, r, a, beta, eps, delta, x0_host,
+                algos[alg.lower()] = (g_alg, alg_epoch, alg != "ALG1", c_alg)
+        runs, ref = time_to_nrmse(args, cfg, geom, pm, cnt, algos, y, r, a, beta, eps, delta, x0_host,
                                   nrmse_mask, nrmse_level)
-        for g_alg in extra_geoms:
+        for g_alg, c_alg in extra:
+            c_alg.close()
             g_alg.close()
-        nrmse = nrmse_all.pop("svrg")
-        estimators = nrmse_all or None
+        nrmse = {"threshold": 0.01, "reference": ref, "runs": runs}
 
     diff = None
     if not args.no_diff:
@@ -531,10 +593,21 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a one-view sample ...")
-        del y, r, a
-        torch.cuda.empty_cache()
+        log("[bench] timing the CPU oracle on a sample of one view ...")
         cpu = cpu_baseline(cfg, keep, x0_host, beta, eps)
+
+    cnt.close()
+    geom.close()
+    del y, r, a, sens, x, x_osem
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batched:
+        log("[bench] batched leg (24 reconstructions) ...")
+        bl = batched_leg(args)
+        batched = {k: bl[k] for k in ("value", "unit", "plain_value", "speedup_vs_plain",
+                                      "max_member_rel_diff_vs_plain", "autotuned", "ms_per_step")}
+        batched["rounds"] = bl["steps"]
+        batched["workload"] = bl["config"]["workload"]
 
     value = args.steps / elapsed
     out = {
@@ -552,19 +625,27 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{cfg['name']}: {cfg['nx']}x{cfg['ny']}x{cfg['nz']} image, "
                                f"{cfg['n_views']} views x {cfg['n_rad']} radial x {geom.n_lors // (cfg['n_views'] * cfg['n_rad'])} planes"
-                               f" x {cfg['n_tof']} TOF, {n} subsets, preconditioned SVRG",
-                   "bins": geom.n_bins, "voxels": geom.n_vox, "counts": cfg.get("counts"),
-                   "y_dtype": str(keep["y"].dtype), "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "k_line<TOF, M_GRAD> (fused forward projection, ratio, backprojection)",
+                               f" x {cfg['n_tof']} TOF, {n} subsets, preconditioned SVRG (zero-count-aware data term)",
+                   "bins": geom.n_bins, "bins_with_counts": n_items, "voxels": geom.n_vox,
+                   "counts": cfg.get("counts"), "y_dtype": str(keep["y"].dtype), "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": kernel_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": kernel_gbps / PEAK_HBM_GBPS, "traffic": traffic,
+                     "kernel": "k_line_counts<TOF, M_GRAD> (zero-count-aware subset gradient)",
                      "avg_launch_ms": grad_ms / grad_launches, "launches": grad_launches,
-                     "algorithmic_hbm_gbps": kernel_gbps, "hbm_frac": kernel_gbps / PEAK_HBM_GBPS},
-        "hbm_gbps_epoch": epoch_bytes * value / 1e9,
+                     "algorithmic_bytes_per_launch": hbm / grad_launches,
+                     "compulsory_bytes_per_launch": compulsory / grad_launches,
+                     "valu_issue": valu},
+        "dense_path": {"value": args.steps / elapsed_d, "unit": "epochs/s",
+                       "kernel": "k_line_tof<M_GRAD> (fused dense subset gradient)",
+                       "avg_launch_ms": dense_ms / dense_launches,
+                       "hbm_frac": hbm / (dense_ms / 1e3) / 1e9 / PEAK_HBM_GBPS,
+                       "image_rel_diff_vs_counts_path": paths_rel_diff},
+        "counts_setup_s": t_counts,
         "objective_final": objective,
+        "objective_final_dense_formula": objective_dense,
         "time_to_nrmse": nrmse,
-        "time_to_nrmse_other_algorithms": estimators,
         "differentiable": diff,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

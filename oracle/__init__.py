@@ -30,14 +30,35 @@ def build(force=False):
     return so
 
 
+def build_native(dest_dir):
+    """Compile the same projector source with -O3 -march=native for the host
+    it runs on, into dest_dir (for timing the oracle as a CPU baseline; the
+    parity tests use build())."""
+    so = os.path.join(dest_dir, "_joseph_native.so")
+    src = os.path.join(_HERE, "joseph.c")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-o", so, src, "-lm"])
+    return so
+
+
+def use_library(path):
+    """Route the oracle's projector calls to another build of joseph.c."""
+    global _LIB
+    _LIB = _load(path)
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    L.orc_joseph.argtypes = ([ctypes.c_int, ctypes.c_long, P, P] + [ctypes.c_int] * 3 +
+                             [ctypes.c_double] * 3 + [ctypes.c_int] + [ctypes.c_double] * 3 +
+                             [P, P, ctypes.c_int])
+    L.orc_joseph.restype = None
+    return L
+
+
 def lib():
     global _LIB
     if _LIB is None:
-        L = ctypes.CDLL(build())
-        P = ctypes.c_void_p
-        L.orc_joseph.argtypes = ([ctypes.c_int, ctypes.c_long, P, P] + [ctypes.c_int] * 3 +
-                                 [ctypes.c_double] * 3 + [ctypes.c_int] + [ctypes.c_double] * 3 +
-                                 [P, P, ctypes.c_int])
-        L.orc_joseph.restype = None
-        _LIB = L
+        _LIB = _load(build())
     return _LIB
+

@@ -42,6 +42,8 @@ pet_status validate(const pet_geom_desc &d) {
         return fail(PET_E_ARG, "pet_geom_create: unknown scanner kind");
     if (d.nx < 1 || d.ny < 1 || d.nz < 1 || !(d.vx > 0) || !(d.vy > 0) || !(d.vz > 0))
         return fail(PET_E_ARG, "pet_geom_create: image sizes and voxel sizes must be positive");
+    if (d.nz > 400) return fail(PET_E_ARG, "pet_geom_create: at most 400 axial voxels");
+    if ((int64_t)d.nx * d.ny * d.nz >= ((int64_t)1 << 31)) return fail(PET_E_ARG, "pet_geom_create: too many voxels");
     if (d.nx > 32000 || d.ny > 32000 || d.nz > 32000)
         return fail(PET_E_ARG, "pet_geom_create: image dimension too large");
     if (d.n_views < 1 || d.n_rad < 1) return fail(PET_E_ARG, "pet_geom_create: n_views and n_rad must be >= 1");

@@ -11,39 +11,60 @@ namespace {
 
 // x [iz][iy][ix] -> T0 [ix][iy + PADA][iz + PADZ] and T1 [iy][ix + PADA][iz + PADZ]
 // (interiors only; the zero borders are set once at creation).
-__global__ void k_to_sheets(const float *__restrict__ x, float *__restrict__ T0, float *__restrict__ T1,
-                            int nx, int ny, int nz, int rz) {
-    int64_t n = (int64_t)nx * ny * nz;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        int ix = v % nx;
-        int iy = (v / nx) % ny;
-        int iz = v / ((int64_t)nx * ny);
-        float val = x[v];
-        T0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + iz + PADZ] = val;
-        T1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + iz + PADZ] = val;
+// Through LDS tiles: workgroup (32 consecutive x, one y) reads the
+// image rows x[z][y][x0 .. x0 + 31] for every z (coalesced along x) and writes,
+// per x, the z-contiguous rows of both sheets (coalesced along z).
+constexpr int TT = 32;
+__global__ void __launch_bounds__(256) k_to_sheets_t(const float *__restrict__ x, float *__restrict__ T0,
+                                                     float *__restrict__ T1, int nx, int ny, int nz, int rz) {
+    extern __shared__ float tile[];  // [nz][TT + 1]
+    const int x0 = blockIdx.x * TT, iy = blockIdx.y;
+    const int w = min(TT, nx - x0);
+    for (int e = threadIdx.x; e < nz * TT; e += blockDim.x) {
+        const int z = e / TT, xx = e - z * TT;
+        tile[z * (TT + 1) + xx] = xx < w ? x[((size_t)z * ny + iy) * nx + x0 + xx] : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
+        const int xx = e / nz, z = e - xx * nz;
+        const float val = tile[z * (TT + 1) + xx];
+        const int ix = x0 + xx;
+        T0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ] = val;
+        T1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] = val;
+    }
+}
+
+// Sum of the two gradient sheets at the voxels of one workgroup's tile
+// (32 consecutive x, one y, every z) into LDS, read z-contiguous.
+__device__ __forceinline__ void sheets_to_tile(const float *__restrict__ G0, const float *__restrict__ G1,
+                                               float *tile, int x0, int w, int iy, int nx, int ny, int nz, int rz) {
+    for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
+        const int xx = e / nz, z = e - xx * nz;
+        const int ix = x0 + xx;
+        tile[z * (TT + 1) + xx] = G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] +
+                                  G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ];
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_from_sheets_t(const float *__restrict__ G0, const float *__restrict__ G1,
+                                                       float *__restrict__ out, int nx, int ny, int nz, int rz,
+                                                       int accumulate) {
+    extern __shared__ float tile[];
+    const int x0 = blockIdx.x * TT, iy = blockIdx.y;
+    const int w = min(TT, nx - x0);
+    sheets_to_tile(G0, G1, tile, x0, w, iy, nx, ny, nz, rz);
+    for (int e = threadIdx.x; e < nz * TT; e += blockDim.x) {
+        const int z = e / TT, xx = e - z * TT;
+        if (xx >= w) continue;
+        const size_t v = ((size_t)z * ny + iy) * nx + x0 + xx;
+        const float sv = tile[z * (TT + 1) + xx];
+        out[v] = accumulate ? out[v] + sv : sv;
     }
 }
 
 __global__ void k_fill(float *__restrict__ p, int64_t n, float val) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
-}
-
-__device__ __forceinline__ float sheet_value(const float *G0, const float *G1, int ix, int iy, int iz, int nx,
-                                             int ny, int rz) {
-    return G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + iz + PADZ] +
-           G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + iz + PADZ];
-}
-
-__global__ void k_from_sheets(const float *__restrict__ G0, const float *__restrict__ G1, float *__restrict__ out,
-                              int nx, int ny, int nz, int rz, int accumulate) {
-    int64_t n = (int64_t)nx * ny * nz;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        int ix = v % nx;
-        int iy = (v / nx) % ny;
-        int iz = v / ((int64_t)nx * ny);
-        float s = sheet_value(G0, G1, ix, iy, iz, nx, ny, rz);
-        out[v] = accumulate ? out[v] + s : s;
-    }
 }
 
 struct W27 {
@@ -95,15 +116,19 @@ struct RdpArgs {
 //   dS/dx_i += w k_i k_j d (2 phi - (d + gamma |d|)) / phi^2
 //   d2S/dx_i^2 += 2 w k_i k_j (s - d + eps)^2 / phi^3
 //   S += 1/2 w k_i k_j d^2 / phi   (each ordered pair once, halved).
+// (32-bit voxel indices: images hold fewer than 2^31 voxels; 1 / phi is the
+// hardware reciprocal, within 1 ulp)
 template <int F>
 __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
-    const int64_t n = (int64_t)a.nx * a.ny * a.nz;
-    const int64_t v = blockIdx.x * (int64_t)IMG_BLOCK + threadIdx.x;
+    const int nxy = a.nx * a.ny;
+    const int n = nxy * a.nz;
+    const int v = blockIdx.x * IMG_BLOCK + threadIdx.x;
     double val = 0.0, pq = 0.0, qdq = 0.0;
     if (v < n) {
-        const int ix = v % a.nx;
-        const int iy = (v / a.nx) % a.ny;
-        const int iz = v / ((int64_t)a.nx * a.ny);
+        const int iz = v / nxy;
+        const int rem = v - iz * nxy;
+        const int iy = rem / a.nx;
+        const int ix = rem - iy * a.nx;
         const float xi = a.x[v];
         const float ki = a.kappa ? a.kappa[v] : 1.f;
         float g = 0.f, h = 0.f, sv = 0.f;
@@ -120,13 +145,13 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
                     if (dx == 0 && dy == 0 && dz == 0) continue;
                     const int jx = ix + dx;
                     if (jx < 0 || jx >= a.nx) continue;
-                    const int64_t u = ((int64_t)jz * a.ny + jy) * a.nx + jx;
+                    const int u = v + dz * nxy + dy * a.nx + dx;
                     const float xj = a.x[u];
                     const float wk = a.w.w[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] * ki * (a.kappa ? a.kappa[u] : 1.f);
                     const float d = xi - xj;
                     const float ad = fabsf(d);
                     const float phi = xi + xj + a.gamma * ad + a.eps;
-                    const float rphi = 1.f / phi;
+                    const float rphi = __builtin_amdgcn_rcpf(phi);
                     g = fmaf(wk * d * (2.f * phi - (d + a.gamma * ad)), rphi * rphi, g);
                     if (F & (R_HESS_OUT | R_PRECOND)) {
                         const float c = 2.f * xj + a.eps;  // s - d + eps
@@ -230,15 +255,19 @@ __global__ void k_precond(const float *__restrict__ x, const float *__restrict__
 }
 
 // ghat_i = g (data gradient of subset i at the snapshot); ghat (+)= g in FP64.
-__global__ void k_snapshot_accum(const float *__restrict__ G0, const float *__restrict__ G1, float *__restrict__ ghat_i,
-                                 double *__restrict__ ghat, float *__restrict__ gcopy, int nx, int ny, int nz, int rz,
-                                 int first, const float *__restrict__ base) {
-    int64_t n = (int64_t)nx * ny * nz;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        int ix = v % nx;
-        int iy = (v / nx) % ny;
-        int iz = v / ((int64_t)nx * ny);
-        float s = sheet_value(G0, G1, ix, iy, iz, nx, ny, rz);
+__global__ void __launch_bounds__(256) k_snapshot_accum(const float *__restrict__ G0, const float *__restrict__ G1,
+                                                        float *__restrict__ ghat_i, double *__restrict__ ghat,
+                                                        float *__restrict__ gcopy, int nx, int ny, int nz, int rz,
+                                                        int first, const float *__restrict__ base) {
+    extern __shared__ float tile[];
+    const int x0 = blockIdx.x * TT, iy = blockIdx.y;
+    const int w = min(TT, nx - x0);
+    sheets_to_tile(G0, G1, tile, x0, w, iy, nx, ny, nz, rz);
+    for (int e = threadIdx.x; e < nz * TT; e += blockDim.x) {
+        const int z = e / TT, xx = e - z * TT;
+        if (xx >= w) continue;
+        const size_t v = ((size_t)z * ny + iy) * nx + x0 + xx;
+        const float s = tile[z * (TT + 1) + xx];
         ghat_i[v] = s;
         if (gcopy) gcopy[v] = s;
         ghat[v] = (first ? (base ? (double)base[v] : 0.0) : ghat[v]) + (double)s;
@@ -437,6 +466,10 @@ __global__ void k_copy(float *__restrict__ d, const float *__restrict__ s, int64
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) d[i] = s[i];
 }
 
+// transposes through LDS tiles: workgroups (x tile, y), LDS nz x (TT + 1) floats
+inline dim3 tile_grid(const pet_geom_s *g) { return dim3((unsigned)((g->d.nx + TT - 1) / TT), (unsigned)g->d.ny); }
+inline size_t tile_lds(const pet_geom_s *g) { return sizeof(float) * (size_t)g->d.nz * (TT + 1); }
+
 inline dim3 grid_for(int64_t n) {
     int64_t b = (n + IMG_BLOCK - 1) / IMG_BLOCK;
     return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 65536));
@@ -484,7 +517,7 @@ hipError_t launch_to_sheets_b(const pet_geom_s *g, const SheetBufs &w, const flo
         if (e != hipSuccess) return e;
         src = gx;
     }
-    hipLaunchKernelGGL(k_to_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, src, w.T0, w.T1, g->d.nx, g->d.ny,
+    hipLaunchKernelGGL(k_to_sheets_t, tile_grid(g), dim3(256), tile_lds(g), s, src, w.T0, w.T1, g->d.nx, g->d.ny,
                        g->d.nz, g->d.nz + 2 * PADZ);
     return hipGetLastError();
 }
@@ -512,12 +545,12 @@ hipError_t launch_zero_sheets(const pet_geom_s *g, hipStream_t s) { return launc
 // Gradient sheets -> image (then G^T = G with a resolution model).
 hipError_t launch_from_sheets_b(const pet_geom_s *g, const SheetBufs &w, float *out, int accumulate, hipStream_t s) {
     if (g->psf_passes) {
-        hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, w.G0, w.G1, w.psf_b, g->d.nx,
+        hipLaunchKernelGGL(k_from_sheets_t, tile_grid(g), dim3(256), tile_lds(g), s, w.G0, w.G1, w.psf_b, g->d.nx,
                            g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, 0);
         const hipError_t e = hipGetLastError();
         return e != hipSuccess ? e : launch_psf_b(g, w, w.psf_b, out, accumulate, s);
     }
-    hipLaunchKernelGGL(k_from_sheets, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, w.G0, w.G1, out, g->d.nx, g->d.ny,
+    hipLaunchKernelGGL(k_from_sheets_t, tile_grid(g), dim3(256), tile_lds(g), s, w.G0, w.G1, out, g->d.nx, g->d.ny,
                        g->d.nz, g->d.nz + 2 * PADZ, accumulate);
     return hipGetLastError();
 }
@@ -733,7 +766,7 @@ hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *gha
                            first, base);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_snapshot_accum, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, g->G0, g->G1, ghat_i, ghat, gcopy,
+    hipLaunchKernelGGL(k_snapshot_accum, tile_grid(g), dim3(256), tile_lds(g), s, g->G0, g->G1, ghat_i, ghat, gcopy,
                        g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first, base);
     return hipGetLastError();
 }
