@@ -7,6 +7,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <string>
+#include <utility>
 
 #include "pet_internal.h"
 
@@ -433,13 +434,16 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
     hipError_t e = hipSuccess;
     const int64_t nv = g->n_vox;
     const double *tau_bb = st->bb ? st->bb + 2 : nullptr;
+    // the iterate alternates between x and the handle's xtmp (the step reads
+    // neighbours, so it cannot update in place); one copy at the end if needed
+    float *cur = x, *nxt = g->xtmp;
     for (int j = 0; j < n && e == hipSuccess; ++j) {
         const int64_t k = st->k + j;
         const bool snap = (k % om) == 0;
         const int i = subset_seq[j];
         const float w = (opt && opt->weight) ? opt->weight[j] : (float)n;
         if (st->bb && k == 0) e = launch_bb_init(st->bb, s);
-        if (e == hipSuccess) e = launch_to_sheets(g, x, s);
+        if (e == hipSuccess) e = launch_to_sheets(g, cur, s);
         if (snap) {
             // with snap_objective, the snapshot's own passes also sum the data
             // term at xhat (no extra projection)
@@ -454,37 +458,38 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             }
             if (e == hipSuccess && so && st->counts) {
                 // D = <sens, x> + sum r - sum y + sum y log(y / ybar)
-                e = launch_dot(st->sens, x, nv, g->partial, so, 1, s);
+                e = launch_dot(st->sens, cur, nv, g->partial, so, 1, s);
                 const pet_counts_s *c = st->counts;
                 if (e == hipSuccess) e = launch_add_scalar(so, c->sum_add[c->n_subsets] - c->sum_y[c->n_subsets], s);
             }
             if (e == hipSuccess && so)
-                e = launch_rdp(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, nullptr, nullptr, g->partial, s);
+                e = launch_rdp(g, cur, st->kappa, st->w, st->beta, st->gamma, st->eps, nullptr, nullptr, g->partial, s);
             if (e == hipSuccess && so) e = launch_reduce_sum(g->partial, rdp_blocks(g), so, 1, s);
             // BB bookkeeping: 0 none, 1 keep the full gradient, 2 also recompute the step bound
             const int bb_mode = !st->bb ? 0 : (opt && opt->bb_update && opt->bb_update[j] && k > 0) ? 2 : 1;
             float *grad_out = st->gnorm ? g->num : nullptr;
             if (e == hipSuccess)
-                e = launch_svrg_step_ex(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
+                e = launch_svrg_step_ex(g, cur, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
                                         st->alpha, st->delta, st->D, 1, g->g, st->ghat_i + (size_t)i * nv, st->ghat, w,
-                                        tau[j], tau_bb, bb_mode, st->x_snap, st->g_prev, grad_out, g->xtmp, s);
+                                        tau[j], tau_bb, bb_mode, st->x_snap, st->g_prev, grad_out, nxt, s);
             if (e == hipSuccess && bb_mode == 2) {
                 e = launch_bb_finish(g, st->bb, s);
-                if (e == hipSuccess) e = launch_step_stored(g, x, st->D, st->g_prev, tau[j], tau_bb, g->xtmp, s);
+                if (e == hipSuccess) e = launch_step_stored(g, cur, st->D, st->g_prev, tau[j], tau_bb, nxt, s);
             }
             if (e == hipSuccess && st->gnorm) e = launch_subset_norms(g, st->ghat_i, g->num, st->gnorm, s);
-            if (e == hipSuccess) e = launch_copy(st->x_snap, x, nv, s);
+            if (e == hipSuccess) e = launch_copy(st->x_snap, cur, nv, s);
         } else {
             e = st->counts ? counts_grad_sheets(g, st->counts, i, nullptr, s)
                            : subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
             if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
             if (e == hipSuccess)
-                e = launch_svrg_step_ex(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
+                e = launch_svrg_step_ex(g, cur, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
                                         st->alpha, st->delta, st->D, 0, g->g, st->ghat_i + (size_t)i * nv, st->ghat, w,
-                                        tau[j], tau_bb, 0, nullptr, nullptr, nullptr, g->xtmp, s);
+                                        tau[j], tau_bb, 0, nullptr, nullptr, nullptr, nxt, s);
         }
-        if (e == hipSuccess) e = launch_copy(x, g->xtmp, nv, s);
+        std::swap(cur, nxt);
     }
+    if (e == hipSuccess && cur != x) e = launch_copy(x, cur, nv, s);
     if (e != hipSuccess) return hip_check(e, name);
     st->k += n;
     if (objective_out)

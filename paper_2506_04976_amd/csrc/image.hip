@@ -63,6 +63,17 @@ __global__ void __launch_bounds__(256) k_from_sheets_t(const float *__restrict__
     }
 }
 
+// Both gradient sheets to zero in one launch.
+__global__ void k_zero2(float *__restrict__ a, int64_t na, float *__restrict__ b, int64_t nb) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+        if (i < na)
+            a[i] = 0.f;
+        else
+            b[i - na] = 0.f;
+    }
+}
+
 __global__ void k_fill(float *__restrict__ p, int64_t n, float val) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = val;
 }
@@ -535,8 +546,8 @@ hipError_t launch_clear_image_sheets(const pet_geom_s *g, const SheetBufs &w, hi
 }
 
 hipError_t launch_zero_sheets_b(const pet_geom_s *g, const SheetBufs &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t0_elems), dim3(IMG_BLOCK), 0, s, w.G0, (int64_t)g->t0_elems, 0.f);
-    hipLaunchKernelGGL(k_fill, grid_for((int64_t)g->t1_elems), dim3(IMG_BLOCK), 0, s, w.G1, (int64_t)g->t1_elems, 0.f);
+    hipLaunchKernelGGL(k_zero2, grid_for((int64_t)(g->t0_elems + g->t1_elems)), dim3(IMG_BLOCK), 0, s, w.G0,
+                       (int64_t)g->t0_elems, w.G1, (int64_t)g->t1_elems);
     return hipGetLastError();
 }
 
