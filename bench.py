@@ -106,7 +106,7 @@ def cpu_baseline(cfg, d, x0, beta, eps, view=0):
                       f"{lors} LORs and {n} RDP gradients per epoch (extrapolated)"}
 
 
-def map_reference(cfg, geom, pm, cnt, sens, beta, eps, delta, x0, max_iter, target):
+def map_reference(cfg, geom, pm, cnt, sens, beta, eps, delta, x0, max_iter, target, polish_iters=1500):
     """Converged MAP image x* by preconditioned L-BFGS-B (as the paper's own
     reference reconstructions): variables z with x = s z, s = sqrt(D) for the
     harmonic preconditioner D at the initial image, bounds z >= 0.  Each
@@ -115,9 +115,11 @@ def map_reference(cfg, geom, pm, cnt, sens, beta, eps, delta, x0, max_iter, targ
     L-BFGS-B stops when its line search cannot make progress; it is restarted
     from its last point (fresh curvature pairs) until the KKT residual
     ||min(x, grad Phi)|| / ||grad Phi(x0)|| reaches `target`, max_iter
-    iterations are spent, or a restart gains less than 1%.  The residual's
-    floor from FP32 arithmetic is measured as the spread of two gradient
-    evaluations at the same point (different atomic summation orders)."""
+    iterations are spent, or a restart gains less than 1%; projected
+    Barzilai-Borwein steps then polish the image toward the target.  The
+    residual's floor from FP32 arithmetic is measured as the spread of two
+    gradient evaluations at the same point (different atomic summation
+    orders)."""
     import numpy as np
     import scipy.optimize as so
     import torch
@@ -167,10 +169,49 @@ def map_reference(cfg, geom, pm, cnt, sens, beta, eps, delta, x0, max_iter, targ
         kkt = new_kkt
         if kkt <= target or res.nit == 0 or not gain:
             break
-    xstar = (torch.from_numpy(z).to(dev) * s).float()
-    return xstar, {"method": "preconditioned L-BFGS-B with restarts", "iterations": used, "runs": len(runs),
-                   "kkt_residual": kkt, "kkt_target": target, "kkt_floor_fp32": floor,
-                   "objective": runs[-1]["objective"], "per_run": runs}
+    lbfgs_kkt = kkt
+    # Polishing with projected Barzilai-Borwein steps in z, alternating the
+    # long and short BB lengths: gradients only, since the line search above
+    # stops once objective differences fall below the objective's FP32
+    # rounding.  The best iterate (lowest KKT residual) is kept; a residual ten
+    # times the best restarts from the best with half the step.
+    zt = torch.from_numpy(z).to(dev)
+    polish = 0
+    if kkt > target and polish_iters > 0:
+        def grad_z(zz):
+            xx = (zz * s).float()
+            phi_, gr_ = value_grad(xx)
+            return phi_, gr_ * s, float(torch.minimum(xx.double(), gr_).norm()) / g0n
+        _, gz, kz = grad_z(zt)
+        best = (kz, zt.clone())
+        alpha = 1.0
+        for it in range(polish_iters):
+            zn = torch.clamp(zt - alpha * gz, min=0.0)
+            _, gn, kn = grad_z(zn)
+            dz, dg = zn - zt, gn - gz
+            sy = float(torch.dot(dz, dg))
+            if sy > 0:
+                alpha = float(torch.dot(dz, dz)) / sy if it % 2 == 0 else sy / float(torch.dot(dg, dg))
+            alpha = min(max(alpha, 1e-6), 1e6)
+            zt, gz = zn, gn
+            polish = it + 1
+            if kn < best[0]:
+                best = (kn, zt.clone())
+            elif kn > 10 * best[0]:
+                zt = best[1].clone()
+                _, gz, _ = grad_z(zt)
+                alpha *= 0.5
+            if best[0] <= target:
+                break
+        zt = best[1]
+        kkt, phi = kkt_of((zt * s).float())
+        log(f"[bench] BB polishing: {polish} iterations, KKT {kkt:.3e}, objective {phi:.10g}")
+        runs.append({"iterations": polish, "kkt_residual": kkt, "objective": phi, "method": "projected BB"})
+    xstar = (zt * s).float()
+    return xstar, {"method": "preconditioned L-BFGS-B with restarts, then projected BB steps",
+                   "iterations": used, "polish_iterations": polish, "runs": len(runs),
+                   "kkt_residual": kkt, "kkt_after_lbfgsb": lbfgs_kkt, "kkt_target": target,
+                   "kkt_floor_fp32": floor, "objective": runs[-1]["objective"], "per_run": runs}
 
 
 def time_to_nrmse(args, cfg, geom, pm, cnt, epochs, y, r, a, beta, eps, delta, x0_host, mask_np, level):
