@@ -176,11 +176,12 @@ pet_status pet_subset_grad_noalloc(pet_geom g, int subset, const float *x, const
  *     D_i(x)      = <sens_i, x> + sum_i add - sum_i y + sum_{i, y > 0} y log(y / ybar(x)),
  * where only bins with y > 0 enter the terms that depend on ybar.  A pet_counts
  * object holds those bins of one data set (y, add, mult) on one geometry,
- * compacted in sinogram order (16 bytes per bin: index within its transaxial
- * line, y, add, mult), with per-line offsets and, per subset, its lines with
- * counts ordered by decreasing count.  The kernels that use it take one
- * workgroup per such line and one compacted bin per thread, walking only the
- * samples inside the bin's TOF window.  The TOF weight of a sample at signed
+ * compacted per transaxial line, TOF bin major within a line (16 bytes per
+ * bin: index within its transaxial line, y, add, mult), with per-line offsets
+ * and, per subset, its lines with counts ordered by decreasing count.  The
+ * kernels that use it take one workgroup per such line and one to sixteen
+ * lanes per compacted bin, walking only the samples inside the bin's TOF
+ * window.  The TOF weight of a sample at signed
  * distance t from the LOR centre in bin b is the geometry's truncated,
  * bin-integrated Gaussian, a function of d = t - t_b alone; it is tabulated
  * from FP64 at 4097 nodes over its support |d| <= bin/2 + nsig sigma and

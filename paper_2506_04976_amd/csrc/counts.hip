@@ -84,7 +84,9 @@ __global__ void __launch_bounds__(256) k_counts_per_line(const void *__restrict_
     }
 }
 
-// Compaction of one line's bins with y > 0, in sinogram order.
+// Compaction of one line's bins with y > 0, TOF bin major (then plane): the
+// records that share a wave then have TOF windows at the same place along the
+// line, so their sample loops run for about the same number of rows.
 __global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y, int dt, const float *__restrict__ add,
                                                      const float *__restrict__ mult, int64_t bins_per_line, int n_tof,
                                                      int n_planes, const int64_t *__restrict__ line_off,
@@ -93,9 +95,11 @@ __global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y,
     const int64_t base = (int64_t)blockIdx.x * bins_per_line;
     int64_t out = line_off[blockIdx.x];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int64_t k0 = 0; k0 < bins_per_line; k0 += blockDim.x) {
-        const int64_t k = k0 + threadIdx.x;
-        const float v = k < bins_per_line ? count_y(y, dt, base + k) : 0.f;
+    for (int64_t q0 = 0; q0 < bins_per_line; q0 += blockDim.x) {
+        const int64_t q = q0 + threadIdx.x;  // (TOF bin, plane) rank
+        const int64_t bq = q / n_planes;
+        const int64_t k = (q - bq * n_planes) * n_tof + bq;  // sinogram index within the line
+        const float v = q < bins_per_line ? count_y(y, dt, base + k) : 0.f;
         const bool has = v > 0.f;
         const uint64_t m = __ballot(has);
         if (lane == 0) s_w[w] = __popcll(m);
@@ -120,13 +124,13 @@ __global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y,
     }
 }
 
-// TOF weight W(d) from the LDS table: linear interpolation between nodes;
-// the position is clamped to the table, whose end nodes are 0.
-__device__ __forceinline__ float tof_weight(const float2 *tab, float d, const CountArgs &c) {
-    const float pos = __builtin_amdgcn_fmed3f(fmaf(d, c.inv_dx, c.pos0), 0.f, c.pos_max);
-    const int k = (int)pos;
-    const float2 t = tab[k];
-    return fmaf(pos - (float)k, t.y, t.x);
+// TOF weight W(d) from the LDS table, at table position pos = d / dx + NW/2:
+// linear interpolation between nodes; the position is clamped to the table,
+// whose end nodes are 0.
+__device__ __forceinline__ float tof_weight_at(const float2 *tab, float pos, float pos_max) {
+    pos = __builtin_amdgcn_fmed3f(pos, 0.f, pos_max);
+    const float2 t = tab[(int)pos];
+    return fmaf(__builtin_amdgcn_fractf(pos), t.y, t.x);
 }
 
 // One workgroup per line with counts.  MODE M_GRAD: gradient sheets receive
@@ -145,8 +149,16 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     float *X = smem;
     double *Z = reinterpret_cast<double *>(smem + sheet);
     float2 *tab = reinterpret_cast<float2 *>(smem + (NEED_Z ? 3 : 1) * sheet);
-    if (TOF)
-        for (int k = threadIdx.x; k < c.nw; k += blockDim.x) tab[k] = c.wtab[k];
+    if (TOF) {
+        // (all of a thread's table loads in flight at once; the kernel runs
+        // with CNT_BLOCK threads)
+        static_assert(NW_TAB % CNT_BLOCK == 0, "the table load assumes CNT_BLOCK divides NW_TAB");
+        float2 w[NW_TAB / CNT_BLOCK];
+#pragma unroll
+        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) w[u] = c.wtab[threadIdx.x + u * CNT_BLOCK];
+#pragma unroll
+        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) tab[threadIdx.x + u * CNT_BLOCK] = w[u];
+    }
     if (nrow > 0) build_sheets<true, NEED_Z>(a, L, nrow, X, Z);
     __syncthreads();
 
@@ -175,42 +187,50 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
         const float len = sqrtf(L.lt2 + P.dz2);
         const float ell = L.vm_um * len;
         int is, ie;
-        z_clip(L, P, a.nz, is, ie);
+        z_clip<true>(L, P, a.nz, is, ie);  // (u is clamped below)
         if (!act) ie = is - 1;
         // d(i) = t(i) - t_b, t(i) = (lambda(i) - 1/2) |u| the signed distance
         // from the LOR centre; rows outside |d| <= D (one row of margin, where
         // the table gives 0) are skipped
-        float d0 = 0.f, dd = 0.f;
+        // table position of row i: pos(i) = (t(i) - t_b) / dx + NW/2, affine in i
+        float pA = 0.f, pB = 0.f;
         if (TOF) {
-            d0 = fmaf(L.lam0 - 0.5f, len, -a.tof.tb[b]);
-            dd = L.dlam * len;
-            const float ia = (-c.wD - d0) / dd, ib = (c.wD - d0) / dd;
-            // clamped to [is, ie] (an empty window gives is > ie) before the conversion
+            const float d0 = fmaf(L.lam0 - 0.5f, len, -a.tof.tb[b]);
+            const float dd = L.dlam * len;
+            const float rdd = __builtin_amdgcn_rcpf(dd);
+            const float ia = (-c.wD - d0) * rdd, ib = (c.wD - d0) * rdd;
+            // clamped to [is, ie] (an empty window gives is > ie) before the
+            // conversion; the one-row margin covers the reciprocal's rounding
             const float lo = fminf(fmaxf(floorf(fminf(ia, ib)) - 1.f, (float)is), (float)(ie + 1));
             const float hi = fmaxf(fminf(ceilf(fmaxf(ia, ib)) + 1.f, (float)ie), (float)(is - 1));
             is = (int)lo;
             ie = (int)hi;
+            pA = dd * c.inv_dx;
+            pB = fmaf(d0, c.inv_dx, c.pos0);
         }
         const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
+        // rows as floats (exact integers): no conversion per sample
+        const float fC = (float)C, fis = (float)(is + ch), fie = (float)ie;
         float s = 0.f;
         const float *xr = X + (is + ch - L.i_lo) * rz;
-        for (int i = is + ch; i <= ie; i += C, xr += C * rz) {
-            const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+        for (float fi = fis; fi <= fie; fi += fC, xr += C * rz) {
+            const float u = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), 0.f, umax);
             const int j = (int)u;
             const float x0 = xr[j], x1 = xr[j + 1];
             const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
-            s = TOF ? fmaf(tof_weight(tab, fmaf((float)i, dd, d0), c), v, s) : s + v;
+            s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, pA, pB), c.pos_max), v, s) : s + v;
         }
         for (int o = 1; o < C; o <<= 1) s += __shfl_xor(s, o, 64);
         if (!act) continue;
         const float ybar = fmaf(e.mult, s * ell, e.add);
-        if (ch == 0) kl += (double)e.y * log((double)e.y / (double)ybar);
+        // (the FP64 logarithm only when the sums are wanted)
+        if (a.partial && ch == 0) kl += (double)e.y * log((double)e.y / (double)ybar);
         if (NEED_Z) {
-            const float Q = -e.mult * (e.y / ybar) * ell;
+            const float Q = -e.mult * e.y * __builtin_amdgcn_rcpf(ybar) * ell;
             double *zr = Z + (is + ch - L.i_lo) * rz;
-            for (int i = is + ch; i <= ie; i += C, zr += C * rz) {
-                const float qw = TOF ? Q * tof_weight(tab, fmaf((float)i, dd, d0), c) : Q;
-                const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+            for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                const float qw = TOF ? Q * tof_weight_at(tab, fmaf(fi, pA, pB), c.pos_max) : Q;
+                const float u = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), 0.f, umax);
                 const int j = (int)u;
                 const float a1 = qw * __builtin_amdgcn_fractf(u);
                 atomicAdd(&zr[j], (double)(qw - a1));

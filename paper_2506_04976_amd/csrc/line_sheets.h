@@ -33,25 +33,46 @@ __device__ __forceinline__ void z_clip(const LineP &L, const PlaneP &P, int nz, 
 // Block prologue: image sheet X (transaxial interpolation of the transposed
 // image) and / or zeroed gradient sheet Z.  Z accumulates in FP64: LDS FP64
 // atomic adds run at full rate on gfx950, FP32 ones do not.
+// The loads of SHEET_UNROLL elements per thread are issued before any of them
+// is used, so that a workgroup waits for memory a few times per line rather
+// than once per element it builds.
+constexpr int SHEET_UNROLL = 4;
+
 template <bool NEED_X, bool NEED_Z>
 __device__ __forceinline__ void build_sheets(const ProjArgs &a, const LineP &L, int nrow, float *X, double *Z) {
     const int rz = a.rz;
-    const float *T = L.axis ? a.T1 : a.T0;
-    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
-    for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
-        if (NEED_X) {
-            int r = e / rz;
-            int zp = e - r * rz;
-            int i = L.i_lo + r;
-            float xa = fmaf((float)i, L.dxa, L.xa0);
-            float jf = floorf(xa);
-            float f = xa - jf;
-            size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
-            float t0 = T[base], t1 = T[base + rz];
-            X[e] = fmaf(f, t1 - t0, t0);
+    const int n = nrow * rz;
+    if (NEED_X) {
+        const float *T = L.axis ? a.T1 : a.T0;
+        const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+        const int step = (int)blockDim.x;
+        for (int e0 = threadIdx.x; e0 < n; e0 += SHEET_UNROLL * step) {
+            float t0[SHEET_UNROLL], t1[SHEET_UNROLL], f[SHEET_UNROLL];
+#pragma unroll
+            for (int u = 0; u < SHEET_UNROLL; ++u) {
+                const int e = e0 + u * step;
+                t0[u] = t1[u] = f[u] = 0.f;
+                if (e < n) {
+                    const int r = e / rz;
+                    const int zp = e - r * rz;
+                    const int i = L.i_lo + r;
+                    const float xa = fmaf((float)i, L.dxa, L.xa0);
+                    const float jf = floorf(xa);
+                    f[u] = xa - jf;
+                    const size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
+                    t0[u] = T[base];
+                    t1[u] = T[base + rz];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SHEET_UNROLL; ++u) {
+                const int e = e0 + u * step;
+                if (e < n) X[e] = fmaf(f[u], t1[u] - t0[u], t0[u]);
+            }
         }
-        if (NEED_Z) Z[e] = 0.0;
     }
+    if (NEED_Z)
+        for (int e = threadIdx.x; e < n; e += blockDim.x) Z[e] = 0.0;
 }
 
 // Block epilogue: spread the gradient sheet over the two transaxial neighbours.

@@ -217,7 +217,7 @@ struct pet_counts_s {
     pet_geom_s *g = nullptr;
     int n_subsets = 0;
     int64_t n_items = 0;
-    pet::CountItem *items = nullptr;  // sinogram order
+    pet::CountItem *items = nullptr;  // per line, TOF bin major
     int64_t *line_off = nullptr;      // [n_lines + 1]
     int *lines = nullptr;             // per subset (then all views): lines with counts, most first
     std::vector<int64_t> lines_off;        // [n_subsets + 2] offsets into lines
