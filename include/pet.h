@@ -501,8 +501,14 @@ pet_status pet_batch_set_launch(pet_batch b, int workgroups, int waves, int orde
  * pet_precond, pet_osem_epoch, pet_objective, pet_svrg_epoch(_ex),
  * pet_saga_epoch, pet_sgd_epoch, pet_subset_hvp.  Without the flag (the
  * default) nothing is checked and values outside the domain give unspecified
- * results.  flags: 0 or PET_CHECK (PET_E_ARG otherwise). */
-enum { PET_CHECK = 1 };
+ * results.
+ *
+ * PET_SMALL_CHUNKS caps the chunks of the zero-count-aware kernels at 16 bins
+ * of a line (normally what the LDS holds, thousands), so that tests can run
+ * their chunked path on small problems; results agree up to rounding.
+ * flags: a combination of PET_CHECK and PET_SMALL_CHUNKS (PET_E_ARG for other
+ * bits). */
+enum { PET_CHECK = 1, PET_SMALL_CHUNKS = 2 };
 pet_status pet_geom_set_flags(pet_geom g, unsigned flags);
 
 /* Instrumentation --------------------------------------------------------

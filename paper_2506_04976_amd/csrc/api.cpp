@@ -602,7 +602,7 @@ extern "C" pet_status pet_profile_enable(pet_geom g, int enable) {
 
 extern "C" pet_status pet_geom_set_flags(pet_geom g, unsigned flags) {
     if (!g) return fail(PET_E_ARG, "pet_geom_set_flags: null handle");
-    if (flags & ~(unsigned)PET_CHECK) return fail(PET_E_ARG, "pet_geom_set_flags: unknown flag");
+    if (flags & ~(unsigned)(PET_CHECK | PET_SMALL_CHUNKS)) return fail(PET_E_ARG, "pet_geom_set_flags: unknown flag");
     g->flags = flags;
     return PET_OK;
 }

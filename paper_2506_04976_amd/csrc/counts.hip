@@ -133,13 +133,126 @@ __device__ __forceinline__ float tof_weight_at(const float2 *tab, float pos, flo
     return fmaf(__builtin_amdgcn_fractf(pos), t.y, t.x);
 }
 
+// Geometry of one compacted bin within its line: the sample rows [is, ie]
+// (z range, then TOF window), the table position pos(i) = pA i + pB of row i,
+// the padded axial position u(i) = zA i + zB and the length factor ell.
+struct RecGeo {
+    int is, ie;
+    float pA, pB, zA, zB, ell;
+};
+
+template <bool TOF>
+__device__ __forceinline__ RecGeo rec_geo(const ProjArgs &a, const CountArgs &c, const LineP &L, const CountItem &e,
+                                          bool act) {
+    RecGeo r;
+    const int p = TOF ? (int)(e.pt / (uint32_t)c.n_tof) : (int)e.pt;
+    const int b = TOF ? (int)(e.pt - (uint32_t)p * (uint32_t)c.n_tof) : 0;
+    const PlaneP P = a.planes[p];
+    const float len = sqrtf(L.lt2 + P.dz2);
+    r.ell = L.vm_um * len;
+    z_clip<true>(L, P, a.nz, r.is, r.ie);  // (u is clamped by the loops)
+    if (!act) r.ie = r.is - 1;
+    r.pA = r.pB = 0.f;
+    if (TOF) {
+        // d(i) = t(i) - t_b, t(i) = (lambda(i) - 1/2) |u| the signed distance
+        // from the LOR centre; rows outside |d| <= D (one row of margin, where
+        // the table gives 0) are skipped
+        const float d0 = fmaf(L.lam0 - 0.5f, len, -a.tof.tb[b]);
+        const float dd = L.dlam * len;
+        const float rdd = __builtin_amdgcn_rcpf(dd);
+        const float ia = (-c.wD - d0) * rdd, ib = (c.wD - d0) * rdd;
+        // clamped to [is, ie] (an empty window gives is > ie) before the
+        // conversion; the one-row margin covers the reciprocal's rounding
+        const float lo = fminf(fmaxf(floorf(fminf(ia, ib)) - 1.f, (float)r.is), (float)(r.ie + 1));
+        const float hi = fmaxf(fminf(ceilf(fmaxf(ia, ib)) + 1.f, (float)r.ie), (float)(r.is - 1));
+        r.is = (int)lo;
+        r.ie = (int)hi;
+        r.pA = dd * c.inv_dx;
+        r.pB = fmaf(d0, c.inv_dx, c.pos0);
+    }
+    r.zA = P.zs * L.dlam;
+    r.zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
+    return r;
+}
+
+// Sum over the workgroup, the same value in every thread (wave sums by
+// shuffles, then the wave partials in a fixed order).
+__device__ __forceinline__ float block_sum_all(float v, float *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float t = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+// Packed fixed-point gradient sheet.  A sample with weight q at axial
+// position u = j + f adds (1 - f) q to cell j and f q to cell j + 1.  Cell j
+// holds two 32-bit integer accumulators in one 64-bit word, A[j] (sum of q)
+// and B[j] (sum of f q), as A + 2^32 B, so that one 64-bit integer atomic
+// add (far cheaper in LDS than two FP64 ones) records a sample; the cell's
+// value is then A[j] - B[j] + B[j - 1].  q is scaled by 2^30 / sum_bins |Q|
+// (Q the bin's factor mult y / ybar ell, TOF weights <= 1), so neither sum can
+// leave 31 bits.  Integer sums do not depend on the order of the adds.
+__device__ __forceinline__ void deposit_packed(unsigned long long *zr, int j, float qs, float f) {
+    const int A = (int)__builtin_rintf(qs);
+    const int B = (int)__builtin_rintf(qs * f);
+    const unsigned long long v =
+        (unsigned long long)(uint32_t)A | ((unsigned long long)(uint32_t)(B + (A >> 31)) << 32);
+    atomicAdd(&zr[j], v);
+}
+
+// The two accumulators of a packed cell: the low word read as signed is A,
+// and (w - A) is exactly 2^32 B.
+__device__ __forceinline__ void unpack_cell(unsigned long long w, long long &A, long long &B) {
+    const int lo = (int)(uint32_t)w;
+    A = lo;
+    B = ((long long)w - (long long)lo) >> 32;
+}
+
+// Spread the packed sheet over the two transaxial neighbours (the readout of
+// the FP64 sheet in the dense kernels, after unpacking).  A line whose bound
+// is not finite (a bin with ybar = 0) adds NaN to every cell it covers.
+__device__ __forceinline__ void scatter_sheet_packed(const ProjArgs &a, const LineP &L, int nrow,
+                                                     const unsigned long long *Zu, float inv_scale, bool finite) {
+    const int rz = a.rz;
+    float *Gout = L.axis ? a.G1 : a.G0;
+    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
+        const int r = e / rz;
+        const int zp = e - r * rz;
+        long long A, B, Ap, Bp = 0;
+        unpack_cell(Zu[e], A, B);
+        if (zp > 0) unpack_cell(Zu[e - 1], Ap, Bp);
+        const long long V = A - B + Bp;
+        float val = (float)V * inv_scale;
+        if (!finite) val = __builtin_nanf("");
+        else if (V == 0) continue;
+        const int i = L.i_lo + r;
+        const float xa = fmaf((float)i, L.dxa, L.xa0);
+        const float jf = floorf(xa);
+        const float f = xa - jf;
+        const size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
+        const float a1 = val * f;
+        atomicAdd(&Gout[base], val - a1);
+        atomicAdd(&Gout[base + rz], a1);
+    }
+}
+
 // One workgroup per line with counts.  MODE M_GRAD: gradient sheets receive
-// -P^T [mult y / ybar] and every block writes its FP64 sum of y log(y / ybar);
-// M_OBJ: the sums only.
+// -P^T [mult y / ybar]; M_OBJ: no gradient.  Both write the workgroup's FP64
+// sum of y log(y / ybar) when a.partial is set.
+//
+// The line's bins are taken in chunks of at most c.q_cap.  Phase one walks
+// every bin of the chunk forward (ybar, the log term, Q = mult y / ybar ell,
+// kept in LDS); with M_GRAD, phase two walks them again and adds -Q W(t - t_b)
+// times the axial interpolation weights to the packed sheet, scaled by the
+// chunk's sum of |Q|.  A chunk's sheet is read out before the next starts.
 template <bool TOF, int MODE>
 __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs c) {
     extern __shared__ float4 smem4[];
     float *smem = reinterpret_cast<float *>(smem4);
+    __shared__ float red[CNT_BLOCK / 64];
     constexpr bool NEED_Z = MODE == M_GRAD;
     const int line = c.lines[blockIdx.x];
     const LineP L = a.lines[line];
@@ -147,8 +260,9 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     const int rz = a.rz;
     const int sheet = (a.rows_max * rz + 3) & ~3;
     float *X = smem;
-    double *Z = reinterpret_cast<double *>(smem + sheet);
+    unsigned long long *Zu = reinterpret_cast<unsigned long long *>(smem + sheet);
     float2 *tab = reinterpret_cast<float2 *>(smem + (NEED_Z ? 3 : 1) * sheet);
+    float *Qs = smem + (NEED_Z ? 3 : 1) * sheet + (TOF ? 2 * NW_TAB : 0);
     if (TOF) {
         // (all of a thread's table loads in flight at once; the kernel runs
         // with CNT_BLOCK threads)
@@ -159,88 +273,86 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
 #pragma unroll
         for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) tab[threadIdx.x + u * CNT_BLOCK] = w[u];
     }
-    if (nrow > 0) build_sheets<true, NEED_Z>(a, L, nrow, X, Z);
+    if (nrow > 0) build_sheets<true, NEED_Z>(a, L, nrow, X, reinterpret_cast<double *>(Zu));
     __syncthreads();
 
     double kl = 0.0;
     const int64_t i0 = c.line_off[line], i1 = c.line_off[line + 1];
     const float umax = (float)(a.nz + PADZ);
-    // C lanes per bin (a power of two, consecutive lanes of one wave) take every
-    // C-th sample of its window; C grows while the line's bins still fill the
-    // workgroup, so that lines with few bins keep every wave busy
-    const int n_it = (int)(i1 - i0);
-    int C = 1;
-    while (C < 16 && n_it * (2 * C) <= (int)blockDim.x) C *= 2;
-    const int ch = threadIdx.x & (C - 1);
-    const int nslot = blockDim.x / C;
     // (a line that misses the image still has bins with counts: ybar = add there,
     // and its y log(y / add) enters the sum; its sample ranges are empty)
-    for (int64_t it0 = i0; it0 < i1; it0 += nslot) {
-        // every lane runs every round: the forward sums are added across the
-        // C lanes of a bin by shuffles
-        const int64_t it = it0 + threadIdx.x / C;
-        const bool act = it < i1;
-        const CountItem e = act ? c.items[it] : CountItem{0u, 0.f, 1.f, 0.f};
-        const int p = TOF ? (int)(e.pt / (uint32_t)c.n_tof) : (int)e.pt;
-        const int b = TOF ? (int)(e.pt - (uint32_t)p * (uint32_t)c.n_tof) : 0;
-        const PlaneP P = a.planes[p];
-        const float len = sqrtf(L.lt2 + P.dz2);
-        const float ell = L.vm_um * len;
-        int is, ie;
-        z_clip<true>(L, P, a.nz, is, ie);  // (u is clamped below)
-        if (!act) ie = is - 1;
-        // d(i) = t(i) - t_b, t(i) = (lambda(i) - 1/2) |u| the signed distance
-        // from the LOR centre; rows outside |d| <= D (one row of margin, where
-        // the table gives 0) are skipped
-        // table position of row i: pos(i) = (t(i) - t_b) / dx + NW/2, affine in i
-        float pA = 0.f, pB = 0.f;
-        if (TOF) {
-            const float d0 = fmaf(L.lam0 - 0.5f, len, -a.tof.tb[b]);
-            const float dd = L.dlam * len;
-            const float rdd = __builtin_amdgcn_rcpf(dd);
-            const float ia = (-c.wD - d0) * rdd, ib = (c.wD - d0) * rdd;
-            // clamped to [is, ie] (an empty window gives is > ie) before the
-            // conversion; the one-row margin covers the reciprocal's rounding
-            const float lo = fminf(fmaxf(floorf(fminf(ia, ib)) - 1.f, (float)is), (float)(ie + 1));
-            const float hi = fmaxf(fminf(ceilf(fmaxf(ia, ib)) + 1.f, (float)ie), (float)(is - 1));
-            is = (int)lo;
-            ie = (int)hi;
-            pA = dd * c.inv_dx;
-            pB = fmaf(d0, c.inv_dx, c.pos0);
-        }
-        const float zA = P.zs * L.dlam, zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
-        // rows as floats (exact integers): no conversion per sample
-        const float fC = (float)C, fis = (float)(is + ch), fie = (float)ie;
-        float s = 0.f;
-        const float *xr = X + (is + ch - L.i_lo) * rz;
-        for (float fi = fis; fi <= fie; fi += fC, xr += C * rz) {
-            const float u = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), 0.f, umax);
-            const int j = (int)u;
-            const float x0 = xr[j], x1 = xr[j + 1];
-            const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
-            s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, pA, pB), c.pos_max), v, s) : s + v;
-        }
-        for (int o = 1; o < C; o <<= 1) s += __shfl_xor(s, o, 64);
-        if (!act) continue;
-        const float ybar = fmaf(e.mult, s * ell, e.add);
-        // (the FP64 logarithm only when the sums are wanted)
-        if (a.partial && ch == 0) kl += (double)e.y * log((double)e.y / (double)ybar);
-        if (NEED_Z) {
-            const float Q = -e.mult * e.y * __builtin_amdgcn_rcpf(ybar) * ell;
-            double *zr = Z + (is + ch - L.i_lo) * rz;
-            for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
-                const float qw = TOF ? Q * tof_weight_at(tab, fmaf(fi, pA, pB), c.pos_max) : Q;
-                const float u = __builtin_amdgcn_fmed3f(fmaf(fi, zA, zB), 0.f, umax);
+    for (int64_t c0 = i0; c0 < i1; c0 += c.q_cap) {
+        const int64_t c1 = c0 + c.q_cap < i1 ? c0 + c.q_cap : i1;
+        // C lanes per bin (a power of two, consecutive lanes of one wave) take
+        // every C-th sample of its window; C grows while the chunk's bins
+        // still fill the workgroup, so that lines with few bins keep every
+        // wave busy
+        const int n_c = (int)(c1 - c0);
+        int C = 1;
+        while (C < 16 && n_c * (2 * C) <= (int)blockDim.x) C *= 2;
+        const int ch = threadIdx.x & (C - 1);
+        const int nslot = blockDim.x / C;
+        const float fC = (float)C;
+        float qabs = 0.f;
+        for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
+            // every lane runs every round: the forward sums are added across
+            // the C lanes of a bin by shuffles
+            const int64_t it = it0 + threadIdx.x / C;
+            const bool act = it < c1;
+            const CountItem e = act ? c.items[it] : CountItem{0u, 0.f, 1.f, 0.f};
+            const RecGeo g = rec_geo<TOF>(a, c, L, e, act);
+            // rows as floats (exact integers): no conversion per sample
+            const float fis = (float)(g.is + ch), fie = (float)g.ie;
+            float s = 0.f;
+            const float *xr = X + (g.is + ch - L.i_lo) * rz;
+            for (float fi = fis; fi <= fie; fi += fC, xr += C * rz) {
+                const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
                 const int j = (int)u;
-                const float a1 = qw * __builtin_amdgcn_fractf(u);
-                atomicAdd(&zr[j], (double)(qw - a1));
-                atomicAdd(&zr[j + 1], (double)a1);
+                const float x0 = xr[j], x1 = xr[j + 1];
+                const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
+                s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max), v, s) : s + v;
+            }
+            for (int o = 1; o < C; o <<= 1) s += __shfl_xor(s, o, 64);
+            if (!act || ch != 0) continue;
+            const float ybar = fmaf(e.mult, s * g.ell, e.add);
+            // (the FP64 logarithm only when the sums are wanted)
+            if (a.partial) kl += (double)e.y * log((double)e.y / (double)ybar);
+            if (NEED_Z) {
+                const float Q = e.mult * e.y * __builtin_amdgcn_rcpf(ybar) * g.ell;
+                Qs[it - c0] = Q;
+                qabs += fabsf(Q);
             }
         }
-    }
-    if (NEED_Z && nrow > 0) {
+        if (!NEED_Z) continue;  // uniform
+        // (the barrier inside also publishes Qs)
+        const float bound = block_sum_all(qabs, red);
+        const bool finite = bound < INFINITY;  // false for inf and NaN
+        const float scale = finite && bound > 0.f ? 0x1p30f / bound : 0.f;
+        if (scale > 0.f) {
+            for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
+                const int64_t it = it0 + threadIdx.x / C;
+                const bool act = it < c1;
+                const CountItem e = act ? c.items[it] : CountItem{0u, 0.f, 1.f, 0.f};
+                const RecGeo g = rec_geo<TOF>(a, c, L, e, act);
+                const float qsc = act ? -Qs[act ? (int)(it - c0) : 0] * scale : 0.f;  // (index < q_cap)
+                const float fis = (float)(g.is + ch), fie = (float)g.ie;
+                unsigned long long *zr = Zu + (g.is + ch - L.i_lo) * rz;
+                for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                    const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
+                    const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                    deposit_packed(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
+                }
+            }
+        }
         __syncthreads();
-        scatter_sheet(a, L, nrow, Z);
+        if (nrow > 0 && (scale > 0.f || !finite))
+            scatter_sheet_packed(a, L, nrow, Zu, finite ? 1.f / scale : 0.f, finite);
+        if (c1 < i1) {
+            // the next chunk starts from a zero sheet (after every readout)
+            __syncthreads();
+            for (int k = threadIdx.x; k < nrow * rz; k += blockDim.x) Zu[k] = 0ull;
+            __syncthreads();
+        }
     }
     if (a.partial) block_sums(kl, kl, a.partial, false);
 }
@@ -265,10 +377,25 @@ hipError_t launch_counts_mode(const pet_geom_s *g, const pet_counts_s *cs, int n
 
 }  // namespace
 
-size_t counts_lds_bytes(const pet_geom_s *g, int mode) {
+// LDS of the sheets and the TOF table (dynamic), and what the gradient mode
+// keeps per bin of a chunk: its factor Q, 4 bytes.
+static size_t counts_lds_base(const pet_geom_s *g, int mode) {
     const size_t sheet = ((size_t)g->rows_max * (g->d.nz + 2 * PADZ) + 3) & ~(size_t)3;
     const size_t tab = g->d.n_tof > 1 ? sizeof(float2) * NW_TAB : 0;
     return (mode == M_GRAD ? 3 : 1) * sheet * sizeof(float) + tab;
+}
+
+// Bins per chunk: what the LDS left after the sheets, the table and 1 KB of
+// static shared memory holds, at most 8192 (0 if less than 256 fit).
+static int counts_q_cap(const pet_geom_s *g) {
+    const size_t base = counts_lds_base(g, M_GRAD) + 1024;
+    if (base >= g->max_lds) return 0;
+    const size_t fit = ((g->max_lds - base) / sizeof(float)) & ~(size_t)3;
+    return fit < 256 ? 0 : (int)std::min<size_t>(fit, 8192);
+}
+
+size_t counts_lds_bytes(const pet_geom_s *g, int mode) {
+    return counts_lds_base(g, mode) + (mode == M_GRAD ? sizeof(float) * (size_t)counts_q_cap(g) : 0);
 }
 
 int counts_blocks(const pet_counts_s *cs, int subset) {
@@ -291,6 +418,7 @@ hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *cs, int mode, i
     c.inv_dx = (float)(NW_TAB / (2.0 * g->wD));
     c.pos0 = (float)(NW_TAB / 2);
     c.pos_max = (float)NW_TAB - 1e-3f;
+    c.q_cap = mode != M_GRAD ? (1 << 30) : (g->flags & PET_SMALL_CHUNKS) ? std::min(16, counts_q_cap(g)) : counts_q_cap(g);
     const size_t lds = counts_lds_bytes(g, mode);
     const bool tof = g->d.n_tof > 1;
     const int threads = CNT_BLOCK;
@@ -335,7 +463,7 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
     const int n_lines = g->d.n_views * g->d.n_rad;
     const int64_t bpl = (int64_t)g->n_planes * g->d.n_tof;
     if (bpl > (int64_t)UINT32_MAX) return fail(PET_E_ARG, "pet_counts_create: too many bins per line");
-    if (counts_lds_bytes(g, M_GRAD) > g->max_lds)
+    if (counts_q_cap(g) == 0)
         return fail(PET_E_ARG, "pet_counts_create: the sheets and TOF table of this geometry exceed the LDS");
     pet_counts_s *c = new (std::nothrow) pet_counts_s();
     if (!c) return fail(PET_E_OOM, "pet_counts_create: host allocation failed");

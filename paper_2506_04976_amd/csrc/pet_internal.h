@@ -113,6 +113,7 @@ struct CountArgs {
     int nw, n_tof;
     float wD;                 // support of W: |d| <= wD
     float inv_dx, pos0, pos_max;  // table position of d: d * inv_dx + pos0, clamped to [0, pos_max]
+    int q_cap;                // bins per chunk of a line (their factors Q are kept in LDS)
 };
 
 // ---- batches of reconstructions -------------------------------------------

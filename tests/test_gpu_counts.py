@@ -92,6 +92,30 @@ def test_counts_subset_grad_and_kl_parity(case):
         assert err_h <= 1e-5, f"subset {subset}: {err_h:.3e}"
 
 
+def test_counts_chunked_grad_parity(case):
+    # PET_SMALL_CHUNKS cuts every line's bins into chunks of 16, each with its
+    # own fixed-point scale and sheet readout: same oracle bar as above
+    pm = case.pm
+    y = case.d["y"]
+    per_line = np.count_nonzero(y.reshape(y.shape[0] * y.shape[1], -1), axis=1)
+    xo = case.x_np.astype(np.float64)
+    pm.pet_geom_set_flags(case.geom, pm.PET_SMALL_CHUNKS)
+    try:
+        for subset in range(case.cfg["n_subsets"]):
+            sens = case.sens_subset(subset)
+            g = torch.full((case.geom.n_vox,), float("nan"), device=case.dev)
+            pm.pet_subset_grad_counts(case.geom, case.counts, subset, case.x, sens, g)
+            ref = case.prob.data_grad(xo, subset).ravel()
+            yb = case.prob.ybar(xo, subset)
+            scale = np.linalg.norm(case.prob.back(case.prob.a[subset] * (1 + case.prob.y[subset] / yb), subset))
+            err = np.linalg.norm(g.cpu().double().numpy() - ref) / scale
+            assert err <= 1e-5, f"subset {subset}: {err:.3e}"
+    finally:
+        pm.pet_geom_set_flags(case.geom, 0)
+    if case.cfg["kind"] != "parallel2d":  # (2D lines hold one bin each)
+        assert per_line.max() > 16, "no line has more than one chunk"
+
+
 def test_counts_objective_parity(case):
     pm = case.pm
     sens = case.sens_subset(-1)
