@@ -15,14 +15,27 @@ namespace {
 // image rows x[z][y][x0 .. x0 + 31] for every z (coalesced along x) and writes,
 // per x, the z-contiguous rows of both sheets (coalesced along z).
 constexpr int TT = 32;
+constexpr int TILE_UNROLL = 8;
 __global__ void __launch_bounds__(256) k_to_sheets_t(const float *__restrict__ x, float *__restrict__ T0,
                                                      float *__restrict__ T1, int nx, int ny, int nz, int rz) {
     extern __shared__ float tile[];  // [nz][TT + 1]
     const int x0 = blockIdx.x * TT, iy = blockIdx.y;
     const int w = min(TT, nx - x0);
-    for (int e = threadIdx.x; e < nz * TT; e += blockDim.x) {
-        const int z = e / TT, xx = e - z * TT;
-        tile[z * (TT + 1) + xx] = xx < w ? x[((size_t)z * ny + iy) * nx + x0 + xx] : 0.f;
+    // (TILE_UNROLL loads per thread in flight before their LDS writes)
+    for (int e0 = threadIdx.x; e0 < nz * TT; e0 += TILE_UNROLL * blockDim.x) {
+        float val[TILE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < TILE_UNROLL; ++u) {
+            const int e = e0 + u * blockDim.x;
+            const int z = e / TT, xx = e - z * TT;
+            val[u] = e < nz * TT && xx < w ? x[((size_t)z * ny + iy) * nx + x0 + xx] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < TILE_UNROLL; ++u) {
+            const int e = e0 + u * blockDim.x;
+            const int z = e / TT, xx = e - z * TT;
+            if (e < nz * TT) tile[z * (TT + 1) + xx] = val[u];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
@@ -38,11 +51,25 @@ __global__ void __launch_bounds__(256) k_to_sheets_t(const float *__restrict__ x
 // (32 consecutive x, one y, every z) into LDS, read z-contiguous.
 __device__ __forceinline__ void sheets_to_tile(const float *__restrict__ G0, const float *__restrict__ G1,
                                                float *tile, int x0, int w, int iy, int nx, int ny, int nz, int rz) {
-    for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
-        const int xx = e / nz, z = e - xx * nz;
-        const int ix = x0 + xx;
-        tile[z * (TT + 1) + xx] = G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] +
-                                  G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ];
+    for (int e0 = threadIdx.x; e0 < w * nz; e0 += TILE_UNROLL * blockDim.x) {
+        float a[TILE_UNROLL], b[TILE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < TILE_UNROLL; ++u) {
+            const int e = e0 + u * blockDim.x;
+            const int xx = e / nz, z = e - xx * nz;
+            const int ix = x0 + xx;
+            a[u] = b[u] = 0.f;
+            if (e < w * nz) {
+                a[u] = G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ];
+                b[u] = G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < TILE_UNROLL; ++u) {
+            const int e = e0 + u * blockDim.x;
+            const int xx = e / nz, z = e - xx * nz;
+            if (e < w * nz) tile[z * (TT + 1) + xx] = a[u] + b[u];
+        }
     }
     __syncthreads();
 }
@@ -63,7 +90,19 @@ __global__ void __launch_bounds__(256) k_from_sheets_t(const float *__restrict__
     }
 }
 
-// Both gradient sheets to zero in one launch.
+// Both gradient sheets to zero in one launch: 16-byte stores when both are
+// 16-byte aligned and hold a multiple of 4 floats.
+__global__ void k_zero2_v4(float4 *__restrict__ a, int64_t na4, float4 *__restrict__ b, int64_t nb4) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na4 + nb4; i += stride) {
+        if (i < na4)
+            a[i] = z;
+        else
+            b[i - na4] = z;
+    }
+}
+
 __global__ void k_zero2(float *__restrict__ a, int64_t na, float *__restrict__ b, int64_t nb) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na + nb; i += stride) {
@@ -122,13 +161,62 @@ struct RdpArgs {
     const double *tau_bb;
 };
 
-// One thread per voxel.  RDP (eq. (rdp)) with gradient and Hessian diagonal as
-// in Appendix A: d = x_i - x_j, s = x_i + x_j, phi = s + gamma |d| + eps,
-//   dS/dx_i += w k_i k_j d (2 phi - (d + gamma |d|)) / phi^2
-//   d2S/dx_i^2 += 2 w k_i k_j (s - d + eps)^2 / phi^3
-//   S += 1/2 w k_i k_j d^2 / phi   (each ordered pair once, halved).
-// (32-bit voxel indices: images hold fewer than 2^31 voxels; 1 / phi is the
-// hardware reciprocal, within 1 ulp)
+// RDP sums of one voxel over its 26 neighbours (eq. (rdp); derivatives as in
+// Appendix A): with d = x_i - x_j, phi = x_i + x_j + gamma |d| + eps and
+// c = 2 x_j + eps (= s - d + eps, s = x_i + x_j),
+//   dS/dx_i   += w k_i k_j d (phi + c) / phi^2     (2 phi - d - gamma |d| = phi + c)
+//   d2S/dx_i^2 += 2 w k_i k_j c^2 / phi^3
+//   S         += 1/2 w k_i k_j d^2 / phi          (each ordered pair once, halved).
+// Branch-free: neighbour coordinates are clamped to the grid and a neighbour
+// outside it gets 1 / phi = 0, so it adds nothing.  1 / phi is the hardware
+// reciprocal, within 1 ulp.
+template <int F, bool KAPPA>
+__device__ __forceinline__ void rdp_sums(const RdpArgs &a, int v, int ix, int iy, int iz, float xi, float &g, float &h,
+                                         float &sv) {
+    const int nxy = a.nx * a.ny;
+    const float ki = KAPPA ? a.kappa[v] : 1.f;
+    const float xe = xi + a.eps;
+    int jz[3], jy[3], jx[3];
+    bool oz[3], oy[3], ox[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int z = iz + k - 1, y = iy + k - 1, x = ix + k - 1;
+        oz[k] = z >= 0 && z < a.nz;
+        oy[k] = y >= 0 && y < a.ny;
+        ox[k] = x >= 0 && x < a.nx;
+        jz[k] = min(max(z, 0), a.nz - 1) * nxy;
+        jy[k] = min(max(y, 0), a.ny - 1) * a.nx;
+        jx[k] = min(max(x, 0), a.nx - 1);
+    }
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int rowb = jz[dz] + jy[dy];
+            const bool ozy = oz[dz] && oy[dy];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                if (dz == 1 && dy == 1 && dx == 1) continue;
+                const int u = rowb + jx[dx];
+                const float xj = a.x[u];
+                float wk = a.w.w[dz * 9 + dy * 3 + dx];
+                if (KAPPA) wk *= ki * a.kappa[u];
+                const float d = xi - xj;
+                const float phi = fmaf(a.gamma, fabsf(d), xe + xj);
+                const float r = ozy && ox[dx] ? __builtin_amdgcn_rcpf(phi) : 0.f;
+                const float c = fmaf(2.f, xj, a.eps);
+                const float r2 = r * r;
+                g = fmaf(wk * d * (phi + c), r2, g);
+                if (F & (R_HESS_OUT | R_PRECOND)) h = fmaf(2.f * wk * c * c, r2 * r, h);
+                if (F & R_VALUE) sv = fmaf(wk * d * d, r, sv);
+            }
+        }
+    }
+}
+
+// One thread per voxel: the RDP sums, then what the flags ask for (gradient,
+// Hessian diagonal, value, preconditioner, the fused estimator and step).
+// (32-bit voxel indices: images hold fewer than 2^31 voxels)
 template <int F>
 __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
     const int nxy = a.nx * a.ny;
@@ -141,37 +229,11 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
         const int iy = rem / a.nx;
         const int ix = rem - iy * a.nx;
         const float xi = a.x[v];
-        const float ki = a.kappa ? a.kappa[v] : 1.f;
         float g = 0.f, h = 0.f, sv = 0.f;
-#pragma unroll
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int jz = iz + dz;
-            if (jz < 0 || jz >= a.nz) continue;
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int jy = iy + dy;
-                if (jy < 0 || jy >= a.ny) continue;
-#pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (dx == 0 && dy == 0 && dz == 0) continue;
-                    const int jx = ix + dx;
-                    if (jx < 0 || jx >= a.nx) continue;
-                    const int u = v + dz * nxy + dy * a.nx + dx;
-                    const float xj = a.x[u];
-                    const float wk = a.w.w[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] * ki * (a.kappa ? a.kappa[u] : 1.f);
-                    const float d = xi - xj;
-                    const float ad = fabsf(d);
-                    const float phi = xi + xj + a.gamma * ad + a.eps;
-                    const float rphi = __builtin_amdgcn_rcpf(phi);
-                    g = fmaf(wk * d * (2.f * phi - (d + a.gamma * ad)), rphi * rphi, g);
-                    if (F & (R_HESS_OUT | R_PRECOND)) {
-                        const float c = 2.f * xj + a.eps;  // s - d + eps
-                        h = fmaf(2.f * wk * c * c, rphi * rphi * rphi, h);
-                    }
-                    if (F & R_VALUE) sv = fmaf(wk * d * d, rphi, sv);
-                }
-            }
-        }
+        if (a.kappa)
+            rdp_sums<F, true>(a, v, ix, iy, iz, xi, g, h, sv);
+        else
+            rdp_sums<F, false>(a, v, ix, iy, iz, xi, g, h, sv);
         const float bg = a.beta * g;
         const float bh = a.beta * h;
         if (F & R_GRAD_OUT) a.grad[v] = bg;
@@ -546,8 +608,13 @@ hipError_t launch_clear_image_sheets(const pet_geom_s *g, const SheetBufs &w, hi
 }
 
 hipError_t launch_zero_sheets_b(const pet_geom_s *g, const SheetBufs &w, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero2, grid_for((int64_t)(g->t0_elems + g->t1_elems)), dim3(IMG_BLOCK), 0, s, w.G0,
-                       (int64_t)g->t0_elems, w.G1, (int64_t)g->t1_elems);
+    const int64_t n0 = (int64_t)g->t0_elems, n1 = (int64_t)g->t1_elems;
+    if ((reinterpret_cast<uintptr_t>(w.G0) | reinterpret_cast<uintptr_t>(w.G1)) % 16 == 0 && n0 % 4 == 0 &&
+        n1 % 4 == 0)
+        hipLaunchKernelGGL(k_zero2_v4, grid_for((n0 + n1) / 4), dim3(IMG_BLOCK), 0, s,
+                           reinterpret_cast<float4 *>(w.G0), n0 / 4, reinterpret_cast<float4 *>(w.G1), n1 / 4);
+    else
+        hipLaunchKernelGGL(k_zero2, grid_for(n0 + n1), dim3(IMG_BLOCK), 0, s, w.G0, n0, w.G1, n1);
     return hipGetLastError();
 }
 
