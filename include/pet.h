@@ -506,9 +506,13 @@ pet_status pet_batch_set_launch(pet_batch b, int workgroups, int waves, int orde
  * PET_SMALL_CHUNKS caps the chunks of the zero-count-aware kernels at 16 bins
  * of a line (normally what the LDS holds, thousands), so that tests can run
  * their chunked path on small problems; results agree up to rounding.
- * flags: a combination of PET_CHECK and PET_SMALL_CHUNKS (PET_E_ARG for other
- * bits). */
-enum { PET_CHECK = 1, PET_SMALL_CHUNKS = 2 };
+ * PET_SIGNED_SHEETS makes the zero-count-aware kernels accumulate their
+ * fixed-point gradient sheets in the signed form that they otherwise take
+ * only for chunks with a negative mean (outside the domain), so that tests
+ * can run it on well-conditioned data; results agree up to rounding.
+ * flags: a combination of PET_CHECK, PET_SMALL_CHUNKS and PET_SIGNED_SHEETS
+ * (PET_E_ARG for other bits). */
+enum { PET_CHECK = 1, PET_SMALL_CHUNKS = 2, PET_SIGNED_SHEETS = 4 };
 pet_status pet_geom_set_flags(pet_geom g, unsigned flags);
 
 /* Instrumentation --------------------------------------------------------

@@ -23,6 +23,7 @@ PET_BACK_GATHER = 2
 PET_Y_F32, PET_Y_U16, PET_Y_U8 = 0, 1, 2
 PET_CHECK = 1
 PET_SMALL_CHUNKS = 2
+PET_SIGNED_SHEETS = 4
 
 _STATUS = {0: "PET_OK", 1: "PET_E_ARG", 2: "PET_E_DOMAIN", 3: "PET_E_OOM", 4: "PET_E_HIP",
            5: "PET_E_NUMERIC", 6: "PET_E_STATE"}

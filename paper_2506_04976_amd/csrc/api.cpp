@@ -140,8 +140,8 @@ namespace {
 // Data-term gradient of one subset into the gradient sheets (G0, G1); the
 // image sheets must already hold x.  Optionally FP64 KL sum into kl_out.
 hipError_t subset_grad_sheets(pet_geom g, int subset, const void *y, int dt, const float *add, const float *mult,
-                              double *kl_out, int kl_accumulate, hipStream_t s) {
-    hipError_t e = launch_zero_sheets(g, s);
+                              double *kl_out, int kl_accumulate, hipStream_t s, bool zeroed = false) {
+    hipError_t e = zeroed ? hipSuccess : launch_zero_sheets(g, s);
     if (e != hipSuccess) return e;
     ProjArgs a = base_args(g, subset);
     a.y = y;
@@ -198,8 +198,8 @@ hipError_t hvp_impl(pet_geom g, int subset, const float *x, const float *v, cons
 // the gradient sheets (the image sheets must hold x); optionally the FP64 sum
 // of y log(y / ybar) over the subset's bins with counts into *ylogy_out.
 hipError_t counts_grad_sheets(pet_geom g, const pet_counts_s *c, int subset, double *ylogy_out, hipStream_t s,
-                              int accumulate = 0) {
-    hipError_t e = launch_zero_sheets(g, s);
+                              int accumulate = 0, bool zeroed = false) {
+    hipError_t e = zeroed ? hipSuccess : launch_zero_sheets(g, s);
     ProjArgs a = base_args(g, subset);
     a.partial = ylogy_out ? g->partial : nullptr;
     if (e == hipSuccess) e = launch_line_counts(g, c, M_GRAD, subset, a, s);
@@ -437,13 +437,20 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
     // the iterate alternates between x and the handle's xtmp (the step reads
     // neighbours, so it cannot update in place); one copy at the end if needed
     float *cur = x, *nxt = g->xtmp;
+    // Fused steps (k_step_tile) leave the image sheets of the new iterate and
+    // cleared gradient sheets behind, so that the next iteration converts
+    // nothing: `sheets` = the image sheets hold cur, `zeroed` = the gradient
+    // sheets' interiors are zero.
+    const bool fuse = step_tile_ok(g) && !st->kappa && !st->gnorm;
+    bool sheets = false, zeroed = false;
     for (int j = 0; j < n && e == hipSuccess; ++j) {
         const int64_t k = st->k + j;
         const bool snap = (k % om) == 0;
         const int i = subset_seq[j];
         const float w = (opt && opt->weight) ? opt->weight[j] : (float)n;
         if (st->bb && k == 0) e = launch_bb_init(st->bb, s);
-        if (e == hipSuccess) e = launch_to_sheets(g, cur, s);
+        if (e == hipSuccess && !sheets) e = launch_to_sheets(g, cur, s);
+        sheets = false;
         if (snap) {
             // with snap_objective, the snapshot's own passes also sum the data
             // term at xhat (no extra projection)
@@ -468,10 +475,17 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             // BB bookkeeping: 0 none, 1 keep the full gradient, 2 also recompute the step bound
             const int bb_mode = !st->bb ? 0 : (opt && opt->bb_update && opt->bb_update[j] && k > 0) ? 2 : 1;
             float *grad_out = st->gnorm ? g->num : nullptr;
-            if (e == hipSuccess)
+            zeroed = false;  // (the gradient sheets hold the last subset's)
+            if (e == hipSuccess && fuse && bb_mode < 2) {
+                e = launch_svrg_step_tile(g, cur, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
+                                          st->alpha, st->delta, st->D, 1, st->ghat_i + (size_t)i * nv, st->ghat, w,
+                                          tau[j], tau_bb, bb_mode == 1, st->g_prev, nxt, s);
+                sheets = true;
+            } else if (e == hipSuccess) {
                 e = launch_svrg_step_ex(g, cur, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
                                         st->alpha, st->delta, st->D, 1, g->g, st->ghat_i + (size_t)i * nv, st->ghat, w,
                                         tau[j], tau_bb, bb_mode, st->x_snap, st->g_prev, grad_out, nxt, s);
+            }
             if (e == hipSuccess && bb_mode == 2) {
                 e = launch_bb_finish(g, st->bb, s);
                 if (e == hipSuccess) e = launch_step_stored(g, cur, st->D, st->g_prev, tau[j], tau_bb, nxt, s);
@@ -479,13 +493,22 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             if (e == hipSuccess && st->gnorm) e = launch_subset_norms(g, st->ghat_i, g->num, st->gnorm, s);
             if (e == hipSuccess) e = launch_copy(st->x_snap, cur, nv, s);
         } else {
-            e = st->counts ? counts_grad_sheets(g, st->counts, i, nullptr, s)
-                           : subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
-            if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
-            if (e == hipSuccess)
-                e = launch_svrg_step_ex(g, cur, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
-                                        st->alpha, st->delta, st->D, 0, g->g, st->ghat_i + (size_t)i * nv, st->ghat, w,
-                                        tau[j], tau_bb, 0, nullptr, nullptr, nullptr, nxt, s);
+            e = st->counts ? counts_grad_sheets(g, st->counts, i, nullptr, s, 0, zeroed)
+                           : subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s, zeroed);
+            if (fuse) {
+                if (e == hipSuccess)
+                    e = launch_svrg_step_tile(g, cur, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
+                                              st->alpha, st->delta, st->D, 0, st->ghat_i + (size_t)i * nv, st->ghat,
+                                              w, tau[j], tau_bb, 0, nullptr, nxt, s);
+                sheets = zeroed = true;
+            } else {
+                if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
+                if (e == hipSuccess)
+                    e = launch_svrg_step_ex(g, cur, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j],
+                                            st->sens, st->alpha, st->delta, st->D, 0, g->g,
+                                            st->ghat_i + (size_t)i * nv, st->ghat, w, tau[j], tau_bb, 0, nullptr,
+                                            nullptr, nullptr, nxt, s);
+            }
         }
         std::swap(cur, nxt);
     }
@@ -602,7 +625,8 @@ extern "C" pet_status pet_profile_enable(pet_geom g, int enable) {
 
 extern "C" pet_status pet_geom_set_flags(pet_geom g, unsigned flags) {
     if (!g) return fail(PET_E_ARG, "pet_geom_set_flags: null handle");
-    if (flags & ~(unsigned)(PET_CHECK | PET_SMALL_CHUNKS)) return fail(PET_E_ARG, "pet_geom_set_flags: unknown flag");
+    if (flags & ~(unsigned)(PET_CHECK | PET_SMALL_CHUNKS | PET_SIGNED_SHEETS))
+        return fail(PET_E_ARG, "pet_geom_set_flags: unknown flag");
     g->flags = flags;
     return PET_OK;
 }

@@ -84,74 +84,22 @@ __global__ void __launch_bounds__(256) k_counts_per_line(const void *__restrict_
     }
 }
 
-// Compaction of one line's bins with y > 0, TOF bin major (then plane): the
-// records that share a wave then have TOF windows at the same place along the
-// line, so their sample loops run for about the same number of rows.
-__global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y, int dt, const float *__restrict__ add,
-                                                     const float *__restrict__ mult, int64_t bins_per_line, int n_tof,
-                                                     int n_planes, const int64_t *__restrict__ line_off,
-                                                     CountItem *__restrict__ items) {
-    __shared__ int s_w[4];
-    const int64_t base = (int64_t)blockIdx.x * bins_per_line;
-    int64_t out = line_off[blockIdx.x];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int64_t q0 = 0; q0 < bins_per_line; q0 += blockDim.x) {
-        const int64_t q = q0 + threadIdx.x;  // (TOF bin, plane) rank
-        const int64_t bq = q / n_planes;
-        const int64_t k = (q - bq * n_planes) * n_tof + bq;  // sinogram index within the line
-        const float v = q < bins_per_line ? count_y(y, dt, base + k) : 0.f;
-        const bool has = v > 0.f;
-        const uint64_t m = __ballot(has);
-        if (lane == 0) s_w[w] = __popcll(m);
-        __syncthreads();
-        int before = 0, total = 0;
-        for (int i = 0; i < nw; ++i) {
-            before += i < w ? s_w[i] : 0;
-            total += s_w[i];
-        }
-        if (has) {
-            const int rank = before + __popcll(m & ((1ull << lane) - 1ull));
-            const int plane = (int)(k / n_tof);
-            CountItem it;
-            it.pt = (uint32_t)k;
-            it.y = v;
-            it.add = add ? add[base + k] : 0.f;
-            it.mult = mult ? mult[(int64_t)blockIdx.x * n_planes + plane] : 1.f;
-            items[out + rank] = it;
-        }
-        out += total;
-        __syncthreads();
-    }
-}
-
-// TOF weight W(d) from the LDS table, at table position pos = d / dx + NW/2:
-// linear interpolation between nodes; the position is clamped to the table,
-// whose end nodes are 0.
-__device__ __forceinline__ float tof_weight_at(const float2 *tab, float pos, float pos_max) {
-    pos = __builtin_amdgcn_fmed3f(pos, 0.f, pos_max);
-    const float2 t = tab[(int)pos];
-    return fmaf(__builtin_amdgcn_fractf(pos), t.y, t.x);
-}
-
-// Geometry of one compacted bin within its line: the sample rows [is, ie]
-// (z range, then TOF window), the table position pos(i) = pA i + pB of row i,
-// the padded axial position u(i) = zA i + zB and the length factor ell.
+// Geometry of one bin with counts within its line (plane p, TOF bin b): the
+// sample rows [is, ie] (z range, then TOF window), the table position
+// pos(i) = pA i + pB of row i, the padded axial position u(i) = zA i + zB
+// and the step length ell.
 struct RecGeo {
     int is, ie;
     float pA, pB, zA, zB, ell;
 };
 
 template <bool TOF>
-__device__ __forceinline__ RecGeo rec_geo(const ProjArgs &a, const CountArgs &c, const LineP &L, const CountItem &e,
-                                          bool act) {
+__device__ __forceinline__ RecGeo rec_geo(const ProjArgs &a, const CountArgs &c, const LineP &L, const PlaneP &P,
+                                          int b) {
     RecGeo r;
-    const int p = TOF ? (int)(e.pt / (uint32_t)c.n_tof) : (int)e.pt;
-    const int b = TOF ? (int)(e.pt - (uint32_t)p * (uint32_t)c.n_tof) : 0;
-    const PlaneP P = a.planes[p];
     const float len = sqrtf(L.lt2 + P.dz2);
     r.ell = L.vm_um * len;
     z_clip<true>(L, P, a.nz, r.is, r.ie);  // (u is clamped by the loops)
-    if (!act) r.ie = r.is - 1;
     r.pA = r.pB = 0.f;
     if (TOF) {
         // d(i) = t(i) - t_b, t(i) = (lambda(i) - 1/2) |u| the signed distance
@@ -175,14 +123,80 @@ __device__ __forceinline__ RecGeo rec_geo(const ProjArgs &a, const CountArgs &c,
     return r;
 }
 
+// Compaction of one line's bins with y > 0, TOF bin major (then plane): the
+// records that share a wave then have TOF windows at the same place along the
+// line, so their sample loops run for about the same number of rows.  Each
+// record carries its LOR's geometry (rec_geo), so that the line kernels load
+// one record per bin and nothing else.
+template <bool TOF>
+__global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y, int dt, const float *__restrict__ add,
+                                                     const float *__restrict__ mult, int64_t bins_per_line,
+                                                     const int64_t *__restrict__ line_off, ProjArgs a, CountArgs c,
+                                                     CountRec *__restrict__ items) {
+    __shared__ int s_w[4];
+    const int n_tof = c.n_tof, n_planes = a.n_planes;
+    const int64_t base = (int64_t)blockIdx.x * bins_per_line;
+    const LineP L = a.lines[blockIdx.x];
+    int64_t out = line_off[blockIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t q0 = 0; q0 < bins_per_line; q0 += blockDim.x) {
+        const int64_t q = q0 + threadIdx.x;  // (TOF bin, plane) rank
+        const int64_t bq = q / n_planes;
+        const int64_t k = (q - bq * n_planes) * n_tof + bq;  // sinogram index within the line
+        const float v = q < bins_per_line ? count_y(y, dt, base + k) : 0.f;
+        const bool has = v > 0.f;
+        const uint64_t m = __ballot(has);
+        if (lane == 0) s_w[w] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int i = 0; i < nw; ++i) {
+            before += i < w ? s_w[i] : 0;
+            total += s_w[i];
+        }
+        if (has) {
+            const int rank = before + __popcll(m & ((1ull << lane) - 1ull));
+            const int plane = (int)(k / n_tof);
+            const RecGeo g = rec_geo<TOF>(a, c, L, a.planes[plane], (int)(k - (int64_t)plane * n_tof));
+            CountRec it;
+            it.is = (int16_t)g.is;
+            it.ie = (int16_t)g.ie;
+            it.pA = g.pA;
+            it.pB = g.pB;
+            it.zA = g.zA;
+            it.zB = g.zB;
+            it.me = (mult ? mult[(int64_t)blockIdx.x * n_planes + plane] : 1.f) * g.ell;
+            it.y = v;
+            it.add = add ? add[base + k] : 0.f;
+            items[out + rank] = it;
+        }
+        out += total;
+        __syncthreads();
+    }
+}
+
+// TOF weight W(d) from the LDS table, at table position pos = d / dx + NW/2:
+// linear interpolation between nodes; the position is clamped to the table,
+// whose end nodes are 0.
+__device__ __forceinline__ float tof_weight_at(const float2 *tab, float pos, float pos_max) {
+    pos = __builtin_amdgcn_fmed3f(pos, 0.f, pos_max);
+    const float2 t = tab[(int)pos];
+    return fmaf(__builtin_amdgcn_fractf(pos), t.y, t.x);
+}
+
 // Sum over the workgroup, the same value in every thread (wave sums by
 // shuffles, then the wave partials in a fixed order).
-__device__ __forceinline__ float block_sum_all(float v, float *red) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+__device__ __forceinline__ float2 block_sum_all(float2 v, float2 *red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        v.x += __shfl_xor(v.x, off, 64);
+        v.y += __shfl_xor(v.y, off, 64);
+    }
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    float t = 0.f;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    float2 t = make_float2(0.f, 0.f);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        t.x += red[w].x;
+        t.y += red[w].y;
+    }
     return t;
 }
 
@@ -194,6 +208,24 @@ __device__ __forceinline__ float block_sum_all(float v, float *red) {
 // value is then A[j] - B[j] + B[j - 1].  q is scaled by 2^30 / sum_bins |Q|
 // (Q the bin's factor mult y / ybar ell, TOF weights <= 1), so neither sum can
 // leave 31 bits.  Integer sums do not depend on the order of the adds.
+//
+// The gradient's share of a sample is -Q W: with every Q of a chunk >= 0 (the
+// case whenever x >= 0 and add > 0) the sheet accumulates +Q W, whose two
+// parts are both nonnegative and pack with no borrow, and the readout
+// negates; otherwise it accumulates the signed shares with the borrow of a
+// negative low word carried into the high one.
+__device__ __forceinline__ uint32_t round_pos(float q) {
+    // floor(q + 1/2) of a nonnegative q below 2^31, in one instruction
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(q));
+    return (uint32_t)r;
+}
+
+__device__ __forceinline__ void deposit_pos(unsigned long long *zr, int j, float q, float f) {
+    const uint32_t A = round_pos(q), B = round_pos(q * f);
+    atomicAdd(&zr[j], (unsigned long long)A | ((unsigned long long)B << 32));
+}
+
 __device__ __forceinline__ void deposit_packed(unsigned long long *zr, int j, float qs, float f) {
     const int A = (int)__builtin_rintf(qs);
     const int B = (int)__builtin_rintf(qs * f);
@@ -203,59 +235,95 @@ __device__ __forceinline__ void deposit_packed(unsigned long long *zr, int j, fl
 }
 
 // The two accumulators of a packed cell: the low word read as signed is A,
-// and (w - A) is exactly 2^32 B.
+// and (w - A) is exactly 2^32 B (signed shares); both words unsigned
+// (nonnegative shares).
+template <bool SIGNED>
 __device__ __forceinline__ void unpack_cell(unsigned long long w, long long &A, long long &B) {
-    const int lo = (int)(uint32_t)w;
-    A = lo;
-    B = ((long long)w - (long long)lo) >> 32;
+    if (SIGNED) {
+        const int lo = (int)(uint32_t)w;
+        A = lo;
+        B = ((long long)w - (long long)lo) >> 32;
+    } else {
+        A = (long long)(uint32_t)w;
+        B = (long long)(w >> 32);
+    }
 }
 
 // Spread the packed sheet over the two transaxial neighbours (the readout of
 // the FP64 sheet in the dense kernels, after unpacking).  A line whose bound
 // is not finite (a bin with ybar = 0) adds NaN to every cell it covers.
+template <bool SIGNED>
+__device__ __forceinline__ float packed_cell_value(const unsigned long long *Zu, int e, int zp, float inv_scale,
+                                                   bool finite) {
+    long long A, B, Ap, Bp = 0;
+    unpack_cell<SIGNED>(Zu[e], A, B);
+    if (zp > 0) unpack_cell<SIGNED>(Zu[e - 1], Ap, Bp);
+    const long long V = A - B + Bp;
+    return finite ? (float)(SIGNED ? V : -V) * inv_scale : __builtin_nanf("");
+}
+
+template <bool SIGNED>
 __device__ __forceinline__ void scatter_sheet_packed(const ProjArgs &a, const LineP &L, int nrow,
                                                      const unsigned long long *Zu, float inv_scale, bool finite) {
     const int rz = a.rz;
     float *Gout = L.axis ? a.G1 : a.G0;
     const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
-    for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
-        const int r = e / rz;
-        const int zp = e - r * rz;
-        long long A, B, Ap, Bp = 0;
-        unpack_cell(Zu[e], A, B);
-        if (zp > 0) unpack_cell(Zu[e - 1], Ap, Bp);
-        const long long V = A - B + Bp;
-        float val = (float)V * inv_scale;
-        if (!finite) val = __builtin_nanf("");
-        else if (V == 0) continue;
-        const int i = L.i_lo + r;
-        const float xa = fmaf((float)i, L.dxa, L.xa0);
-        const float jf = floorf(xa);
-        const float f = xa - jf;
-        const size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
-        const float a1 = val * f;
-        atomicAdd(&Gout[base], val - a1);
-        atomicAdd(&Gout[base + rz], a1);
+    if (rz <= (int)blockDim.x) {
+        const SheetWalk w = sheet_walk(rz);
+        if (!w.on) return;
+        for (int r = w.r0; r < nrow; r += w.R) {
+            const float val = packed_cell_value<SIGNED>(Zu, r * rz + w.zp, w.zp, inv_scale, finite);
+            if (val == 0.f) continue;
+            spread_cell(Gout, sheet_row(L, L.i_lo + r, other_stride, rz), w.zp, rz, val);
+        }
+    } else {
+        for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
+            const int r = e / rz;
+            const int zp = e - r * rz;
+            const float val = packed_cell_value<SIGNED>(Zu, e, zp, inv_scale, finite);
+            if (val == 0.f) continue;
+            spread_cell(Gout, sheet_row(L, L.i_lo + r, other_stride, rz), zp, rz, val);
+        }
     }
 }
+
+// Lanes per bin of a chunk of n_c bins: a power of two C <= 16, doubled while
+// the chunk's bins still fill the workgroup, so that lines with few bins keep
+// every wave busy.
+__device__ __forceinline__ int lanes_per_bin(int n_c) {
+    int C = 1;
+    while (C < 16 && n_c * (2 * C) <= (int)blockDim.x) C *= 2;
+    return C;
+}
+
+// Rows of the image sheet a thread loads in the prologue's batch (more rows,
+// if any, in later passes).
+constexpr int CNT_SHEET_ROWS = 12;
 
 // One workgroup per line with counts.  MODE M_GRAD: gradient sheets receive
 // -P^T [mult y / ybar]; M_OBJ: no gradient.  Both write the workgroup's FP64
 // sum of y log(y / ybar) when a.partial is set.
 //
+// Prologue: every load the line starts with is in flight at once (TOF table,
+// the image rows of the sheet, the thread's first bin and then its plane), so
+// that a workgroup waits for memory about twice per line before its samples.
+//
 // The line's bins are taken in chunks of at most c.q_cap.  Phase one walks
-// every bin of the chunk forward (ybar, the log term, Q = mult y / ybar ell,
-// kept in LDS); with M_GRAD, phase two walks them again and adds -Q W(t - t_b)
-// times the axial interpolation weights to the packed sheet, scaled by the
-// chunk's sum of |Q|.  A chunk's sheet is read out before the next starts.
+// every bin of the chunk forward (ybar, the log term, Q = mult y / ybar ell);
+// with M_GRAD, phase two walks them again and adds -Q W(t - t_b) times the
+// axial interpolation weights to the packed sheet, scaled by the chunk's sum
+// of |Q|.  When a chunk has at most one bin per lane group (the usual case),
+// its bin, geometry and Q stay in registers between the phases; otherwise Q
+// goes through LDS and phase two reloads the bins.  A chunk's sheet is read
+// out before the next starts.
 template <bool TOF, int MODE>
 __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs c) {
     extern __shared__ float4 smem4[];
     float *smem = reinterpret_cast<float *>(smem4);
-    __shared__ float red[CNT_BLOCK / 64];
+    __shared__ float2 red[CNT_BLOCK / 64];
     constexpr bool NEED_Z = MODE == M_GRAD;
-    const int line = c.lines[blockIdx.x];
-    const LineP L = a.lines[line];
+    const CountLine desc = c.desc[blockIdx.x];
+    const LineP &L = desc.L;
     const int nrow = L.i_hi - L.i_lo + 1;
     const int rz = a.rz;
     const int sheet = (a.rows_max * rz + 3) & ~3;
@@ -263,90 +331,169 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     unsigned long long *Zu = reinterpret_cast<unsigned long long *>(smem + sheet);
     float2 *tab = reinterpret_cast<float2 *>(smem + (NEED_Z ? 3 : 1) * sheet);
     float *Qs = smem + (NEED_Z ? 3 : 1) * sheet + (TOF ? 2 * NW_TAB : 0);
+    const int64_t i0 = desc.i0, i1 = desc.i0 + desc.n;
+    const CountRec none{1, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // no rows, no count
+
+    // ---- prologue: issue every load, then store
+    static_assert(NW_TAB % CNT_BLOCK == 0, "the table load assumes CNT_BLOCK divides NW_TAB");
+    float2 wt[TOF ? NW_TAB / CNT_BLOCK : 1];
     if (TOF) {
-        // (all of a thread's table loads in flight at once; the kernel runs
-        // with CNT_BLOCK threads)
-        static_assert(NW_TAB % CNT_BLOCK == 0, "the table load assumes CNT_BLOCK divides NW_TAB");
-        float2 w[NW_TAB / CNT_BLOCK];
 #pragma unroll
-        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) w[u] = c.wtab[threadIdx.x + u * CNT_BLOCK];
-#pragma unroll
-        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) tab[threadIdx.x + u * CNT_BLOCK] = w[u];
+        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) wt[u] = c.wtab[threadIdx.x + u * CNT_BLOCK];
     }
-    if (nrow > 0) build_sheets<true, NEED_Z>(a, L, nrow, X, reinterpret_cast<double *>(Zu));
+    const int64_t c1_first = i0 + c.q_cap < i1 ? i0 + c.q_cap : i1;
+    const int C_first = lanes_per_bin((int)(c1_first - i0));
+    const int64_t it_first = i0 + threadIdx.x / C_first;
+    const bool act_first = it_first < c1_first;
+    const CountRec e_first = act_first ? c.items[it_first] : none;
+    // image sheet rows (the column walk of build_sheets; the fallback for
+    // rz > blockDim and the rows past the batch are built after the stores)
+    const float *T = L.axis ? a.T1 : a.T0;
+    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    const bool walk = rz <= (int)blockDim.x;  // uniform
+    const SheetWalk sw = sheet_walk(rz);
+    float t0[CNT_SHEET_ROWS], t1[CNT_SHEET_ROWS], tf[CNT_SHEET_ROWS];
+#pragma unroll
+    for (int u = 0; u < CNT_SHEET_ROWS; ++u) {
+        const int r = sw.r0 + u * sw.R;
+        t0[u] = t1[u] = tf[u] = 0.f;
+        if (walk && sw.on && r < nrow) {
+            const SheetRow sr = sheet_row(L, L.i_lo + r, other_stride, rz);
+            tf[u] = sr.f;
+            const float *src = T + sr.base + sw.zp;
+            t0[u] = src[0];
+            t1[u] = src[rz];
+        }
+    }
+    if (TOF) {
+#pragma unroll
+        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) tab[threadIdx.x + u * CNT_BLOCK] = wt[u];
+    }
+    if (walk) {
+        if (sw.on) {
+#pragma unroll
+            for (int u = 0; u < CNT_SHEET_ROWS; ++u) {
+                const int r = sw.r0 + u * sw.R;
+                if (r < nrow) X[r * rz + sw.zp] = fmaf(tf[u], t1[u] - t0[u], t0[u]);
+            }
+            for (int r = sw.r0 + CNT_SHEET_ROWS * sw.R; r < nrow; r += sw.R) {
+                const SheetRow sr = sheet_row(L, L.i_lo + r, other_stride, rz);
+                const float *src = T + sr.base + sw.zp;
+                X[r * rz + sw.zp] = fmaf(sr.f, src[rz] - src[0], src[0]);
+            }
+        }
+        if (NEED_Z)
+            for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) Zu[e] = 0ull;
+    } else if (nrow > 0) {
+        build_sheets<true, NEED_Z>(a, L, nrow, X, reinterpret_cast<double *>(Zu));
+    }
     __syncthreads();
 
     double kl = 0.0;
-    const int64_t i0 = c.line_off[line], i1 = c.line_off[line + 1];
     const float umax = (float)(a.nz + PADZ);
+    bool pre = true;  // the prologue holds the first round's bins (uniform)
     // (a line that misses the image still has bins with counts: ybar = add there,
     // and its y log(y / add) enters the sum; its sample ranges are empty)
     for (int64_t c0 = i0; c0 < i1; c0 += c.q_cap) {
         const int64_t c1 = c0 + c.q_cap < i1 ? c0 + c.q_cap : i1;
-        // C lanes per bin (a power of two, consecutive lanes of one wave) take
-        // every C-th sample of its window; C grows while the chunk's bins
-        // still fill the workgroup, so that lines with few bins keep every
-        // wave busy
+        // C lanes per bin (consecutive lanes of one wave) take every C-th
+        // sample of its window
         const int n_c = (int)(c1 - c0);
-        int C = 1;
-        while (C < 16 && n_c * (2 * C) <= (int)blockDim.x) C *= 2;
+        const int C = lanes_per_bin(n_c);
         const int ch = threadIdx.x & (C - 1);
         const int nslot = blockDim.x / C;
+        const bool one_round = n_c <= nslot;  // uniform
         const float fC = (float)C;
-        float qabs = 0.f;
+        float qabs = 0.f, qneg = 0.f;
+        // one-round chunks: the thread's bin and factor for phase two
+        CountRec ek = none;
+        float Qk = 0.f;
         for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
             // every lane runs every round: the forward sums are added across
             // the C lanes of a bin by shuffles
             const int64_t it = it0 + threadIdx.x / C;
             const bool act = it < c1;
-            const CountItem e = act ? c.items[it] : CountItem{0u, 0.f, 1.f, 0.f};
-            const RecGeo g = rec_geo<TOF>(a, c, L, e, act);
+            CountRec e;
+            if (pre) {
+                e = e_first;
+                pre = false;
+            } else {
+                e = act ? c.items[it] : none;
+            }
             // rows as floats (exact integers): no conversion per sample
-            const float fis = (float)(g.is + ch), fie = (float)g.ie;
+            const float fis = (float)(e.is + ch), fie = (float)e.ie;
             float s = 0.f;
-            const float *xr = X + (g.is + ch - L.i_lo) * rz;
+            const float *xr = X + (e.is + ch - L.i_lo) * rz;
             for (float fi = fis; fi <= fie; fi += fC, xr += C * rz) {
-                const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                const float u = __builtin_amdgcn_fmed3f(fmaf(fi, e.zA, e.zB), 0.f, umax);
                 const int j = (int)u;
                 const float x0 = xr[j], x1 = xr[j + 1];
                 const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
-                s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max), v, s) : s + v;
+                s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, e.pA, e.pB), c.pos_max), v, s) : s + v;
             }
+            // (every lane of the bin ends with the bin's sum)
             for (int o = 1; o < C; o <<= 1) s += __shfl_xor(s, o, 64);
-            if (!act || ch != 0) continue;
-            const float ybar = fmaf(e.mult, s * g.ell, e.add);
+            const float ybar = fmaf(e.me, s, e.add);
             // (the FP64 logarithm only when the sums are wanted)
-            if (a.partial) kl += (double)e.y * log((double)e.y / (double)ybar);
+            if (a.partial && act && ch == 0) kl += (double)e.y * log((double)e.y / (double)ybar);
             if (NEED_Z) {
-                const float Q = e.mult * e.y * __builtin_amdgcn_rcpf(ybar) * g.ell;
-                Qs[it - c0] = Q;
-                qabs += fabsf(Q);
+                const float Q = act ? e.me * e.y * __builtin_amdgcn_rcpf(ybar) : 0.f;
+                if (ch == 0) {
+                    qabs += fabsf(Q);
+                    qneg += Q < 0.f ? 1.f : 0.f;
+                }
+                if (one_round) {
+                    ek = e;
+                    Qk = Q;
+                } else if (act && ch == 0) {
+                    Qs[it - c0] = Q;
+                }
             }
         }
         if (!NEED_Z) continue;  // uniform
         // (the barrier inside also publishes Qs)
-        const float bound = block_sum_all(qabs, red);
+        const float2 tot = block_sum_all(make_float2(qabs, qneg), red);
+        const float bound = tot.x;
         const bool finite = bound < INFINITY;  // false for inf and NaN
+        const bool sgn = tot.y > 0.f || c.force_signed;  // some Q < 0 (uniform)
         const float scale = finite && bound > 0.f ? 0x1p30f / bound : 0.f;
         if (scale > 0.f) {
             for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
                 const int64_t it = it0 + threadIdx.x / C;
                 const bool act = it < c1;
-                const CountItem e = act ? c.items[it] : CountItem{0u, 0.f, 1.f, 0.f};
-                const RecGeo g = rec_geo<TOF>(a, c, L, e, act);
-                const float qsc = act ? -Qs[act ? (int)(it - c0) : 0] * scale : 0.f;  // (index < q_cap)
+                CountRec g;
+                float qsc;
+                if (one_round) {
+                    g = ek;
+                    qsc = Qk * scale;
+                } else {
+                    g = act ? c.items[it] : none;
+                    qsc = act ? Qs[act ? (int)(it - c0) : 0] * scale : 0.f;  // (index < q_cap)
+                }
                 const float fis = (float)(g.is + ch), fie = (float)g.ie;
                 unsigned long long *zr = Zu + (g.is + ch - L.i_lo) * rz;
-                for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
-                    const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
-                    const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
-                    deposit_packed(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
+                if (!sgn) {
+                    for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                        const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
+                        const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                        deposit_pos(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
+                    }
+                } else {
+                    for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                        const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
+                        const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                        deposit_packed(zr, (int)u, -qw, __builtin_amdgcn_fractf(u));
+                    }
                 }
             }
         }
         __syncthreads();
-        if (nrow > 0 && (scale > 0.f || !finite))
-            scatter_sheet_packed(a, L, nrow, Zu, finite ? 1.f / scale : 0.f, finite);
+        if (nrow > 0 && (scale > 0.f || !finite)) {
+            if (sgn)
+                scatter_sheet_packed<true>(a, L, nrow, Zu, finite ? 1.f / scale : 0.f, finite);
+            else
+                scatter_sheet_packed<false>(a, L, nrow, Zu, finite ? 1.f / scale : 0.f, finite);
+        }
         if (c1 < i1) {
             // the next chunk starts from a zero sheet (after every readout)
             __syncthreads();
@@ -355,6 +502,20 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
         }
     }
     if (a.partial) block_sums(kl, kl, a.partial, false);
+}
+
+// Descriptors of a launch's lines (geometry and item ranges), one per line.
+__global__ void k_counts_desc(const int *__restrict__ lines, int n, const LineP *__restrict__ geo,
+                              const int64_t *__restrict__ line_off, CountLine *__restrict__ desc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int l = lines[k];
+    CountLine d;
+    d.L = geo[l];
+    d.i0 = line_off[l];
+    d.n = (int32_t)(line_off[l + 1] - line_off[l]);
+    d.line = l;
+    desc[k] = d;
 }
 
 template <bool TOF, int MODE>
@@ -403,14 +564,9 @@ int counts_blocks(const pet_counts_s *cs, int subset) {
     return (int)(cs->lines_off[row + 1] - cs->lines_off[row]);
 }
 
-hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *cs, int mode, int subset, const ProjArgs &a,
-                              hipStream_t s) {
-    const int nblk = counts_blocks(cs, subset);
-    if (nblk == 0) return hipSuccess;
+// The TOF table's constants (and the TOF bin count) of a geometry.
+static CountArgs count_args(const pet_geom_s *g) {
     CountArgs c{};
-    c.items = cs->items;
-    c.line_off = cs->line_off;
-    c.lines = cs->lines + cs->lines_off[subset < 0 ? cs->n_subsets : subset];
     c.wtab = g->wtab;
     c.nw = NW_TAB;
     c.n_tof = g->d.n_tof;
@@ -418,7 +574,18 @@ hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *cs, int mode, i
     c.inv_dx = (float)(NW_TAB / (2.0 * g->wD));
     c.pos0 = (float)(NW_TAB / 2);
     c.pos_max = (float)NW_TAB - 1e-3f;
+    return c;
+}
+
+hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *cs, int mode, int subset, const ProjArgs &a,
+                              hipStream_t s) {
+    const int nblk = counts_blocks(cs, subset);
+    if (nblk == 0) return hipSuccess;
+    CountArgs c = count_args(g);
+    c.items = cs->items;
+    c.desc = cs->desc + cs->lines_off[subset < 0 ? cs->n_subsets : subset];
     c.q_cap = mode != M_GRAD ? (1 << 30) : (g->flags & PET_SMALL_CHUNKS) ? std::min(16, counts_q_cap(g)) : counts_q_cap(g);
+    c.force_signed = (g->flags & PET_SIGNED_SHEETS) != 0;
     const size_t lds = counts_lds_bytes(g, mode);
     const bool tof = g->d.n_tof > 1;
     const int threads = CNT_BLOCK;
@@ -486,11 +653,18 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
     for (int l = 0; l < n_lines; ++l) off[l + 1] = off[l] + cnt[l];
     c->n_items = off[n_lines];
     if (e == hipSuccess) e = hipMalloc(&c->line_off, sizeof(int64_t) * (n_lines + 1));
-    if (e == hipSuccess) e = hipMalloc(&c->items, sizeof(CountItem) * std::max<int64_t>(c->n_items, 1));
+    if (e == hipSuccess) e = hipMalloc(&c->items, sizeof(CountRec) * std::max<int64_t>(c->n_items, 1));
     if (e == hipSuccess) e = hipMemcpy(c->line_off, off.data(), sizeof(int64_t) * (n_lines + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess && c->n_items > 0)
-        hipLaunchKernelGGL(k_counts_fill, dim3(n_lines), dim3(256), 0, 0, y, y_dtype, add, mult, bpl, g->d.n_tof,
-                           g->n_planes, c->line_off, c->items);
+    if (e == hipSuccess && c->n_items > 0) {
+        const ProjArgs pa = geom_proj_args(g);
+        const CountArgs ca = count_args(g);
+        if (g->d.n_tof > 1)
+            hipLaunchKernelGGL(k_counts_fill<true>, dim3(n_lines), dim3(256), 0, 0, y, y_dtype, add, mult, bpl,
+                               c->line_off, pa, ca, c->items);
+        else
+            hipLaunchKernelGGL(k_counts_fill<false>, dim3(n_lines), dim3(256), 0, 0, y, y_dtype, add, mult, bpl,
+                               c->line_off, pa, ca, c->items);
+    }
     if (e == hipSuccess) e = hipGetLastError();
     // per subset (then all views): its lines with counts, most counts first,
     // and the sums of y and add over all its bins
@@ -524,6 +698,13 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
     if (e == hipSuccess) e = hipMalloc(&c->lines, sizeof(int) * std::max<size_t>(lines.size(), 1));
     if (e == hipSuccess && !lines.empty())
         e = hipMemcpy(c->lines, lines.data(), sizeof(int) * lines.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&c->desc, sizeof(CountLine) * std::max<size_t>(lines.size(), 1));
+    if (e == hipSuccess && !lines.empty()) {
+        const int nl = (int)lines.size();
+        hipLaunchKernelGGL(k_counts_desc, dim3((nl + 255) / 256), dim3(256), 0, 0, c->lines, nl, g->lines,
+                           c->line_off, c->desc);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (d_cnt) (void)hipFree(d_cnt);
     if (d_ys) (void)hipFree(d_ys);
@@ -540,7 +721,7 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
 extern "C" pet_status pet_counts_destroy(pet_counts c) {
     if (!c) return PET_OK;
     (void)hipDeviceSynchronize();
-    void *ptrs[] = {c->items, c->line_off, c->lines};
+    void *ptrs[] = {c->items, c->line_off, c->lines, c->desc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;

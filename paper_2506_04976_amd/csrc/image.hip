@@ -214,6 +214,73 @@ __device__ __forceinline__ void rdp_sums(const RdpArgs &a, int v, int ix, int iy
     }
 }
 
+// What the flags ask for at one voxel once its RDP sums are known (gradient,
+// Hessian diagonal, value, preconditioner, the fused estimator and step).
+// gi: the sampled subset's data gradient at the voxel (regular iterations).
+// Returns the new iterate (xi when no step is taken).
+template <int F>
+__device__ __forceinline__ float rdp_finish(const RdpArgs &a, int v, float xi, float g, float h, float sv, float gi,
+                                            double &val, double &pq, double &qdq) {
+    const float bg = a.beta * g;
+    const float bh = a.beta * h;
+    if (F & R_GRAD_OUT) a.grad[v] = bg;
+    if (F & R_HESS_OUT) a.hess[v] = bh;
+    if (F & R_VALUE) val = 0.5 * (double)a.beta * (double)sv;
+    float Dv = 0.f;
+    if (F & R_PRECOND) {
+        const float xd = xi + a.delta;
+        const float den = a.sens[v] + a.alpha * bh * xd;
+        Dv = den != 0.f ? xd / den : 0.f;
+        a.D[v] = Dv;
+    } else if (F & R_UPDATE) {
+        Dv = a.D[v];
+    }
+    float xn = xi;
+    if (F & R_UPDATE) {
+        float est;
+        if (F & R_SAGA) {
+            // J_i = D_i + (beta / n) S, eq. (template); the table holds
+            // grad J_i at the iterate where subset i was last sampled
+            if (F & R_SNAPSHOT) {
+                est = (float)a.table_sum[v];  // first iteration: table just filled at x
+            } else {
+                const float ji = gi + bg / a.n_sub;
+                const float ti = a.table_i[v];
+                est = fmaf(a.n_sub, ji - ti, (float)a.table_sum[v]);
+                a.table_sum[v] += (double)ji - (double)ti;
+                a.table_i[v] = ji;
+            }
+        } else if (F & R_SGD) {
+            est = fmaf(a.n_sub, gi, bg);
+        } else if (F & R_SNAPSHOT) {
+            est = (float)a.ghat[v] + bg;
+        } else {
+            est = fmaf(a.n_sub, gi - a.ghat_i[v], (float)a.ghat[v]) + bg;
+        }
+        if (F & R_EST_OUT) a.est_out[v] = est;
+        if (F & R_BB_DOT) {
+            // p = x - x_snap_prev, q = est - g_prev (both full gradients)
+            const double p = (double)xi - (double)a.x_snap[v];
+            const double q = (double)est - (double)a.g_prev[v];
+            pq = p * q;
+            qdq = q * q * (double)Dv;
+        }
+        if (F & (R_BB_STORE | R_BB_DOT)) a.g_prev[v] = est;
+        if (!(F & R_BB_DOT)) {
+            const float tau = a.tau_bb ? fminf(a.tau, (float)*a.tau_bb) : a.tau;
+            xn = fmaxf(0.f, fmaf(-tau * Dv, est, xi));
+            a.x_out[v] = xn;
+        }
+    }
+    return xn;
+}
+
+// Whether the estimator of these flags reads the sampled subset's gradient.
+template <int F>
+constexpr bool reads_gi() {
+    return (F & R_UPDATE) && !(F & R_SNAPSHOT);
+}
+
 // One thread per voxel: the RDP sums, then what the flags ask for (gradient,
 // Hessian diagonal, value, preconditioner, the fused estimator and step).
 // (32-bit voxel indices: images hold fewer than 2^31 voxels)
@@ -234,55 +301,7 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
             rdp_sums<F, true>(a, v, ix, iy, iz, xi, g, h, sv);
         else
             rdp_sums<F, false>(a, v, ix, iy, iz, xi, g, h, sv);
-        const float bg = a.beta * g;
-        const float bh = a.beta * h;
-        if (F & R_GRAD_OUT) a.grad[v] = bg;
-        if (F & R_HESS_OUT) a.hess[v] = bh;
-        if (F & R_VALUE) val = 0.5 * (double)a.beta * (double)sv;
-        float Dv = 0.f;
-        if (F & R_PRECOND) {
-            const float xd = xi + a.delta;
-            const float den = a.sens[v] + a.alpha * bh * xd;
-            Dv = den != 0.f ? xd / den : 0.f;
-            a.D[v] = Dv;
-        } else if (F & R_UPDATE) {
-            Dv = a.D[v];
-        }
-        if (F & R_UPDATE) {
-            float est;
-            if (F & R_SAGA) {
-                // J_i = D_i + (beta / n) S, eq. (template); the table holds
-                // grad J_i at the iterate where subset i was last sampled
-                if (F & R_SNAPSHOT) {
-                    est = (float)a.table_sum[v];  // first iteration: table just filled at x
-                } else {
-                    const float ji = a.gi[v] + bg / a.n_sub;
-                    const float ti = a.table_i[v];
-                    est = fmaf(a.n_sub, ji - ti, (float)a.table_sum[v]);
-                    a.table_sum[v] += (double)ji - (double)ti;
-                    a.table_i[v] = ji;
-                }
-            } else if (F & R_SGD) {
-                est = fmaf(a.n_sub, a.gi[v], bg);
-            } else if (F & R_SNAPSHOT) {
-                est = (float)a.ghat[v] + bg;
-            } else {
-                est = fmaf(a.n_sub, a.gi[v] - a.ghat_i[v], (float)a.ghat[v]) + bg;
-            }
-            if (F & R_EST_OUT) a.est_out[v] = est;
-            if (F & R_BB_DOT) {
-                // p = x - x_snap_prev, q = est - g_prev (both full gradients)
-                const double p = (double)xi - (double)a.x_snap[v];
-                const double q = (double)est - (double)a.g_prev[v];
-                pq = p * q;
-                qdq = q * q * (double)Dv;
-            }
-            if (F & (R_BB_STORE | R_BB_DOT)) a.g_prev[v] = est;
-            if (!(F & R_BB_DOT)) {
-                const float tau = a.tau_bb ? fminf(a.tau, (float)*a.tau_bb) : a.tau;
-                a.x_out[v] = fmaxf(0.f, fmaf(-tau * Dv, est, xi));
-            }
-        }
+        (void)rdp_finish<F>(a, v, xi, g, h, sv, reads_gi<F>() ? a.gi[v] : 0.f, val, pq, qdq);
     }
     if (F & R_BB_DOT) {
         __shared__ double red2[2][IMG_BLOCK / 64];
@@ -315,6 +334,130 @@ __global__ void __launch_bounds__(IMG_BLOCK) k_rdp(RdpArgs a) {
             for (int w = 0; w < IMG_BLOCK / 64; ++w) s += red[w];
             a.partial[blockIdx.x] = s;
         }
+    }
+}
+
+// ---- the step of an iteration fused with the sheet conversions -------------
+// Workgroup: the voxels of one tile (TT consecutive x, one y, every z), as in
+// the sheet transposes.  It
+//  * sums the subset's data gradient from the two gradient sheets into LDS
+//    (reads z-contiguous) and clears the cells it read, so that the next
+//    subset's line kernels start from zero sheets;
+//  * stages the iterate with a one-voxel halo (three y rows, TT + 2 x, nz + 2 z)
+//    in LDS for the 26-neighbour RDP sums;
+//  * takes the step of rdp_finish for every voxel of the tile;
+//  * writes the new iterate as an image and, through LDS, as the two
+//    transposed image sheets that the next subset's line kernels read.
+// Without a kappa image and a resolution model; no block reductions.
+constexpr int STEP_BLOCK = 512;
+
+__host__ __device__ constexpr int halo_elems(int nz) { return 3 * (nz + 2) * (TT + 2); }
+
+template <int F>
+__global__ void __launch_bounds__(STEP_BLOCK) k_step_tile(RdpArgs a, float *__restrict__ G0, float *__restrict__ G1,
+                                                         float *__restrict__ T0, float *__restrict__ T1, int rz) {
+    extern __shared__ float lds[];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    float *halo = lds;                          // [3][nz + 2][TT + 2]
+    float *tile = lds + halo_elems(nz);         // [nz][TT + 1]: gradient in, new iterate out
+    const int x0 = blockIdx.x * TT, iy = blockIdx.y;
+    const int w = min(TT, nx - x0);
+    const int hz = nz + 2, hx = TT + 2;
+    // halo of the iterate (outside the grid: 0, masked out by the sums);
+    // TILE_UNROLL loads per thread in flight before their LDS writes
+    const int nh = 3 * hz * hx;
+    for (int e0 = threadIdx.x; e0 < nh; e0 += TILE_UNROLL * blockDim.x) {
+        float val[TILE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < TILE_UNROLL; ++u) {
+            const int e = e0 + u * blockDim.x;
+            const int dy = e / (hz * hx);
+            const int rem = e - dy * hz * hx;
+            const int zz = rem / hx;
+            const int z = zz - 1, x = x0 + rem - zz * hx - 1, y = iy + dy - 1;
+            val[u] = e < nh && y >= 0 && y < ny && z >= 0 && z < nz && x >= 0 && x < nx
+                         ? a.x[((size_t)z * ny + y) * nx + x]
+                         : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < TILE_UNROLL; ++u) {
+            const int e = e0 + u * blockDim.x;
+            if (e < nh) halo[e] = val[u];
+        }
+    }
+    if (reads_gi<F>()) {
+        // the subset's gradient, then zero cells for the next subset
+        for (int e0 = threadIdx.x; e0 < w * nz; e0 += TILE_UNROLL * blockDim.x) {
+            float ga[TILE_UNROLL], gb[TILE_UNROLL];
+#pragma unroll
+            for (int u = 0; u < TILE_UNROLL; ++u) {
+                const int e = e0 + u * blockDim.x;
+                const int xx = e / nz, z = e - xx * nz;
+                const int ix = x0 + xx;
+                ga[u] = gb[u] = 0.f;
+                if (e < w * nz) {
+                    ga[u] = G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ];
+                    gb[u] = G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TILE_UNROLL; ++u) {
+                const int e = e0 + u * blockDim.x;
+                if (e >= w * nz) continue;
+                const int xx = e / nz, z = e - xx * nz;
+                const int ix = x0 + xx;
+                tile[z * (TT + 1) + xx] = ga[u] + gb[u];
+                G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] = 0.f;
+                G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ] = 0.f;
+            }
+        }
+    }
+    __syncthreads();
+    const int nxy = nx * ny;
+    for (int e = threadIdx.x; e < nz * TT; e += blockDim.x) {
+        const int z = e / TT, xx = e - z * TT;
+        if (xx >= w) continue;
+        const int ix = x0 + xx;
+        const int v = (z * ny + iy) * nx + ix;
+        // RDP sums over the 26 neighbours from the halo (rdp_sums with LDS reads)
+        const float *hc = halo + (1 * hz + z + 1) * hx + xx + 1;
+        const float xi = *hc;
+        const float xe = xi + a.eps;
+        float g = 0.f, h = 0.f, sv = 0.f;
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+            const bool oz = z + dz - 1 >= 0 && z + dz - 1 < nz;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const bool ozy = oz && iy + dy - 1 >= 0 && iy + dy - 1 < ny;
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    if (dz == 1 && dy == 1 && dx == 1) continue;
+                    const bool in = ozy && ix + dx - 1 >= 0 && ix + dx - 1 < nx;
+                    const float xj = halo[(dy * hz + z + dz) * hx + xx + dx];
+                    const float wk = a.w.w[dz * 9 + dy * 3 + dx];
+                    const float d = xi - xj;
+                    const float phi = fmaf(a.gamma, fabsf(d), xe + xj);
+                    const float r = in ? __builtin_amdgcn_rcpf(phi) : 0.f;
+                    const float c = fmaf(2.f, xj, a.eps);
+                    const float r2 = r * r;
+                    g = fmaf(wk * d * (phi + c), r2, g);
+                    if (F & (R_HESS_OUT | R_PRECOND)) h = fmaf(2.f * wk * c * c, r2 * r, h);
+                }
+            }
+        }
+        (void)nxy;
+        double val = 0.0, pq = 0.0, qdq = 0.0;
+        const float gi = reads_gi<F>() ? tile[z * (TT + 1) + xx] : 0.f;
+        tile[z * (TT + 1) + xx] = rdp_finish<F>(a, v, xi, g, h, sv, gi, val, pq, qdq);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
+        const int xx = e / nz, z = e - xx * nz;
+        const float val = tile[z * (TT + 1) + xx];
+        const int ix = x0 + xx;
+        T0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ] = val;
+        T1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] = val;
     }
 }
 
@@ -708,6 +851,62 @@ hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *ka
         case 5: return rdp_launch<R_PRECOND | R_UPDATE | R_EST_OUT>(a, g->n_vox, s);
         case 6: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT>(a, g->n_vox, s);
         default: return rdp_launch<R_PRECOND | R_UPDATE | R_SNAPSHOT | R_EST_OUT>(a, g->n_vox, s);
+    }
+}
+
+template <int F>
+hipError_t step_tile_launch(const pet_geom_s *g, const RdpArgs &a, hipStream_t s) {
+    const int nz = g->d.nz;
+    const size_t lds = sizeof(float) * ((size_t)halo_elems(nz) + (size_t)nz * (TT + 1));
+    hipLaunchKernelGGL((k_step_tile<F>), tile_grid(g), dim3(STEP_BLOCK), lds, s, a, g->G0, g->G1, g->T0, g->T1,
+                       nz + 2 * PADZ);
+    return hipGetLastError();
+}
+
+// Whether the fused step (k_step_tile) serves a handle: no resolution model
+// (the sheets then hold G x) and a tile that fits the default LDS.
+bool step_tile_ok(const pet_geom_s *g) {
+    const size_t lds = sizeof(float) * ((size_t)halo_elems(g->d.nz) + (size_t)g->d.nz * (TT + 1));
+    return g->psf_passes == 0 && lds <= 64 * 1024;
+}
+
+// SVRG step of one iteration fused with the sheet conversions (k_step_tile):
+// regular iterations read the sampled subset's data gradient from the
+// handle's gradient sheets and clear them; every iteration writes x_out and
+// the handle's image sheets of x_out.  bb_store: keep the snapshot's full
+// gradient in g_prev.  No kappa image; the caller checks step_tile_ok.
+hipError_t launch_svrg_step_tile(const pet_geom_s *g, const float *x, const float *w27, float beta, float gamma,
+                                 float eps, int update_pc, const float *sens, float alpha, float delta, float *D,
+                                 int snapshot, const float *ghat_i, const double *ghat, float w, float tau,
+                                 const double *tau_bb, int bb_store, float *g_prev, float *x_out, hipStream_t s) {
+    RdpArgs a{};
+    a.x = x;
+    for (int i = 0; i < 27; ++i) a.w.w[i] = w27[i];
+    a.beta = beta;
+    a.gamma = gamma;
+    a.eps = eps;
+    a.nx = g->d.nx;
+    a.ny = g->d.ny;
+    a.nz = g->d.nz;
+    a.sens = sens;
+    a.alpha = alpha;
+    a.delta = delta;
+    a.D = D;
+    a.ghat_i = ghat_i;
+    a.ghat = ghat;
+    a.n_sub = w;
+    a.tau = tau;
+    a.tau_bb = tau_bb;
+    a.x_out = x_out;
+    a.g_prev = g_prev;
+    const int code = (update_pc ? 1 : 0) | (snapshot ? 2 : 0) | (snapshot && bb_store ? 4 : 0);
+    switch (code) {
+        case 0: return step_tile_launch<R_UPDATE>(g, a, s);
+        case 1: return step_tile_launch<R_UPDATE | R_PRECOND>(g, a, s);
+        case 2: return step_tile_launch<R_UPDATE | R_SNAPSHOT>(g, a, s);
+        case 3: return step_tile_launch<R_UPDATE | R_SNAPSHOT | R_PRECOND>(g, a, s);
+        case 6: return step_tile_launch<R_UPDATE | R_SNAPSHOT | R_BB_STORE>(g, a, s);
+        default: return step_tile_launch<R_UPDATE | R_SNAPSHOT | R_PRECOND | R_BB_STORE>(g, a, s);
     }
 }
 

@@ -30,13 +30,48 @@ __device__ __forceinline__ void z_clip(const LineP &L, const PlaneP &P, int nz, 
     }
 }
 
+// Sheet cells (row r, padded axial position zp) are dealt to the threads of
+// a workgroup by column: thread t keeps zp = t mod rz and takes rows
+// t / rz, t / rz + R, ... with R = blockDim / rz (the threads past R rz idle).
+// No division per cell; needs rz <= blockDim (else one cell per thread and
+// pass, with a division each).
+struct SheetWalk {
+    int r0, zp, R;
+    bool on;
+};
+
+__device__ __forceinline__ SheetWalk sheet_walk(int rz) {
+    SheetWalk w;
+    w.R = (int)blockDim.x / rz;
+    w.r0 = (int)threadIdx.x / rz;
+    w.zp = (int)threadIdx.x - w.r0 * rz;
+    w.on = w.r0 < w.R;
+    return w;
+}
+
+// Row i of a line: the transposed image row it interpolates, at the
+// transaxial position xa = i dxa + xa0 (cell jf, fraction f).
+struct SheetRow {
+    size_t base;  // offset of (i, jf + PADA, 0) in the transposed image
+    float f;
+};
+
+__device__ __forceinline__ SheetRow sheet_row(const LineP &L, int i, size_t other_stride, int rz) {
+    SheetRow s;
+    const float xa = fmaf((float)i, L.dxa, L.xa0);
+    const float jf = floorf(xa);
+    s.f = xa - jf;
+    s.base = (size_t)i * other_stride + (size_t)(((int)jf + PADA) * rz);
+    return s;
+}
+
 // Block prologue: image sheet X (transaxial interpolation of the transposed
 // image) and / or zeroed gradient sheet Z.  Z accumulates in FP64: LDS FP64
 // atomic adds run at full rate on gfx950, FP32 ones do not.
-// The loads of SHEET_UNROLL elements per thread are issued before any of them
-// is used, so that a workgroup waits for memory a few times per line rather
-// than once per element it builds.
-constexpr int SHEET_UNROLL = 4;
+// The loads of SHEET_UNROLL rows per thread are issued before any of them is
+// used, so that a workgroup waits for memory a few times per line rather than
+// once per element it builds.
+constexpr int SHEET_UNROLL = 8;
 
 template <bool NEED_X, bool NEED_Z>
 __device__ __forceinline__ void build_sheets(const ProjArgs &a, const LineP &L, int nrow, float *X, double *Z) {
@@ -45,34 +80,49 @@ __device__ __forceinline__ void build_sheets(const ProjArgs &a, const LineP &L, 
     if (NEED_X) {
         const float *T = L.axis ? a.T1 : a.T0;
         const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
-        const int step = (int)blockDim.x;
-        for (int e0 = threadIdx.x; e0 < n; e0 += SHEET_UNROLL * step) {
-            float t0[SHEET_UNROLL], t1[SHEET_UNROLL], f[SHEET_UNROLL];
+        if (rz <= (int)blockDim.x) {
+            const SheetWalk w = sheet_walk(rz);
+            if (w.on) {
+                for (int rb = w.r0; rb < nrow; rb += SHEET_UNROLL * w.R) {
+                    float t0[SHEET_UNROLL], t1[SHEET_UNROLL], f[SHEET_UNROLL];
 #pragma unroll
-            for (int u = 0; u < SHEET_UNROLL; ++u) {
-                const int e = e0 + u * step;
-                t0[u] = t1[u] = f[u] = 0.f;
-                if (e < n) {
-                    const int r = e / rz;
-                    const int zp = e - r * rz;
-                    const int i = L.i_lo + r;
-                    const float xa = fmaf((float)i, L.dxa, L.xa0);
-                    const float jf = floorf(xa);
-                    f[u] = xa - jf;
-                    const size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
-                    t0[u] = T[base];
-                    t1[u] = T[base + rz];
+                    for (int u = 0; u < SHEET_UNROLL; ++u) {
+                        const int r = rb + u * w.R;
+                        t0[u] = t1[u] = f[u] = 0.f;
+                        if (r < nrow) {
+                            const SheetRow sr = sheet_row(L, L.i_lo + r, other_stride, rz);
+                            f[u] = sr.f;
+                            const float *src = T + sr.base + w.zp;
+                            t0[u] = src[0];
+                            t1[u] = src[rz];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < SHEET_UNROLL; ++u) {
+                        const int r = rb + u * w.R;
+                        if (r < nrow) X[r * rz + w.zp] = fmaf(f[u], t1[u] - t0[u], t0[u]);
+                    }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < SHEET_UNROLL; ++u) {
-                const int e = e0 + u * step;
-                if (e < n) X[e] = fmaf(f[u], t1[u] - t0[u], t0[u]);
+        } else {
+            for (int e = threadIdx.x; e < n; e += blockDim.x) {
+                const int r = e / rz;
+                const int zp = e - r * rz;
+                const SheetRow sr = sheet_row(L, L.i_lo + r, other_stride, rz);
+                const float *src = T + sr.base + zp;
+                X[e] = fmaf(sr.f, src[rz] - src[0], src[0]);
             }
         }
     }
     if (NEED_Z)
         for (int e = threadIdx.x; e < n; e += blockDim.x) Z[e] = 0.0;
+}
+
+// One sheet cell's value spread over the two transaxial neighbours.
+__device__ __forceinline__ void spread_cell(float *Gout, const SheetRow &sr, int zp, int rz, float val) {
+    const float a1 = val * sr.f;
+    atomicAdd(&Gout[sr.base + zp], val - a1);
+    atomicAdd(&Gout[sr.base + zp + rz], a1);
 }
 
 // Block epilogue: spread the gradient sheet over the two transaxial neighbours.
@@ -81,19 +131,21 @@ __device__ __forceinline__ void scatter_sheet(const ProjArgs &a, const LineP &L,
     const int rz = a.rz;
     float *Gout = (L.axis ? a.G1 : a.G0) + g_off;
     const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
-    for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
-        float val = (float)Z[e];
-        if (val == 0.f) continue;
-        int r = e / rz;
-        int zp = e - r * rz;
-        int i = L.i_lo + r;
-        float xa = fmaf((float)i, L.dxa, L.xa0);
-        float jf = floorf(xa);
-        float f = xa - jf;
-        size_t base = (size_t)i * other_stride + (size_t)((int)jf + PADA) * rz + zp;
-        float a1 = val * f;
-        atomicAdd(&Gout[base], val - a1);
-        atomicAdd(&Gout[base + rz], a1);
+    if (rz <= (int)blockDim.x) {
+        const SheetWalk w = sheet_walk(rz);
+        if (!w.on) return;
+        for (int r = w.r0; r < nrow; r += w.R) {
+            const float val = (float)Z[r * rz + w.zp];
+            if (val == 0.f) continue;
+            spread_cell(Gout, sheet_row(L, L.i_lo + r, other_stride, rz), w.zp, rz, val);
+        }
+    } else {
+        for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
+            const float val = (float)Z[e];
+            if (val == 0.f) continue;
+            const int r = e / rz;
+            spread_cell(Gout, sheet_row(L, L.i_lo + r, other_stride, rz), e - r * rz, rz, val);
+        }
     }
 }
 

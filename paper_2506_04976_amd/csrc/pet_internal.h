@@ -95,25 +95,41 @@ struct ProjArgs {
 };
 
 // ---- zero-count-aware data term (counts.hip) --------------------------------
-// One bin with y > 0: its index within its transaxial line (plane * n_tof +
-// TOF bin), count, background and the LOR's multiplicative factor.
-struct CountItem {
-    uint32_t pt;
-    float y, add, mult;
+// One bin with y > 0 of a transaxial line, with what the counts kernel needs
+// of its LOR (computed once, at compaction): the sample rows that reach the
+// grid and the bin's TOF window, the TOF table position and the padded axial
+// position as affine functions of the row, mult times the step length, the
+// count and the background.
+struct CountRec {
+    int16_t is, ie;  // sample rows [is, ie] (empty: is > ie)
+    float pA, pB;    // TOF table position of row i: pA i + pB (0 without TOF)
+    float zA, zB;    // padded axial position of row i: zA i + zB
+    float me;        // mult * ell, ell the LOR's step length (mm)
+    float y, add;
 };
-static_assert(sizeof(CountItem) == 16, "CountItem layout");
+static_assert(sizeof(CountRec) == 32, "CountRec layout");
 constexpr int NW_TAB = 4096;    // intervals of the tabulated TOF weight W(d)
 constexpr int CNT_BLOCK = 1024;  // threads per workgroup of the counts line kernel
 
+// One line with counts as a workgroup of the counts kernel sees it: the
+// line's geometry and the range of its bins in the item array.
+struct CountLine {
+    LineP L;
+    int64_t i0;  // first item
+    int32_t n;   // items
+    int32_t line;
+};
+static_assert(sizeof(CountLine) == 48, "CountLine layout");
+
 struct CountArgs {
-    const CountItem *items;
-    const int64_t *line_off;  // items of line l: [line_off[l], line_off[l + 1])
-    const int *lines;         // the launch's lines (workgroup b takes lines[b])
+    const CountRec *items;
+    const CountLine *desc;    // the launch's lines (workgroup b takes desc[b])
     const float2 *wtab;       // TOF: (W_k, W_{k+1} - W_k) at the table's nodes
     int nw, n_tof;
     float wD;                 // support of W: |d| <= wD
     float inv_dx, pos0, pos_max;  // table position of d: d * inv_dx + pos0, clamped to [0, pos_max]
     int q_cap;                // bins per chunk of a line (their factors Q are kept in LDS)
+    int force_signed;         // signed fixed-point sheets for every chunk (tests)
 };
 
 // ---- batches of reconstructions -------------------------------------------
@@ -218,9 +234,10 @@ struct pet_counts_s {
     pet_geom_s *g = nullptr;
     int n_subsets = 0;
     int64_t n_items = 0;
-    pet::CountItem *items = nullptr;  // per line, TOF bin major
+    pet::CountRec *items = nullptr;   // per line, TOF bin major
     int64_t *line_off = nullptr;      // [n_lines + 1]
     int *lines = nullptr;             // per subset (then all views): lines with counts, most first
+    pet::CountLine *desc = nullptr;   // the same lines with their geometry and item ranges
     std::vector<int64_t> lines_off;        // [n_subsets + 2] offsets into lines
     std::vector<int64_t> items_per_subset; // [n_subsets + 1]
     std::vector<double> sum_y, sum_add;    // [n_subsets + 1] over every bin of the subset (then all)
@@ -310,6 +327,11 @@ hipError_t launch_svrg_step(const pet_geom_s *g, const float *x, const float *ka
                             float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
                             float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,
                             float n_sub, float tau, float *x_out, float *est_out, hipStream_t s);
+bool step_tile_ok(const pet_geom_s *g);
+hipError_t launch_svrg_step_tile(const pet_geom_s *g, const float *x, const float *w27, float beta, float gamma,
+                                 float eps, int update_pc, const float *sens, float alpha, float delta, float *D,
+                                 int snapshot, const float *ghat_i, const double *ghat, float w, float tau,
+                                 const double *tau_bb, int bb_store, float *g_prev, float *x_out, hipStream_t s);
 hipError_t launch_svrg_step_ex(const pet_geom_s *g, const float *x, const float *kappa, const float *w27, float beta,
                                float gamma, float eps, int update_pc, const float *sens, float alpha, float delta,
                                float *D, int snapshot, const float *gi, const float *ghat_i, const double *ghat,

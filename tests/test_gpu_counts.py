@@ -92,6 +92,57 @@ def test_counts_subset_grad_and_kl_parity(case):
         assert err_h <= 1e-5, f"subset {subset}: {err_h:.3e}"
 
 
+def test_counts_signed_sheets(case):
+    # PET_SIGNED_SHEETS: every chunk accumulates its fixed-point sheet in the
+    # signed form (low word with borrow) that chunks with a negative factor
+    # take; on the same well-conditioned data, the same oracle bar.
+    pm = case.pm
+    xo = case.x_np.astype(np.float64)
+    pm.pet_geom_set_flags(case.geom, pm.PET_SIGNED_SHEETS)
+    try:
+        for subset in range(case.cfg["n_subsets"]):
+            sens = case.sens_subset(subset)
+            g = torch.full((case.geom.n_vox,), float("nan"), device=case.dev)
+            pm.pet_subset_grad_counts(case.geom, case.counts, subset, case.x, sens, g)
+            ref = case.prob.data_grad(xo, subset).ravel()
+            yb = case.prob.ybar(xo, subset)
+            scale = np.linalg.norm(case.prob.back(case.prob.a[subset] * (1 + case.prob.y[subset] / yb), subset))
+            err = np.linalg.norm(g.cpu().double().numpy() - ref) / scale
+            assert err <= 1e-5, f"subset {subset}: {err:.3e}"
+    finally:
+        pm.pet_geom_set_flags(case.geom, 0)
+
+
+def test_counts_negative_means(case):
+    # Negative means lie outside the domain (d = inf for s <= 0 < t), but
+    # without PET_CHECK the kernels still evaluate the formulas.  With x < 0
+    # and add < 0 every bin has ybar <= add < 0, so every factor Q is negative
+    # and each chunk switches to the signed fixed-point sheet by itself; |ybar|
+    # stays >= |add|, so the data are as well conditioned as for x >= 0 and the
+    # oracle bar is the same.
+    pm = case.pm
+    xn = (-case.x_np).astype(np.float32)
+    xo = xn.astype(np.float64)
+    x = torch.from_numpy(xn.ravel()).to(case.dev)
+    neg_r = -case.r
+    cnt = pm.Counts(case.geom, case.y, neg_r, case.a)
+    prob = recon.Problem(case.cfg, case.d["y"], -case.d["r"], case.d["mult"], beta=1.0, gamma=2.0, eps=1.0)
+    try:
+        for subset in range(case.cfg["n_subsets"]):
+            yb = prob.ybar(xo, subset)
+            yy = prob.y[subset]
+            assert np.all(yb[yy > 0] < 0)
+            sens = case.sens_subset(subset)
+            g = torch.full((case.geom.n_vox,), float("nan"), device=case.dev)
+            pm.pet_subset_grad_counts(case.geom, cnt, subset, x, sens, g)
+            ref = prob.data_grad(xo, subset).ravel()
+            scale = np.linalg.norm(prob.back(prob.a[subset] * (1 + yy / np.abs(yb)), subset))
+            err = np.linalg.norm(g.cpu().double().numpy() - ref) / scale
+            assert err <= 1e-5, f"subset {subset}: {err:.3e}"
+    finally:
+        cnt.close()
+
+
 def test_counts_chunked_grad_parity(case):
     # PET_SMALL_CHUNKS cuts every line's bins into chunks of 16, each with its
     # own fixed-point scale and sheet readout: same oracle bar as above

@@ -107,7 +107,7 @@ def test_domain_checks_return_pet_e_domain(pm):
     pm.pet_geom_set_flags(g, 0)
     pm.pet_subset_grad(g, 1, xb, y, r, a, out)
     with pytest.raises(pm.PetError, match="unknown flag"):
-        pm.pet_geom_set_flags(g, 6)
+        pm.pet_geom_set_flags(g, 8)
     torch.cuda.synchronize()
     g.close()
 
