@@ -281,8 +281,9 @@ typedef struct {
      * n (grad D_i(x) - ghat_i), so ghat_i holds -P_i^T[mult y / ybar(xhat)] and
      * ghat = sens + sum_i ghat_i, the same full gradient as the dense path;
      * objective_out is computed from the compacted bins.  The iterates equal
-     * the dense path's up to rounding.  Not with gnorm (PET_E_ARG).  SAGA, SGD,
-     * the reverse mode and batches use the dense kernels (PET_E_ARG if set). */
+     * the dense path's up to rounding.  Not with gnorm (PET_E_ARG).  SAGA and
+     * SGD take it too (see pet_saga_epoch); the reverse mode and batches use
+     * the dense kernels (PET_E_ARG if set). */
     pet_counts counts;
     /* Objective at the snapshots (nullable device double): every snapshot
      * iteration writes Phi(xhat) = D(A xhat + r, y) + beta S(xhat) in FP64,
@@ -337,7 +338,16 @@ pet_status pet_svrg_epoch_ex(pet_geom g, pet_svrg_state *state, float *x, const 
  *     filled at the current x before the first iteration (all subsets; that
  *     iteration then steps along sum_q T_q, the full gradient).
  *   SGD: g = n grad J_i(x) = n grad D_i(x) + beta grad S(x); ghat_i / ghat are
- *     not used (may be null).
+ *     not used (may be null) on the dense path.
+ * With state->counts (the zero-count-aware data term, as for pet_svrg_epoch)
+ * the line kernels walk only the bins with counts, which give
+ * h_i(x) = -P_i^T[mult y / ybar] with grad D_i = P_i^T mult + h_i:
+ *   SAGA's table then holds h_i + (beta/n) grad S (the P_i^T mult cancel in
+ *     grad J_i - T_i) and state->ghat holds its sum plus state->sens;
+ *   SGD needs state->ghat_i: at state->k == 0 it receives the subset
+ *     sensitivities P_i^T mult (one dense back projection per subset), which
+ *     later epochs of the same state reuse.
+ * Iterates agree with the dense path up to rounding.
  * x_snap and omega are not used.  A state serves one estimator: the SVRG
  * snapshot table (data gradients only) is not a SAGA table.  Same argument
  * rules and errors as pet_svrg_epoch. */

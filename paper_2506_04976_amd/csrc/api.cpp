@@ -544,11 +544,13 @@ static pet_status sgm_epoch(pet_geom g, pet_svrg_state *st, int estimator, float
                             const char *name) {
     const std::string nm(name);
     if (!g || !st || !x || !subset_seq || !tau || !update_pc) return fail(PET_E_ARG, nm + ": null argument");
-    if (!st->D || !st->sens || !st->y || (estimator == SGM_SAGA && (!st->ghat_i || !st->ghat)))
+    const pet_counts_s *cnt = st->counts;
+    if (!st->D || !st->sens || !st->y || (estimator == SGM_SAGA && (!st->ghat_i || !st->ghat)) ||
+        (cnt && !st->ghat_i))
         return fail(PET_E_ARG, nm + ": incomplete state");
     if (!valid_dtype(st->y_dtype)) return fail(PET_E_ARG, nm + ": bad y dtype");
     if (st->k < 0) return fail(PET_E_STATE, nm + ": negative iteration counter");
-    if (st->counts) return fail(PET_E_ARG, nm + ": runs the dense kernels (state->counts must be NULL)");
+    if (cnt && cnt->g != g) return fail(PET_E_ARG, nm + ": counts were made for another geometry");
     const int n = g->d.n_subsets;
     for (int j = 0; j < n; ++j)
         if (subset_seq[j] < 0 || subset_seq[j] >= n) return fail(PET_E_ARG, nm + ": subset_seq entry out of range");
@@ -559,6 +561,21 @@ static pet_status sgm_epoch(pet_geom g, pet_svrg_state *st, int estimator, float
     }
     hipError_t e = hipSuccess;
     const int64_t nv = g->n_vox;
+    // Zero-count-aware path: the line kernels give h_i(x) = -P_i^T[mult y / ybar]
+    // only, and grad D_i = sens_i + h_i.  SAGA's table then holds h_i + (beta /
+    // n) grad S (the sens_i cancel in n(grad J_i - T_i)) and its sum starts
+    // from sens = sum_i sens_i; SGD keeps the n subset sensitivities sens_i in
+    // state->ghat_i (back projections of mult, filled at k = 0) and adds them
+    // to h_i in the step.
+    if (cnt && estimator == SGM_SGD && st->k == 0) {
+        for (int q = 0; q < n && e == hipSuccess; ++q) {
+            e = launch_zero_sheets(g, s);
+            ProjArgs a = base_args(g, q);
+            a.mult = st->mult;
+            if (e == hipSuccess) e = launch_line_kernel(g, M_BACK, q, a, s);
+            if (e == hipSuccess) e = launch_from_sheets(g, st->ghat_i + (size_t)q * nv, 0, s);
+        }
+    }
     for (int j = 0; j < n && e == hipSuccess; ++j) {
         const int64_t k = st->k + j;
         const int i = subset_seq[j];
@@ -567,28 +584,32 @@ static pet_status sgm_epoch(pet_geom g, pet_svrg_state *st, int estimator, float
         if (first) {
             // table of data gradients at x, then the prior shares and the sum
             for (int q = 0; q < n && e == hipSuccess; ++q) {
-                e = subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+                e = cnt ? counts_grad_sheets(g, cnt, q, nullptr, s)
+                        : subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
                 if (e == hipSuccess) e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s);
             }
             if (e == hipSuccess)
                 e = launch_rdp(g, x, st->kappa, st->w, st->beta, st->gamma, st->eps, g->num, nullptr, nullptr, s);
-            if (e == hipSuccess) e = launch_saga_table_prior(g, st->ghat_i, st->ghat, g->num, s);
+            if (e == hipSuccess) e = launch_saga_table_prior(g, st->ghat_i, st->ghat, g->num, s, cnt ? st->sens : nullptr);
         } else {
-            e = subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
+            e = cnt ? counts_grad_sheets(g, cnt, i, nullptr, s)
+                    : subset_grad_sheets(g, i, st->y, st->y_dtype, st->add, st->mult, nullptr, 0, s);
             if (e == hipSuccess) e = launch_from_sheets(g, g->g, 0, s);
         }
+        float *table_i = estimator == SGM_SAGA || cnt ? st->ghat_i + (size_t)i * nv : nullptr;
         if (e == hipSuccess)
             e = launch_sgm_step(g, estimator, x, st->kappa, st->w, st->beta, st->gamma, st->eps, update_pc[j],
-                                st->sens, st->alpha, st->delta, st->D, first, g->g,
-                                estimator == SGM_SAGA ? st->ghat_i + (size_t)i * nv : nullptr, st->ghat, (float)n,
+                                st->sens, st->alpha, st->delta, st->D, first, g->g, table_i, st->ghat, (float)n,
                                 tau[j], g->xtmp, s);
         if (e == hipSuccess) e = launch_copy(x, g->xtmp, nv, s);
     }
     if (e != hipSuccess) return hip_check(e, name);
     st->k += n;
     if (objective_out)
-        e = objective_impl(g, x, st->y, st->y_dtype, st->add, st->mult, st->kappa, st->w, st->beta, st->gamma,
-                           st->eps, objective_out, s);
+        e = cnt ? objective_counts_impl(g, cnt, x, st->sens, st->kappa, st->w, st->beta, st->gamma, st->eps,
+                                        objective_out, s)
+                : objective_impl(g, x, st->y, st->y_dtype, st->add, st->mult, st->kappa, st->w, st->beta, st->gamma,
+                                 st->eps, objective_out, s);
     const pet_status rs = hip_check(e, name);
     if (rs != PET_OK || !objective_out || !checking(g)) return rs;
     return check_numeric(s, objective_out, name);

@@ -174,13 +174,15 @@ __global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y,
     }
 }
 
-// TOF weight W(d) from the LDS table, at table position pos = d / dx + NW/2:
-// linear interpolation between nodes; the position is clamped to the table,
+// TOF weight W(d) from the LDS table of W at the NW_TAB + 1 nodes, at table
+// position pos = d / dx + NW/2: linear interpolation between the two nodes
+// around pos (one two-word LDS read); the position is clamped to the table,
 // whose end nodes are 0.
-__device__ __forceinline__ float tof_weight_at(const float2 *tab, float pos, float pos_max) {
+__device__ __forceinline__ float tof_weight_at(const float *tab, float pos, float pos_max) {
     pos = __builtin_amdgcn_fmed3f(pos, 0.f, pos_max);
-    const float2 t = tab[(int)pos];
-    return fmaf(__builtin_amdgcn_fractf(pos), t.y, t.x);
+    const int k = (int)pos;
+    const float w0 = tab[k], w1 = tab[k + 1];
+    return fmaf(__builtin_amdgcn_fractf(pos), w1 - w0, w0);
 }
 
 // Sum over the workgroup, the same value in every thread (wave sums by
@@ -262,27 +264,31 @@ __device__ __forceinline__ float packed_cell_value(const unsigned long long *Zu,
     return finite ? (float)(SIGNED ? V : -V) * inv_scale : __builtin_nanf("");
 }
 
+// Readout of the packed sheet rows [lo, hi) of the line (Zu holds them from
+// row lo on), spread over the two transaxial neighbours like the FP64 sheet of
+// the dense kernels.  A line whose bound is not finite (a bin with ybar = 0)
+// adds NaN to every cell it covers.
 template <bool SIGNED>
-__device__ __forceinline__ void scatter_sheet_packed(const ProjArgs &a, const LineP &L, int nrow,
-                                                     const unsigned long long *Zu, float inv_scale, bool finite) {
+__device__ __forceinline__ void scatter_rows_packed(const ProjArgs &a, const LineP &L, int lo, int hi,
+                                                    const unsigned long long *Zu, float inv_scale, bool finite) {
     const int rz = a.rz;
     float *Gout = L.axis ? a.G1 : a.G0;
     const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
     if (rz <= (int)blockDim.x) {
         const SheetWalk w = sheet_walk(rz);
         if (!w.on) return;
-        for (int r = w.r0; r < nrow; r += w.R) {
-            const float val = packed_cell_value<SIGNED>(Zu, r * rz + w.zp, w.zp, inv_scale, finite);
+        for (int r = lo + w.r0; r < hi; r += w.R) {
+            const float val = packed_cell_value<SIGNED>(Zu, (r - lo) * rz + w.zp, w.zp, inv_scale, finite);
             if (val == 0.f) continue;
             spread_cell(Gout, sheet_row(L, L.i_lo + r, other_stride, rz), w.zp, rz, val);
         }
     } else {
-        for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) {
+        for (int e = threadIdx.x; e < (hi - lo) * rz; e += blockDim.x) {
             const int r = e / rz;
             const int zp = e - r * rz;
             const float val = packed_cell_value<SIGNED>(Zu, e, zp, inv_scale, finite);
             if (val == 0.f) continue;
-            spread_cell(Gout, sheet_row(L, L.i_lo + r, other_stride, rz), zp, rz, val);
+            spread_cell(Gout, sheet_row(L, L.i_lo + lo + r, other_stride, rz), zp, rz, val);
         }
     }
 }
@@ -296,26 +302,61 @@ __device__ __forceinline__ int lanes_per_bin(int n_c) {
     return C;
 }
 
-// Rows of the image sheet a thread loads in the prologue's batch (more rows,
-// if any, in later passes).
-constexpr int CNT_SHEET_ROWS = 12;
+// Rows of the image sheet whose loads a thread has in flight at once.
+constexpr int CNT_SHEET_ROWS = 8;
+
+// Image sheet X of a line (rows [0, nrow), padded axial positions [0, rz)):
+// the transaxial interpolation of the transposed image, as build_sheets.
+__device__ __forceinline__ void build_x(const ProjArgs &a, const LineP &L, int nrow, float *X) {
+    const int rz = a.rz;
+    if (rz > (int)blockDim.x) {
+        build_sheets<true, false>(a, L, nrow, X, nullptr);
+        return;
+    }
+    const float *T = L.axis ? a.T1 : a.T0;
+    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    const SheetWalk sw = sheet_walk(rz);
+    if (!sw.on) return;
+    for (int rb = sw.r0; rb < nrow; rb += CNT_SHEET_ROWS * sw.R) {
+        float t0[CNT_SHEET_ROWS], t1[CNT_SHEET_ROWS], tf[CNT_SHEET_ROWS];
+#pragma unroll
+        for (int u = 0; u < CNT_SHEET_ROWS; ++u) {
+            const int r = rb + u * sw.R;
+            t0[u] = t1[u] = tf[u] = 0.f;
+            if (r < nrow) {
+                const SheetRow sr = sheet_row(L, L.i_lo + r, other_stride, rz);
+                tf[u] = sr.f;
+                const float *src = T + sr.base + sw.zp;
+                t0[u] = src[0];
+                t1[u] = src[rz];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CNT_SHEET_ROWS; ++u) {
+            const int r = rb + u * sw.R;
+            if (r < nrow) X[r * rz + sw.zp] = fmaf(tf[u], t1[u] - t0[u], t0[u]);
+        }
+    }
+}
 
 // One workgroup per line with counts.  MODE M_GRAD: gradient sheets receive
 // -P^T [mult y / ybar]; M_OBJ: no gradient.  Both write the workgroup's FP64
 // sum of y log(y / ybar) when a.partial is set.
 //
-// Prologue: every load the line starts with is in flight at once (TOF table,
-// the image rows of the sheet, the thread's first bin and then its plane), so
-// that a workgroup waits for memory about twice per line before its samples.
+// LDS: one sheet region that holds the image sheet X (nrow x rz floats) while
+// the bins are walked forward, and then the packed gradient sheet of half the
+// rows (ceil(nrow / 2) x rz 64-bit words, the same bytes); the TOF table; the
+// factors Q of a chunk.  About 63 KB on the brain-sized workloads, so that
+// two workgroups share a CU and one's barriers overlap the other's samples.
 //
 // The line's bins are taken in chunks of at most c.q_cap.  Phase one walks
-// every bin of the chunk forward (ybar, the log term, Q = mult y / ybar ell);
-// with M_GRAD, phase two walks them again and adds -Q W(t - t_b) times the
-// axial interpolation weights to the packed sheet, scaled by the chunk's sum
-// of |Q|.  When a chunk has at most one bin per lane group (the usual case),
-// its bin, geometry and Q stay in registers between the phases; otherwise Q
-// goes through LDS and phase two reloads the bins.  A chunk's sheet is read
-// out before the next starts.
+// every bin of the chunk forward (ybar, the log term, Q = mult y / ybar ell).
+// With M_GRAD, phase two runs once per half of the rows: it clears the packed
+// sheet, adds the chunk's shares -Q W(t - t_b) (times the axial interpolation
+// weights, scaled by 2^30 / sum |Q|) of the samples in those rows, and reads
+// the half out.  When a chunk has at most one bin per lane group, its bin and
+// Q stay in registers between the phases; otherwise Q goes through LDS and
+// phase two reloads the bins.  A next chunk rebuilds X.
 template <bool TOF, int MODE>
 __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs c) {
     extern __shared__ float4 smem4[];
@@ -326,80 +367,50 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     const LineP &L = desc.L;
     const int nrow = L.i_hi - L.i_lo + 1;
     const int rz = a.rz;
-    const int sheet = (a.rows_max * rz + 3) & ~3;
     float *X = smem;
-    unsigned long long *Zu = reinterpret_cast<unsigned long long *>(smem + sheet);
-    float2 *tab = reinterpret_cast<float2 *>(smem + (NEED_Z ? 3 : 1) * sheet);
-    float *Qs = smem + (NEED_Z ? 3 : 1) * sheet + (TOF ? 2 * NW_TAB : 0);
+    unsigned long long *Zu = reinterpret_cast<unsigned long long *>(smem);  // (X's bytes, after phase one)
+    float *tab = smem + c.sheet_floats;
+    float *Qs = tab + (TOF ? c.tab_floats : 0);
     const int64_t i0 = desc.i0, i1 = desc.i0 + desc.n;
+    const int hrows = (nrow + 1) >> 1;
     const CountRec none{1, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // no rows, no count
 
-    // ---- prologue: issue every load, then store
-    static_assert(NW_TAB % CNT_BLOCK == 0, "the table load assumes CNT_BLOCK divides NW_TAB");
-    float2 wt[TOF ? NW_TAB / CNT_BLOCK : 1];
     if (TOF) {
+        // the table's loads in flight together, eight per thread
+        for (int k0 = threadIdx.x; k0 <= NW_TAB; k0 += 8 * CNT_BLOCK) {
+            float wv[8];
 #pragma unroll
-        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) wt[u] = c.wtab[threadIdx.x + u * CNT_BLOCK];
-    }
-    const int64_t c1_first = i0 + c.q_cap < i1 ? i0 + c.q_cap : i1;
-    const int C_first = lanes_per_bin((int)(c1_first - i0));
-    const int64_t it_first = i0 + threadIdx.x / C_first;
-    const bool act_first = it_first < c1_first;
-    const CountRec e_first = act_first ? c.items[it_first] : none;
-    // image sheet rows (the column walk of build_sheets; the fallback for
-    // rz > blockDim and the rows past the batch are built after the stores)
-    const float *T = L.axis ? a.T1 : a.T0;
-    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
-    const bool walk = rz <= (int)blockDim.x;  // uniform
-    const SheetWalk sw = sheet_walk(rz);
-    float t0[CNT_SHEET_ROWS], t1[CNT_SHEET_ROWS], tf[CNT_SHEET_ROWS];
-#pragma unroll
-    for (int u = 0; u < CNT_SHEET_ROWS; ++u) {
-        const int r = sw.r0 + u * sw.R;
-        t0[u] = t1[u] = tf[u] = 0.f;
-        if (walk && sw.on && r < nrow) {
-            const SheetRow sr = sheet_row(L, L.i_lo + r, other_stride, rz);
-            tf[u] = sr.f;
-            const float *src = T + sr.base + sw.zp;
-            t0[u] = src[0];
-            t1[u] = src[rz];
-        }
-    }
-    if (TOF) {
-#pragma unroll
-        for (int u = 0; u < NW_TAB / CNT_BLOCK; ++u) tab[threadIdx.x + u * CNT_BLOCK] = wt[u];
-    }
-    if (walk) {
-        if (sw.on) {
-#pragma unroll
-            for (int u = 0; u < CNT_SHEET_ROWS; ++u) {
-                const int r = sw.r0 + u * sw.R;
-                if (r < nrow) X[r * rz + sw.zp] = fmaf(tf[u], t1[u] - t0[u], t0[u]);
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u * CNT_BLOCK;
+                wv[u] = k <= NW_TAB ? c.wtab[k] : 0.f;
             }
-            for (int r = sw.r0 + CNT_SHEET_ROWS * sw.R; r < nrow; r += sw.R) {
-                const SheetRow sr = sheet_row(L, L.i_lo + r, other_stride, rz);
-                const float *src = T + sr.base + sw.zp;
-                X[r * rz + sw.zp] = fmaf(sr.f, src[rz] - src[0], src[0]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u * CNT_BLOCK;
+                if (k <= NW_TAB) tab[k] = wv[u];
             }
         }
-        if (NEED_Z)
-            for (int e = threadIdx.x; e < nrow * rz; e += blockDim.x) Zu[e] = 0ull;
-    } else if (nrow > 0) {
-        build_sheets<true, NEED_Z>(a, L, nrow, X, reinterpret_cast<double *>(Zu));
     }
+    if (nrow > 0) build_x(a, L, nrow, X);
     __syncthreads();
 
     double kl = 0.0;
     const float umax = (float)(a.nz + PADZ);
-    bool pre = true;  // the prologue holds the first round's bins (uniform)
     // (a line that misses the image still has bins with counts: ybar = add there,
     // and its y log(y / add) enters the sum; its sample ranges are empty)
     for (int64_t c0 = i0; c0 < i1; c0 += c.q_cap) {
         const int64_t c1 = c0 + c.q_cap < i1 ? c0 + c.q_cap : i1;
+        if (NEED_Z && c0 > i0) {
+            // phase two of the previous chunk overwrote X (its last barrier
+            // follows the readout)
+            if (nrow > 0) build_x(a, L, nrow, X);
+            __syncthreads();
+        }
         // C lanes per bin (consecutive lanes of one wave) take every C-th
         // sample of its window
         const int n_c = (int)(c1 - c0);
         const int C = lanes_per_bin(n_c);
+        const int lc = __builtin_ctz((unsigned)C);
         const int ch = threadIdx.x & (C - 1);
         const int nslot = blockDim.x / C;
         const bool one_round = n_c <= nslot;  // uniform
@@ -413,13 +424,7 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             // the C lanes of a bin by shuffles
             const int64_t it = it0 + threadIdx.x / C;
             const bool act = it < c1;
-            CountRec e;
-            if (pre) {
-                e = e_first;
-                pre = false;
-            } else {
-                e = act ? c.items[it] : none;
-            }
+            const CountRec e = act ? c.items[it] : none;
             // rows as floats (exact integers): no conversion per sample
             const float fis = (float)(e.is + ch), fie = (float)e.ie;
             float s = 0.f;
@@ -451,53 +456,58 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             }
         }
         if (!NEED_Z) continue;  // uniform
-        // (the barrier inside also publishes Qs)
+        // (the barrier inside also publishes Qs and ends every read of X)
         const float2 tot = block_sum_all(make_float2(qabs, qneg), red);
         const float bound = tot.x;
         const bool finite = bound < INFINITY;  // false for inf and NaN
         const bool sgn = tot.y > 0.f || c.force_signed;  // some Q < 0 (uniform)
         const float scale = finite && bound > 0.f ? 0x1p30f / bound : 0.f;
-        if (scale > 0.f) {
-            for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
-                const int64_t it = it0 + threadIdx.x / C;
-                const bool act = it < c1;
-                CountRec g;
-                float qsc;
-                if (one_round) {
-                    g = ek;
-                    qsc = Qk * scale;
-                } else {
-                    g = act ? c.items[it] : none;
-                    qsc = act ? Qs[act ? (int)(it - c0) : 0] * scale : 0.f;  // (index < q_cap)
-                }
-                const float fis = (float)(g.is + ch), fie = (float)g.ie;
-                unsigned long long *zr = Zu + (g.is + ch - L.i_lo) * rz;
-                if (!sgn) {
-                    for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
-                        const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
-                        const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
-                        deposit_pos(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
+        if (nrow == 0 || (scale == 0.f && finite)) continue;  // (nothing to add; uniform)
+        for (int lo = 0; lo < nrow; lo += hrows) {
+            const int hi = lo + hrows < nrow ? lo + hrows : nrow;
+            const int ra = L.i_lo + lo, rb = L.i_lo + hi - 1;  // absolute rows of this half
+            for (int k = threadIdx.x; k < (hi - lo) * rz; k += blockDim.x) Zu[k] = 0ull;
+            __syncthreads();
+            if (scale > 0.f) {
+                for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
+                    const int64_t it = it0 + threadIdx.x / C;
+                    const bool act = it < c1;
+                    CountRec g;
+                    float qsc;
+                    if (one_round) {
+                        g = ek;
+                        qsc = Qk * scale;
+                    } else {
+                        g = act ? c.items[it] : none;
+                        qsc = act ? Qs[act ? (int)(it - c0) : 0] * scale : 0.f;  // (index < q_cap)
                     }
-                } else {
-                    for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
-                        const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
-                        const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
-                        deposit_packed(zr, (int)u, -qw, __builtin_amdgcn_fractf(u));
+                    // this lane's rows g.is + ch + kC that fall in [ra, rb]
+                    int r0 = g.is + ch;
+                    if (r0 < ra) r0 += ((ra - r0 + C - 1) >> lc) << lc;
+                    const int r1 = g.ie < rb ? g.ie : rb;
+                    const float fis = (float)r0, fie = (float)r1;
+                    unsigned long long *zr = Zu + (r0 - ra) * rz;
+                    if (!sgn) {
+                        for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                            const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
+                            const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                            deposit_pos(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
+                        }
+                    } else {
+                        for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                            const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
+                            const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                            deposit_packed(zr, (int)u, -qw, __builtin_amdgcn_fractf(u));
+                        }
                     }
                 }
             }
-        }
-        __syncthreads();
-        if (nrow > 0 && (scale > 0.f || !finite)) {
-            if (sgn)
-                scatter_sheet_packed<true>(a, L, nrow, Zu, finite ? 1.f / scale : 0.f, finite);
-            else
-                scatter_sheet_packed<false>(a, L, nrow, Zu, finite ? 1.f / scale : 0.f, finite);
-        }
-        if (c1 < i1) {
-            // the next chunk starts from a zero sheet (after every readout)
             __syncthreads();
-            for (int k = threadIdx.x; k < nrow * rz; k += blockDim.x) Zu[k] = 0ull;
+            if (sgn)
+                scatter_rows_packed<true>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite);
+            else
+                scatter_rows_packed<false>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite);
+            // (before the next half clears the sheet, or the next chunk's X)
             __syncthreads();
         }
     }
@@ -538,25 +548,35 @@ hipError_t launch_counts_mode(const pet_geom_s *g, const pet_counts_s *cs, int n
 
 }  // namespace
 
-// LDS of the sheets and the TOF table (dynamic), and what the gradient mode
-// keeps per bin of a chunk: its factor Q, 4 bytes.
-static size_t counts_lds_base(const pet_geom_s *g, int mode) {
-    const size_t sheet = ((size_t)g->rows_max * (g->d.nz + 2 * PADZ) + 3) & ~(size_t)3;
-    const size_t tab = g->d.n_tof > 1 ? sizeof(float2) * NW_TAB : 0;
-    return (mode == M_GRAD ? 3 : 1) * sheet * sizeof(float) + tab;
+// LDS of the counts kernel (dynamic), in floats: the sheet region (X, or the
+// packed gradient sheet of half the rows), the TOF table (NW_TAB + 1 nodes),
+// each rounded up to 16 bytes.
+static size_t counts_sheet_floats(const pet_geom_s *g) {
+    const size_t rz = (size_t)g->d.nz + 2 * PADZ;
+    const size_t x = (size_t)g->rows_max * rz;
+    const size_t zu = 2 * (((size_t)g->rows_max + 1) / 2) * rz;
+    return (std::max(x, zu) + 3) & ~(size_t)3;
 }
 
-// Bins per chunk: what the LDS left after the sheets, the table and 1 KB of
-// static shared memory holds, at most 8192 (0 if less than 256 fit).
+static size_t counts_tab_floats(const pet_geom_s *g) {
+    return g->d.n_tof > 1 ? ((size_t)NW_TAB + 1 + 3) & ~(size_t)3 : 0;
+}
+
+static size_t counts_lds_base(const pet_geom_s *g) {
+    return sizeof(float) * (counts_sheet_floats(g) + counts_tab_floats(g));
+}
+
+// Bins per chunk with M_GRAD: at most CNT_QCAP, fewer if the LDS cannot hold
+// their factors next to the sheet and the table (0 if less than 256 fit).
 static int counts_q_cap(const pet_geom_s *g) {
-    const size_t base = counts_lds_base(g, M_GRAD) + 1024;
+    const size_t base = counts_lds_base(g) + 1024;
     if (base >= g->max_lds) return 0;
     const size_t fit = ((g->max_lds - base) / sizeof(float)) & ~(size_t)3;
-    return fit < 256 ? 0 : (int)std::min<size_t>(fit, 8192);
+    return fit < 256 ? 0 : (int)std::min<size_t>(fit, CNT_QCAP);
 }
 
 size_t counts_lds_bytes(const pet_geom_s *g, int mode) {
-    return counts_lds_base(g, mode) + (mode == M_GRAD ? sizeof(float) * (size_t)counts_q_cap(g) : 0);
+    return counts_lds_base(g) + (mode == M_GRAD ? sizeof(float) * (size_t)counts_q_cap(g) : 0);
 }
 
 int counts_blocks(const pet_counts_s *cs, int subset) {
@@ -567,8 +587,10 @@ int counts_blocks(const pet_counts_s *cs, int subset) {
 // The TOF table's constants (and the TOF bin count) of a geometry.
 static CountArgs count_args(const pet_geom_s *g) {
     CountArgs c{};
-    c.wtab = g->wtab;
+    c.wtab = g->wtabf;
     c.nw = NW_TAB;
+    c.sheet_floats = (int)counts_sheet_floats(g);
+    c.tab_floats = (int)counts_tab_floats(g);
     c.n_tof = g->d.n_tof;
     c.wD = g->wD;
     c.inv_dx = (float)(NW_TAB / (2.0 * g->wD));

@@ -447,6 +447,11 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
         for (int k = 0; k < NW_TAB; ++k) tab[k] = make_float2((float)W[k], (float)(W[k + 1] - W[k]));
         e = hipMalloc(&g->wtab, sizeof(float2) * NW_TAB);
         if (e == hipSuccess) e = hipMemcpy(g->wtab, tab.data(), sizeof(float2) * NW_TAB, hipMemcpyHostToDevice);
+        std::vector<float> tabf(NW_TAB + 1);
+        for (int k = 0; k <= NW_TAB; ++k) tabf[k] = (float)W[k];
+        if (e == hipSuccess) e = hipMalloc(&g->wtabf, sizeof(float) * (NW_TAB + 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(g->wtabf, tabf.data(), sizeof(float) * (NW_TAB + 1), hipMemcpyHostToDevice);
     }
     // padded sheet borders must be zero once; interiors are rewritten per use
     if (e == hipSuccess) e = hipMemset(g->T0, 0, sizeof(float) * g->t0_elems);
@@ -475,7 +480,7 @@ extern "C" pet_status pet_geom_destroy(pet_geom g) {
     }
     void *ptrs[] = {g->lines, g->planes, g->segs, g->views_dev, g->line_order, g->T0, g->T1, g->G0, g->G1, g->g, g->xtmp,
                     g->grad, g->hess, g->num, g->sensi, g->partial, g->dscratch, g->fscratch, g->psf_a, g->psf_b,
-                    g->check_counts, g->wtab, g->gsegs};
+                    g->check_counts, g->wtab, g->wtabf, g->gsegs};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete g;

@@ -251,7 +251,9 @@ __device__ __forceinline__ float rdp_finish(const RdpArgs &a, int v, float xi, f
                 a.table_i[v] = ji;
             }
         } else if (F & R_SGD) {
-            est = fmaf(a.n_sub, gi, bg);
+            // (table_i: the part of the subset's data gradient that the
+            // sheets do not hold, its sensitivity on the zero-count-aware path)
+            est = fmaf(a.n_sub, a.table_i ? gi + a.table_i[v] : gi, bg);
         } else if (F & R_SNAPSHOT) {
             est = (float)a.ghat[v] + bg;
         } else {
@@ -494,10 +496,11 @@ __global__ void __launch_bounds__(256) k_snapshot_accum(const float *__restrict_
 // in table (n x nvox); add each subset's prior share (beta / n) grad S(x) and
 // form the table's sum in FP64 from the stored entries.
 __global__ void k_saga_table_prior(float *__restrict__ table, double *__restrict__ table_sum,
-                                   const float *__restrict__ bgrad, int n_sub, int64_t nv) {
+                                   const float *__restrict__ bgrad, int n_sub, int64_t nv,
+                                   const float *__restrict__ base) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
         const float share = bgrad[v] / (float)n_sub;
-        double sum = 0.0;
+        double sum = base ? (double)base[v] : 0.0;
         for (int i = 0; i < n_sub; ++i) {
             const float t = table[(size_t)i * nv + v] + share;
             table[(size_t)i * nv + v] = t;
@@ -993,9 +996,9 @@ hipError_t launch_subset_norms(const pet_geom_s *g, const float *ghat_i, const f
 }
 
 hipError_t launch_saga_table_prior(const pet_geom_s *g, float *table, double *table_sum, const float *bgrad,
-                                  hipStream_t s) {
+                                  hipStream_t s, const float *base) {
     hipLaunchKernelGGL(k_saga_table_prior, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, table, table_sum, bgrad,
-                       g->d.n_subsets, g->n_vox);
+                       g->d.n_subsets, g->n_vox, base);
     return hipGetLastError();
 }
 

@@ -109,7 +109,8 @@ struct CountRec {
 };
 static_assert(sizeof(CountRec) == 32, "CountRec layout");
 constexpr int NW_TAB = 4096;    // intervals of the tabulated TOF weight W(d)
-constexpr int CNT_BLOCK = 1024;  // threads per workgroup of the counts line kernel
+constexpr int CNT_BLOCK = 512;   // threads per workgroup of the counts line kernel
+constexpr int CNT_QCAP = 2048;   // bins per chunk of the counts line kernel (their factors in LDS)
 
 // One line with counts as a workgroup of the counts kernel sees it: the
 // line's geometry and the range of its bins in the item array.
@@ -124,7 +125,8 @@ static_assert(sizeof(CountLine) == 48, "CountLine layout");
 struct CountArgs {
     const CountRec *items;
     const CountLine *desc;    // the launch's lines (workgroup b takes desc[b])
-    const float2 *wtab;       // TOF: (W_k, W_{k+1} - W_k) at the table's nodes
+    const float *wtab;        // TOF: W at the table's NW_TAB + 1 nodes
+    int sheet_floats, tab_floats;  // LDS layout: sheet region, TOF table (floats)
     int nw, n_tof;
     float wD;                 // support of W: |d| <= wD
     float inv_dx, pos0, pos_max;  // table position of d: d * inv_dx + pos0, clamped to [0, pos_max]
@@ -207,7 +209,8 @@ struct pet_geom_s {
     // TOF weight of a point at signed distance d from a bin centre,
     // W(d) = 1/2 [E(bin/2 - d) - E(-bin/2 - d)] (E the clamped erf), at NW_TAB + 1
     // nodes over its support |d| <= wD, as (W_k, W_{k+1} - W_k) pairs
-    float2 *wtab = nullptr;
+    float2 *wtab = nullptr;   // TOF weight table: (W_k, W_{k+1} - W_k) at NW_TAB nodes (gather adjoint)
+    float *wtabf = nullptr;   // and W at the NW_TAB + 1 nodes (counts kernels)
     float wD = 0.f;
     size_t lds_bytes = 0;
     size_t max_lds = 0;                 // the device's LDS limit per workgroup
@@ -345,7 +348,7 @@ hipError_t launch_subset_norms(const pet_geom_s *g, const float *ghat_i, const f
                                hipStream_t s);
 enum SgmEstimator { SGM_SAGA = 1, SGM_SGD = 2 };
 hipError_t launch_saga_table_prior(const pet_geom_s *g, float *table, double *table_sum, const float *bgrad,
-                                  hipStream_t s);
+                                  hipStream_t s, const float *base = nullptr);
 hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, const float *kappa, const float *w27,
                            float beta, float gamma, float eps, int update_pc, const float *sens, float alpha,
                            float delta, float *D, int first, const float *gi, float *table_i, double *table_sum,

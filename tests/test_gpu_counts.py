@@ -177,7 +177,7 @@ def test_counts_objective_parity(case):
     assert float(out.cpu()) == pytest.approx(case.prob.objective(case.x_np.astype(np.float64)), rel=1e-5)
 
 
-def _svrg(case, counts, epochs):
+def _svrg(case, counts, epochs, algo="svrg"):
     pm = case.pm
     cfg, n = case.cfg, case.cfg["n_subsets"]
     beta = configs.beta_value(cfg)
@@ -189,12 +189,13 @@ def _svrg(case, counts, epochs):
     st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=beta, gamma=2.0, eps=1e-3 * mx,
                              alpha=1.0, delta=1e-3 * mx, counts=case.counts if counts else None)
     orders = data.subset_orders(cfg, epochs)
-    tau_rule = recon.stepsize_vanishing(1.0, 0.02, n)
+    tau_rule = recon.stepsize_vanishing(0.3, 0.5, n) if algo == "sgd" else recon.stepsize_vanishing(1.0, 0.02, n)
     upd = recon.pc_update_iters(n)
     obj = torch.zeros(1, dtype=torch.float64, device=case.dev)
+    epoch_fn = {"svrg": pm.pet_svrg_epoch, "saga": pm.pet_saga_epoch, "sgd": pm.pet_sgd_epoch}[algo]
     for e in range(epochs):
         ks = [e * n + j for j in range(n)]
-        pm.pet_svrg_epoch(case.geom, st, x, orders[e], [tau_rule(k) for k in ks], [k in upd for k in ks], obj)
+        epoch_fn(case.geom, st, x, orders[e], [tau_rule(k) for k in ks], [k in upd for k in ks], obj)
     return x.cpu().double().numpy(), float(obj.cpu()), (orders, tau_rule, upd, beta)
 
 
@@ -216,6 +217,28 @@ def test_counts_svrg_reconstruction_parity(case):
     assert obj_cnt == pytest.approx(obj_dense, rel=1e-5)
 
 
+@pytest.mark.parametrize("algo", ["saga", "sgd"])
+def test_counts_saga_sgd_reconstruction_parity(case, algo):
+    # SAGA (table of h_i + (beta/n) grad S, sum from the sensitivity) and SGD
+    # (subset sensitivities in state->ghat_i) on the zero-count-aware path,
+    # against the FP64 oracle's dense iteration and against the GPU's dense
+    # path on the same schedule (eq. (saga), Section 2.1).
+    epochs = case.cfg["epochs"]
+    x_cnt, obj_cnt, (orders, tau_rule, upd, beta) = _svrg(case, True, epochs, algo)
+    x0 = recon.osem_epoch(case.prob, np.ones(case.prob.shape))
+    m0 = float(x0.max())
+    prob = recon.Problem(case.cfg, case.d["y"], case.d["r"], case.d["mult"], beta=beta, gamma=2.0, eps=1e-3 * m0,
+                         alpha=1.0, delta=1e-3 * m0)
+    x_orc = getattr(recon, algo)(prob, x0, epochs, recon.order_rule(orders), tau_rule, upd).ravel()
+    err = _rel(x_cnt, x_orc)
+    print(f"[{case.cfg['name']}] zero-count-aware {algo}, {epochs} epochs: relative L2 {err:.2e}", flush=True)
+    assert err <= 1e-4
+    assert obj_cnt == pytest.approx(prob.objective(x_cnt.reshape(prob.shape)), rel=1e-5)
+    x_dense, obj_dense, _ = _svrg(case, False, epochs, algo)
+    assert _rel(x_cnt, x_dense) <= 1e-4
+    assert obj_cnt == pytest.approx(obj_dense, rel=1e-5)
+
+
 def test_counts_argument_errors(case):
     pm = case.pm
     other = pm.Geometry(case.cfg)
@@ -228,11 +251,15 @@ def test_counts_argument_errors(case):
                                   torch.zeros(1, dtype=torch.float64, device=case.dev))
     n = case.cfg["n_subsets"]
     sens = case.sens_subset(-1)
-    st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=0.1, gamma=2.0, eps=1e-3,
-                             counts=case.counts)
     seq, tau, upd = list(range(n)), [1.0] * n, [True] + [False] * (n - 1)
-    with pytest.raises(pm.PetError, match="dense kernels"):
-        pm.pet_saga_epoch(case.geom, st, case.x.clone(), seq, tau, upd)
+    other_counts = pm.Counts(other, case.y, case.r, case.a)
+    st_other = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=0.1, gamma=2.0, eps=1e-3,
+                                   counts=other_counts)
+    for fn in (pm.pet_svrg_epoch, pm.pet_saga_epoch, pm.pet_sgd_epoch):
+        with pytest.raises(pm.PetError, match="another geometry"):
+            fn(case.geom, st_other, case.x.clone(), seq, tau, upd)
+    del st_other
+    other_counts.close()
     stg = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=0.1, gamma=2.0, eps=1e-3,
                               counts=case.counts, gnorm=True)
     with pytest.raises(pm.PetError, match="gnorm"):
