@@ -35,8 +35,8 @@ PEAK_HBM_GBPS = 8000.0
 # calibrated FETCH_SIZE / WRITE_SIZE counter runs, and its VALU issue fraction
 # (SQ counters), valid for the kernel source with this hash only (reported as
 # null otherwise).
-MEASURED_TRAFFIC = {"c2_tof": (192.0e6, "093b29dd7b4f34aa")}
-MEASURED_VALU = {"c2_tof": (0.63, "093b29dd7b4f34aa")}
+MEASURED_TRAFFIC = {"c2_tof": (234.0e6, "0e64bc8d790e7d0a")}
+MEASURED_VALU = {"c2_tof": (0.79, "0e64bc8d790e7d0a")}
 
 
 def log(msg):
@@ -620,8 +620,8 @@ def main():
         extra = []
         if not args.no_estimators:
             algos.update(svrg_dense=(geom, epoch, False, None),
-                         saga=(geom, make_epoch(pm.pet_saga_epoch), False, None),
-                         sgd=(geom, make_epoch(pm.pet_sgd_epoch), False, None))
+                         saga=(geom, make_epoch(pm.pet_saga_epoch), False, cnt),
+                         sgd=(geom, make_epoch(pm.pet_sgd_epoch), False, cnt))
             # the submitted algorithms, each with its own subset count
             for alg, target in (("ALG1", 25.0), ("ALG2", 25.0), ("ALG3", 24.2)):
                 n_alg = schedules.subsets_for(cfg["n_views"], target)
