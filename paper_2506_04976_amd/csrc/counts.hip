@@ -120,6 +120,24 @@ __device__ __forceinline__ RecGeo rec_geo(const ProjArgs &a, const CountArgs &c,
     }
     r.zA = P.zs * L.dlam;
     r.zB = fmaf(L.lam0, P.zs, P.zb) + (float)PADZ;
+    // Rows whose axial position u would leave the sheet row (cells j, j + 1
+    // for u in [0, rz - 1)) or whose table position would leave the TOF table
+    // carry no weight (zero padding, outside the TOF support): drop them at the
+    // ends, so that the line kernels need no clamps.  Both positions are affine
+    // in the row and evaluated as the kernels do (one correctly rounded FMA,
+    // monotone in the row), so rows between two in-range ends are in range.
+    const float ulim = (float)(a.rz - 1);
+    auto in_range = [&](int i) {
+        const float u = fmaf((float)i, r.zA, r.zB);
+        if (!(u >= 0.f && u < ulim)) return false;
+        if (TOF) {
+            const float pos = fmaf((float)i, r.pA, r.pB);
+            if (!(pos >= 0.f && pos <= c.pos_max)) return false;
+        }
+        return true;
+    };
+    while (r.is <= r.ie && !in_range(r.is)) ++r.is;
+    while (r.is <= r.ie && !in_range(r.ie)) --r.ie;
     return r;
 }
 
@@ -174,15 +192,12 @@ __global__ void __launch_bounds__(256) k_counts_fill(const void *__restrict__ y,
     }
 }
 
-// TOF weight W(d) from the LDS table of W at the NW_TAB + 1 nodes, at table
-// position pos = d / dx + NW/2: linear interpolation between the two nodes
-// around pos (one two-word LDS read); the position is clamped to the table,
-// whose end nodes are 0.
-__device__ __forceinline__ float tof_weight_at(const float *tab, float pos, float pos_max) {
-    pos = __builtin_amdgcn_fmed3f(pos, 0.f, pos_max);
-    const int k = (int)pos;
-    const float w0 = tab[k], w1 = tab[k + 1];
-    return fmaf(__builtin_amdgcn_fractf(pos), w1 - w0, w0);
+// TOF weight W(d) from the LDS table of (W_k, W_{k+1} - W_k) at its NW_TAB
+// nodes, at table position pos = d / dx + NW/2 in [0, pos_max]: linear
+// interpolation between the two nodes around pos (one 8-byte LDS read).
+__device__ __forceinline__ float tof_weight_at(const float2 *tab, float pos) {
+    const float2 t = tab[(int)pos];
+    return fmaf(__builtin_amdgcn_fractf(pos), t.y, t.x);
 }
 
 // Sum over the workgroup, the same value in every thread (wave sums by
@@ -369,33 +384,27 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     const int rz = a.rz;
     float *X = smem;
     unsigned long long *Zu = reinterpret_cast<unsigned long long *>(smem);  // (X's bytes, after phase one)
-    float *tab = smem + c.sheet_floats;
-    float *Qs = tab + (TOF ? c.tab_floats : 0);
+    float2 *tab = reinterpret_cast<float2 *>(smem + c.sheet_floats);
+    float *Qs = smem + c.sheet_floats + (TOF ? c.tab_floats : 0);
     const int64_t i0 = desc.i0, i1 = desc.i0 + desc.n;
     const int hrows = (nrow + 1) >> 1;
     const CountRec none{1, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // no rows, no count
 
     if (TOF) {
         // the table's loads in flight together, eight per thread
-        for (int k0 = threadIdx.x; k0 <= NW_TAB; k0 += 8 * CNT_BLOCK) {
-            float wv[8];
+        static_assert(NW_TAB % (8 * CNT_BLOCK) == 0, "the table load assumes 8 CNT_BLOCK divides NW_TAB");
+        for (int k0 = threadIdx.x; k0 < NW_TAB; k0 += 8 * CNT_BLOCK) {
+            float2 wv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = k0 + u * CNT_BLOCK;
-                wv[u] = k <= NW_TAB ? c.wtab[k] : 0.f;
-            }
+            for (int u = 0; u < 8; ++u) wv[u] = c.wtab[k0 + u * CNT_BLOCK];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = k0 + u * CNT_BLOCK;
-                if (k <= NW_TAB) tab[k] = wv[u];
-            }
+            for (int u = 0; u < 8; ++u) tab[k0 + u * CNT_BLOCK] = wv[u];
         }
     }
     if (nrow > 0) build_x(a, L, nrow, X);
     __syncthreads();
 
     double kl = 0.0;
-    const float umax = (float)(a.nz + PADZ);
     // (a line that misses the image still has bins with counts: ybar = add there,
     // and its y log(y / add) enters the sum; its sample ranges are empty)
     for (int64_t c0 = i0; c0 < i1; c0 += c.q_cap) {
@@ -430,11 +439,11 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             float s = 0.f;
             const float *xr = X + (e.is + ch - L.i_lo) * rz;
             for (float fi = fis; fi <= fie; fi += fC, xr += C * rz) {
-                const float u = __builtin_amdgcn_fmed3f(fmaf(fi, e.zA, e.zB), 0.f, umax);
+                const float u = fmaf(fi, e.zA, e.zB);  // (in [0, rz - 1): the records' rows are cut to it)
                 const int j = (int)u;
                 const float x0 = xr[j], x1 = xr[j + 1];
                 const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
-                s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, e.pA, e.pB), c.pos_max), v, s) : s + v;
+                s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, e.pA, e.pB)), v, s) : s + v;
             }
             // (every lane of the bin ends with the bin's sum)
             for (int o = 1; o < C; o <<= 1) s += __shfl_xor(s, o, 64);
@@ -489,14 +498,14 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
                     unsigned long long *zr = Zu + (r0 - ra) * rz;
                     if (!sgn) {
                         for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
-                            const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
-                            const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                            const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB)) : qsc;
+                            const float u = fmaf(fi, g.zA, g.zB);
                             deposit_pos(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
                         }
                     } else {
                         for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
-                            const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB), c.pos_max) : qsc;
-                            const float u = __builtin_amdgcn_fmed3f(fmaf(fi, g.zA, g.zB), 0.f, umax);
+                            const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB)) : qsc;
+                            const float u = fmaf(fi, g.zA, g.zB);
                             deposit_packed(zr, (int)u, -qw, __builtin_amdgcn_fractf(u));
                         }
                     }
@@ -558,9 +567,7 @@ static size_t counts_sheet_floats(const pet_geom_s *g) {
     return (std::max(x, zu) + 3) & ~(size_t)3;
 }
 
-static size_t counts_tab_floats(const pet_geom_s *g) {
-    return g->d.n_tof > 1 ? ((size_t)NW_TAB + 1 + 3) & ~(size_t)3 : 0;
-}
+static size_t counts_tab_floats(const pet_geom_s *g) { return g->d.n_tof > 1 ? 2 * (size_t)NW_TAB : 0; }
 
 static size_t counts_lds_base(const pet_geom_s *g) {
     return sizeof(float) * (counts_sheet_floats(g) + counts_tab_floats(g));
@@ -568,11 +575,16 @@ static size_t counts_lds_base(const pet_geom_s *g) {
 
 // Bins per chunk with M_GRAD: at most CNT_QCAP, fewer if the LDS cannot hold
 // their factors next to the sheet and the table (0 if less than 256 fit).
+// When at least 256 fit in half a CU's LDS (with 1 KB of static shared
+// memory), the chunk is sized for that, so that two workgroups share a CU.
 static int counts_q_cap(const pet_geom_s *g) {
     const size_t base = counts_lds_base(g) + 1024;
-    if (base >= g->max_lds) return 0;
-    const size_t fit = ((g->max_lds - base) / sizeof(float)) & ~(size_t)3;
-    return fit < 256 ? 0 : (int)std::min<size_t>(fit, CNT_QCAP);
+    for (size_t budget : {(size_t)CU_LDS_BYTES / 2, g->max_lds}) {
+        if (base >= budget) continue;
+        const size_t fit = ((budget - base) / sizeof(float)) & ~(size_t)3;
+        if (fit >= 256) return (int)std::min<size_t>(fit, CNT_QCAP);
+    }
+    return 0;
 }
 
 size_t counts_lds_bytes(const pet_geom_s *g, int mode) {
@@ -587,7 +599,7 @@ int counts_blocks(const pet_counts_s *cs, int subset) {
 // The TOF table's constants (and the TOF bin count) of a geometry.
 static CountArgs count_args(const pet_geom_s *g) {
     CountArgs c{};
-    c.wtab = g->wtabf;
+    c.wtab = g->wtab;
     c.nw = NW_TAB;
     c.sheet_floats = (int)counts_sheet_floats(g);
     c.tab_floats = (int)counts_tab_floats(g);

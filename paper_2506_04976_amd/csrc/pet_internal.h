@@ -111,6 +111,7 @@ static_assert(sizeof(CountRec) == 32, "CountRec layout");
 constexpr int NW_TAB = 4096;    // intervals of the tabulated TOF weight W(d)
 constexpr int CNT_BLOCK = 512;   // threads per workgroup of the counts line kernel
 constexpr int CNT_QCAP = 2048;   // bins per chunk of the counts line kernel (their factors in LDS)
+constexpr int CU_LDS_BYTES = 160 * 1024;  // LDS of one gfx950 CU
 
 // One line with counts as a workgroup of the counts kernel sees it: the
 // line's geometry and the range of its bins in the item array.
@@ -125,7 +126,7 @@ static_assert(sizeof(CountLine) == 48, "CountLine layout");
 struct CountArgs {
     const CountRec *items;
     const CountLine *desc;    // the launch's lines (workgroup b takes desc[b])
-    const float *wtab;        // TOF: W at the table's NW_TAB + 1 nodes
+    const float2 *wtab;       // TOF: (W_k, W_{k+1} - W_k) at the table's NW_TAB nodes
     int sheet_floats, tab_floats;  // LDS layout: sheet region, TOF table (floats)
     int nw, n_tof;
     float wD;                 // support of W: |d| <= wD
