@@ -456,12 +456,15 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             // term at xhat (no extra projection)
             double *so = st->snap_objective;
             for (int q = 0; q < n && e == hipSuccess; ++q) {
-                e = st->counts ? counts_grad_sheets(g, st->counts, q, so, s, q > 0)
-                               : subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, so, q > 0, s);
+                e = st->counts ? counts_grad_sheets(g, st->counts, q, so, s, q > 0, zeroed)
+                               : subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, so, q > 0, s,
+                                                    zeroed);
                 // zero-count-aware tables hold the x-dependent parts; ghat starts from sens
+                // (with fused steps the accumulation also clears the gradient sheets)
                 if (e == hipSuccess)
                     e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s,
-                                              st->counts ? st->sens : nullptr);
+                                              st->counts ? st->sens : nullptr, fuse);
+                zeroed = fuse;
             }
             if (e == hipSuccess && so && st->counts) {
                 // D = <sens, x> + sum r - sum y + sum y log(y / ybar)
@@ -475,7 +478,6 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             // BB bookkeeping: 0 none, 1 keep the full gradient, 2 also recompute the step bound
             const int bb_mode = !st->bb ? 0 : (opt && opt->bb_update && opt->bb_update[j] && k > 0) ? 2 : 1;
             float *grad_out = st->gnorm ? g->num : nullptr;
-            zeroed = false;  // (the gradient sheets hold the last subset's)
             if (e == hipSuccess && fuse && bb_mode < 2) {
                 e = launch_svrg_step_tile(g, cur, st->w, st->beta, st->gamma, st->eps, update_pc[j], st->sens,
                                           st->alpha, st->delta, st->D, 1, st->ghat_i + (size_t)i * nv, st->ghat, w,

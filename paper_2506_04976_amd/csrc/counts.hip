@@ -272,11 +272,19 @@ __device__ __forceinline__ void unpack_cell(unsigned long long w, long long &A, 
 template <bool SIGNED>
 __device__ __forceinline__ float packed_cell_value(const unsigned long long *Zu, int e, int zp, float inv_scale,
                                                    bool finite) {
+    if (!SIGNED) {
+        // nonnegative shares: B <= A in every cell (each sample's rounded
+        // f q <= its rounded q), so A - B + B' < 2^32 in 32-bit arithmetic
+        const unsigned long long w = Zu[e];
+        const uint32_t Bp = zp > 0 ? (uint32_t)(Zu[e - 1] >> 32) : 0u;
+        const uint32_t V = (uint32_t)w - (uint32_t)(w >> 32) + Bp;
+        return finite ? -(float)V * inv_scale : __builtin_nanf("");
+    }
     long long A, B, Ap, Bp = 0;
-    unpack_cell<SIGNED>(Zu[e], A, B);
-    if (zp > 0) unpack_cell<SIGNED>(Zu[e - 1], Ap, Bp);
+    unpack_cell<true>(Zu[e], A, B);
+    if (zp > 0) unpack_cell<true>(Zu[e - 1], Ap, Bp);
     const long long V = A - B + Bp;
-    return finite ? (float)(SIGNED ? V : -V) * inv_scale : __builtin_nanf("");
+    return finite ? (float)V * inv_scale : __builtin_nanf("");
 }
 
 // Readout of the packed sheet rows [lo, hi) of the line (Zu holds them from
@@ -288,7 +296,7 @@ __device__ __forceinline__ void scatter_rows_packed(const ProjArgs &a, const Lin
                                                     const unsigned long long *Zu, float inv_scale, bool finite) {
     const int rz = a.rz;
     float *Gout = L.axis ? a.G1 : a.G0;
-    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    const int other_stride = ((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
     if (rz <= (int)blockDim.x) {
         const SheetWalk w = sheet_walk(rz);
         if (!w.on) return;
@@ -329,7 +337,7 @@ __device__ __forceinline__ void build_x(const ProjArgs &a, const LineP &L, int n
         return;
     }
     const float *T = L.axis ? a.T1 : a.T0;
-    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    const int other_stride = ((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
     const SheetWalk sw = sheet_walk(rz);
     if (!sw.on) return;
     for (int rb = sw.r0; rb < nrow; rb += CNT_SHEET_ROWS * sw.R) {

@@ -404,6 +404,10 @@ extern "C" pet_status pet_geom_create(const pet_geom_desc *desc, pet_geom *out) 
     auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes == 0 ? 16 : bytes) == hipSuccess; };
     g->t0_elems = (size_t)d.nx * (d.ny + 2 * PADA) * rz;
     g->t1_elems = (size_t)d.ny * (d.nx + 2 * PADA) * rz;
+    if (std::max(g->t0_elems, g->t1_elems) >= (size_t)INT32_MAX) {
+        delete g;
+        return fail(PET_E_ARG, "pet_geom_create: image too large for the 32-bit offsets of the line kernels");
+    }
     // line-kernel partials (2 per line) or two per image block (BB dots)
     g->n_partial = std::max<size_t>(2 * (size_t)nl, 2 * (size_t)((g->n_vox + IMG_BLOCK - 1) / IMG_BLOCK)) + 64;
     bool ok = alloc((void **)&g->lines, sizeof(LineP) * nl) && alloc((void **)&g->planes, sizeof(PlaneP) * planes.size()) &&

@@ -473,14 +473,23 @@ __global__ void k_precond(const float *__restrict__ x, const float *__restrict__
 }
 
 // ghat_i = g (data gradient of subset i at the snapshot); ghat (+)= g in FP64.
-__global__ void __launch_bounds__(256) k_snapshot_accum(const float *__restrict__ G0, const float *__restrict__ G1,
+// (clear: the gradient sheets' cells read here are set to zero afterwards, so
+// that the next subset's line kernels need no separate clearing)
+__global__ void __launch_bounds__(256) k_snapshot_accum(float *__restrict__ G0, float *__restrict__ G1,
                                                         float *__restrict__ ghat_i, double *__restrict__ ghat,
                                                         float *__restrict__ gcopy, int nx, int ny, int nz, int rz,
-                                                        int first, const float *__restrict__ base) {
+                                                        int first, const float *__restrict__ base, int clear) {
     extern __shared__ float tile[];
     const int x0 = blockIdx.x * TT, iy = blockIdx.y;
     const int w = min(TT, nx - x0);
     sheets_to_tile(G0, G1, tile, x0, w, iy, nx, ny, nz, rz);
+    if (clear)
+        for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
+            const int xx = e / nz, z = e - xx * nz;
+            const int ix = x0 + xx;
+            G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] = 0.f;
+            G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ] = 0.f;
+        }
     for (int e = threadIdx.x; e < nz * TT; e += blockDim.x) {
         const int z = e / TT, xx = e - z * TT;
         if (xx >= w) continue;
@@ -1038,7 +1047,7 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
 }
 
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
-                                 hipStream_t s, const float *base) {
+                                 hipStream_t s, const float *base, int clear) {
     if (g->psf_passes) {
         hipError_t e = launch_from_sheets(g, ghat_i, 0, s);
         if (e != hipSuccess) return e;
@@ -1047,7 +1056,7 @@ hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *gha
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_snapshot_accum, tile_grid(g), dim3(256), tile_lds(g), s, g->G0, g->G1, ghat_i, ghat, gcopy,
-                       g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first, base);
+                       g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first, base, clear);
     return hipGetLastError();
 }
 

@@ -50,18 +50,19 @@ __device__ __forceinline__ SheetWalk sheet_walk(int rz) {
 }
 
 // Row i of a line: the transposed image row it interpolates, at the
-// transaxial position xa = i dxa + xa0 (cell jf, fraction f).
+// transaxial position xa = i dxa + xa0 (cell jf, fraction f).  Offsets are
+// 32-bit: a transposed image holds fewer than 2^31 floats (pet_geom_create).
 struct SheetRow {
-    size_t base;  // offset of (i, jf + PADA, 0) in the transposed image
+    int base;  // offset of (i, jf + PADA, 0) in the transposed image
     float f;
 };
 
-__device__ __forceinline__ SheetRow sheet_row(const LineP &L, int i, size_t other_stride, int rz) {
+__device__ __forceinline__ SheetRow sheet_row(const LineP &L, int i, int other_stride, int rz) {
     SheetRow s;
     const float xa = fmaf((float)i, L.dxa, L.xa0);
     const float jf = floorf(xa);
     s.f = xa - jf;
-    s.base = (size_t)i * other_stride + (size_t)(((int)jf + PADA) * rz);
+    s.base = i * other_stride + ((int)jf + PADA) * rz;
     return s;
 }
 
@@ -79,7 +80,7 @@ __device__ __forceinline__ void build_sheets(const ProjArgs &a, const LineP &L, 
     const int n = nrow * rz;
     if (NEED_X) {
         const float *T = L.axis ? a.T1 : a.T0;
-        const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+        const int other_stride = ((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
         if (rz <= (int)blockDim.x) {
             const SheetWalk w = sheet_walk(rz);
             if (w.on) {
@@ -130,7 +131,7 @@ __device__ __forceinline__ void scatter_sheet(const ProjArgs &a, const LineP &L,
                                               int64_t g_off = 0) {
     const int rz = a.rz;
     float *Gout = (L.axis ? a.G1 : a.G0) + g_off;
-    const size_t other_stride = (size_t)((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
+    const int other_stride = ((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
     if (rz <= (int)blockDim.x) {
         const SheetWalk w = sheet_walk(rz);
         if (!w.on) return;

@@ -355,8 +355,10 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
                            float delta, float *D, int first, const float *gi, float *table_i, double *table_sum,
                            float n_sub, float tau, float *x_out, hipStream_t s);
 // ghat_i <- the gradient sheets' image; ghat (+)= it in FP64 (first: ghat = base + it, base nullable)
+// clear (only without a resolution model): zero the gradient sheets' cells
+// after reading them
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
-                                 hipStream_t s, const float *base = nullptr);
+                                 hipStream_t s, const float *base = nullptr, int clear = 0);
 // FP64 dot product into *out (accumulate: add), through `partial`
 int dot_blocks(int64_t n);
 hipError_t launch_dot(const float *a, const float *b, int64_t n, double *partial, double *out, int accumulate,
