@@ -603,7 +603,7 @@ def main():
         nb, nl, _ = geom.info(i)
         hbm += nb * (y.element_size() + 4) + nl * 4 + 4 * geom.n_vox * 2
         items += cnt.info(i)[0]
-    compulsory = 16.0 * items + 4 * geom.n_vox * 2 * len(launched)
+    compulsory = 32.0 * items + 4 * geom.n_vox * 2 * len(launched)  # 32-byte records, image in, gradient out
     import hashlib
     src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_2506_04976_amd", "csrc", "counts.hip"),
                                    "rb").read()).hexdigest()[:16]
@@ -700,6 +700,9 @@ def main():
                      "avg_launch_ms": grad_ms / grad_launches, "launches": grad_launches,
                      "algorithmic_bytes_per_launch": hbm / grad_launches,
                      "compulsory_bytes_per_launch": compulsory / grad_launches,
+                     # what the counters saw per launch, as a rate against the same peak
+                     "traffic_frac": (traffic / (grad_s / grad_launches) / 1e9 / PEAK_HBM_GBPS
+                                      if traffic is not None else None),
                      "valu_issue": valu},
         "dense_path": {"value": args.steps / elapsed_d, "unit": "epochs/s",
                        "kernel": "k_line_tof<M_GRAD> (fused dense subset gradient)",
