@@ -365,52 +365,61 @@ __global__ void __launch_bounds__(STEP_BLOCK) k_step_tile(RdpArgs a, float *__re
     const int x0 = blockIdx.x * TT, iy = blockIdx.y;
     const int w = min(TT, nx - x0);
     const int hz = nz + 2, hx = TT + 2;
-    // halo of the iterate (outside the grid: 0, masked out by the sums);
-    // TILE_UNROLL loads per thread in flight before their LDS writes
-    const int nh = 3 * hz * hx;
-    for (int e0 = threadIdx.x; e0 < nh; e0 += TILE_UNROLL * blockDim.x) {
-        float val[TILE_UNROLL];
+    // halo of the iterate (outside the grid: 0, masked out by the sums):
+    // thread t takes column t mod hx of every (blockDim / hx)-th row of each
+    // y slice, TILE_UNROLL loads in flight before their LDS writes
+    {
+        const int RS = (int)blockDim.x / hx;
+        const int c = (int)threadIdx.x % hx, r0 = (int)threadIdx.x / hx;
+        const int x = x0 + c - 1;
+        const bool xin = x >= 0 && x < nx;
+        if (r0 < RS)
+            for (int dy = 0; dy < 3; ++dy) {
+                const int y = iy + dy - 1;
+                const bool yin = xin && y >= 0 && y < ny;
+                for (int zz0 = r0; zz0 < hz; zz0 += TILE_UNROLL * RS) {
+                    float val[TILE_UNROLL];
 #pragma unroll
-        for (int u = 0; u < TILE_UNROLL; ++u) {
-            const int e = e0 + u * blockDim.x;
-            const int dy = e / (hz * hx);
-            const int rem = e - dy * hz * hx;
-            const int zz = rem / hx;
-            const int z = zz - 1, x = x0 + rem - zz * hx - 1, y = iy + dy - 1;
-            val[u] = e < nh && y >= 0 && y < ny && z >= 0 && z < nz && x >= 0 && x < nx
-                         ? a.x[((size_t)z * ny + y) * nx + x]
-                         : 0.f;
-        }
+                    for (int u = 0; u < TILE_UNROLL; ++u) {
+                        const int z = zz0 + u * RS - 1;
+                        val[u] = yin && z >= 0 && z < nz ? a.x[(z * ny + y) * nx + x] : 0.f;
+                    }
 #pragma unroll
-        for (int u = 0; u < TILE_UNROLL; ++u) {
-            const int e = e0 + u * blockDim.x;
-            if (e < nh) halo[e] = val[u];
-        }
+                    for (int u = 0; u < TILE_UNROLL; ++u) {
+                        const int zz = zz0 + u * RS;
+                        if (zz < hz) halo[(dy * hz + zz) * hx + c] = val[u];
+                    }
+                }
+            }
     }
-    if (reads_gi<F>()) {
+    // the sheets' cells of the tile: thread t takes axial cell t mod nz of
+    // every (blockDim / nz)-th column (z-contiguous reads and writes)
+    const int CS = (int)blockDim.x / nz;
+    const int zq = (int)threadIdx.x % nz, xq = (int)threadIdx.x / nz;
+    const bool col_on = xq < CS;
+    const int g1row = (iy * (nx + 2 * PADA) + PADA) * rz + zq + PADZ;  // G1/T1 cell (iy, x0 + xx)
+    const int g0col = (iy + PADA) * rz + zq + PADZ;                    // G0/T0 cell (x0 + xx, iy)
+    const int g0stride = (ny + 2 * PADA) * rz;
+    if (reads_gi<F>() && col_on) {
         // the subset's gradient, then zero cells for the next subset
-        for (int e0 = threadIdx.x; e0 < w * nz; e0 += TILE_UNROLL * blockDim.x) {
+        for (int xx0 = xq; xx0 < w; xx0 += TILE_UNROLL * CS) {
             float ga[TILE_UNROLL], gb[TILE_UNROLL];
 #pragma unroll
             for (int u = 0; u < TILE_UNROLL; ++u) {
-                const int e = e0 + u * blockDim.x;
-                const int xx = e / nz, z = e - xx * nz;
-                const int ix = x0 + xx;
+                const int xx = xx0 + u * CS, ix = x0 + xx;
                 ga[u] = gb[u] = 0.f;
-                if (e < w * nz) {
-                    ga[u] = G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ];
-                    gb[u] = G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ];
+                if (xx < w) {
+                    ga[u] = G1[g1row + ix * rz];
+                    gb[u] = G0[g0col + ix * g0stride];
                 }
             }
 #pragma unroll
             for (int u = 0; u < TILE_UNROLL; ++u) {
-                const int e = e0 + u * blockDim.x;
-                if (e >= w * nz) continue;
-                const int xx = e / nz, z = e - xx * nz;
-                const int ix = x0 + xx;
-                tile[z * (TT + 1) + xx] = ga[u] + gb[u];
-                G1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] = 0.f;
-                G0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ] = 0.f;
+                const int xx = xx0 + u * CS, ix = x0 + xx;
+                if (xx >= w) continue;
+                tile[zq * (TT + 1) + xx] = ga[u] + gb[u];
+                G1[g1row + ix * rz] = 0.f;
+                G0[g0col + ix * g0stride] = 0.f;
             }
         }
     }
@@ -454,13 +463,13 @@ __global__ void __launch_bounds__(STEP_BLOCK) k_step_tile(RdpArgs a, float *__re
         tile[z * (TT + 1) + xx] = rdp_finish<F>(a, v, xi, g, h, sv, gi, val, pq, qdq);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
-        const int xx = e / nz, z = e - xx * nz;
-        const float val = tile[z * (TT + 1) + xx];
-        const int ix = x0 + xx;
-        T0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ] = val;
-        T1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] = val;
-    }
+    if (col_on)
+        for (int xx = xq; xx < w; xx += CS) {
+            const float val = tile[zq * (TT + 1) + xx];
+            const int ix = x0 + xx;
+            T0[g0col + ix * g0stride] = val;
+            T1[g1row + ix * rz] = val;
+        }
 }
 
 __global__ void k_precond(const float *__restrict__ x, const float *__restrict__ sens, const float *__restrict__ hess,
