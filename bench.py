@@ -35,8 +35,8 @@ PEAK_HBM_GBPS = 8000.0
 # calibrated FETCH_SIZE / WRITE_SIZE counter runs, and its VALU issue fraction
 # (SQ counters), valid for the kernel source with this hash only (reported as
 # null otherwise).
-MEASURED_TRAFFIC = {"c2_tof": (235.1e6, "3be97cd6c4afd2de")}
-MEASURED_VALU = {"c2_tof": (0.67, "3be97cd6c4afd2de")}
+MEASURED_TRAFFIC = {"c2_tof": (234.8e6, "5ac3f37f5f4d562b")}
+MEASURED_VALU = {"c2_tof": (0.72, "5ac3f37f5f4d562b")}
 
 
 def log(msg):

@@ -444,15 +444,31 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             const CountRec e = act ? c.items[it] : none;
             // rows as floats (exact integers): no conversion per sample
             const float fis = (float)(e.is + ch), fie = (float)e.ie;
-            float s = 0.f;
+            // two samples per iteration (their LDS reads in flight together,
+            // two partial sums), then the odd one; u stays in [0, rz - 1)
+            // (the records' rows are cut to it)
+            float s = 0.f, s1 = 0.f;
             const float *xr = X + (e.is + ch - L.i_lo) * rz;
-            for (float fi = fis; fi <= fie; fi += fC, xr += C * rz) {
-                const float u = fmaf(fi, e.zA, e.zB);  // (in [0, rz - 1): the records' rows are cut to it)
+            const int step = C * rz;
+            float fi = fis;
+            for (; fi + fC <= fie; fi += 2.f * fC, xr += 2 * step) {
+                const float fj = fi + fC;
+                const float u0 = fmaf(fi, e.zA, e.zB), u1 = fmaf(fj, e.zA, e.zB);
+                const int j0 = (int)u0, j1 = (int)u1;
+                const float a0 = xr[j0], b0 = xr[j0 + 1], a1 = xr[step + j1], b1 = xr[step + j1 + 1];
+                const float v0 = fmaf(__builtin_amdgcn_fractf(u0), b0 - a0, a0);
+                const float v1 = fmaf(__builtin_amdgcn_fractf(u1), b1 - a1, a1);
+                s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, e.pA, e.pB)), v0, s) : s + v0;
+                s1 = TOF ? fmaf(tof_weight_at(tab, fmaf(fj, e.pA, e.pB)), v1, s1) : s1 + v1;
+            }
+            if (fi <= fie) {
+                const float u = fmaf(fi, e.zA, e.zB);
                 const int j = (int)u;
                 const float x0 = xr[j], x1 = xr[j + 1];
                 const float v = fmaf(__builtin_amdgcn_fractf(u), x1 - x0, x0);
                 s = TOF ? fmaf(tof_weight_at(tab, fmaf(fi, e.pA, e.pB)), v, s) : s + v;
             }
+            s += s1;
             // (every lane of the bin ends with the bin's sum)
             for (int o = 1; o < C; o <<= 1) s += __shfl_xor(s, o, 64);
             const float ybar = fmaf(e.me, s, e.add);
@@ -505,7 +521,18 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
                     const float fis = (float)r0, fie = (float)r1;
                     unsigned long long *zr = Zu + (r0 - ra) * rz;
                     if (!sgn) {
-                        for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                        // (two samples per iteration, as forward)
+                        const int step = C * rz;
+                        float fi = fis;
+                        for (; fi + fC <= fie; fi += 2.f * fC, zr += 2 * step) {
+                            const float fj = fi + fC;
+                            const float qw0 = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB)) : qsc;
+                            const float qw1 = TOF ? qsc * tof_weight_at(tab, fmaf(fj, g.pA, g.pB)) : qsc;
+                            const float u0 = fmaf(fi, g.zA, g.zB), u1 = fmaf(fj, g.zA, g.zB);
+                            deposit_pos(zr, (int)u0, qw0, __builtin_amdgcn_fractf(u0));
+                            deposit_pos(zr + step, (int)u1, qw1, __builtin_amdgcn_fractf(u1));
+                        }
+                        if (fi <= fie) {
                             const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB)) : qsc;
                             const float u = fmaf(fi, g.zA, g.zB);
                             deposit_pos(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
