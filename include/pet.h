@@ -216,6 +216,17 @@ pet_status pet_subset_grad_counts(pet_geom g, pet_counts c, int subset, const fl
 pet_status pet_objective_counts(pet_geom g, pet_counts c, const float *x, const float *sens, const float *kappa,
                                 const float w[27], float beta, float gamma, float eps, double *out, void *stream);
 
+/* pet_osem_epoch from the compacted bins (Section 3.1 initialisation): for
+ * each subset i in order[] (host array of n_subsets entries),
+ * x <- x * P_i^T(mult y / ybar) / P_i^T mult, where only bins with y > 0 enter
+ * the numerator (the others add 0 to it).  mult is the LOR array the counts
+ * were made with (nullable: 1); it enters P_i^T mult, which on a TOF geometry
+ * is computed with the bins' weights summed per sample.  Voxels with
+ * P_i^T mult = 0 keep x.  xmax_out (device float, nullable) receives max(x)
+ * after the epoch.  PET_E_ARG if c was made for another geometry. */
+pet_status pet_osem_epoch_counts(pet_geom g, pet_counts c, float *x, const float *mult, const int32_t *order,
+                                 float *xmax_out, void *stream);
+
 /* Relative difference prior (eq. (rdp)) and its derivatives (Appendix A),
  * scaled by beta: grad_out = beta dS/dx, hessdiag_out = beta d2S/dx2 (nullable),
  * value_out = beta S (device double, nullable).  w[27]: weight of neighbour

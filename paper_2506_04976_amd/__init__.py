@@ -8,6 +8,7 @@ from ._lib import (  # noqa: F401
     pet_subset_grad, pet_subset_grad_noalloc, pet_svrg_epoch, pet_saga_epoch, pet_sgd_epoch, pet_work_counts, PET_KERNEL_GRAD,
     PET_KERNEL_FWD, PET_KERNEL_BACK, rdp_weights27, y_dtype_code, pet_subset_hvp, pet_rdp_hvp, pet_precond_vjp, pet_svrg_epoch_vjp, VjpBuffers,
     PET_KERNEL_HVP, Batch, PET_CHECK, PET_SMALL_CHUNKS, PET_SIGNED_SHEETS, pet_geom_set_flags, Counts, pet_subset_grad_counts, pet_objective_counts,
+    pet_osem_epoch_counts,
     PET_KERNEL_COUNTS, PET_KERNEL_GATHER, PET_BACK_GATHER,
 )
 from .unrolled import UnrolledProblem, UnrolledSVRG, unrolled_svrg  # noqa: F401

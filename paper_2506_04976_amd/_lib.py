@@ -37,7 +37,7 @@ EXPORTS = ["pet_geom_create", "pet_geom_destroy", "pet_geom_info", "pet_fwd", "p
            "pet_batch_set_launch",
            "pet_work_counts", "pet_profile_enable", "pet_profile_read", "pet_geom_set_flags",
            "pet_counts_create", "pet_counts_destroy", "pet_counts_info", "pet_subset_grad_counts",
-           "pet_objective_counts", "pet_last_error"]
+           "pet_objective_counts", "pet_osem_epoch_counts", "pet_last_error"]
 PET_KERNEL_FWD, PET_KERNEL_BACK, PET_KERNEL_GRAD, PET_KERNEL_EM, PET_KERNEL_OBJ = range(5)
 PET_KERNEL_HVP = 6
 PET_KERNEL_COUNTS = 7
@@ -138,6 +138,7 @@ def lib():
         L.pet_counts_info.argtypes = [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.pet_subset_grad_counts.argtypes = [P, P, I, P, P, P, P, P]
         L.pet_objective_counts.argtypes = [P, P, P, P, P, ctypes.POINTER(F), F, F, F, P, P]
+        L.pet_osem_epoch_counts.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_int32), P, P]
         L.pet_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
@@ -471,6 +472,17 @@ def pet_subset_grad_counts(geom, counts, subset, x, sens_subset, grad_out, kl_ou
                                         _ptr(grad_out, torch.float32, geom.n_vox, "grad_out"),
                                         _ptr(kl_out, torch.float64, 1, "kl_out"), _stream(stream)))
     return grad_out
+
+
+def pet_osem_epoch_counts(geom, counts, x, mult, order, xmax_out=None, stream=None):
+    order = [int(v) for v in order]
+    if len(order) != geom.n_subsets:
+        raise ValueError("order must list every subset once per epoch")
+    arr = (ctypes.c_int32 * len(order))(*order)
+    _check(lib().pet_osem_epoch_counts(geom.handle, counts.handle, _ptr(x, torch.float32, geom.n_vox, "x"),
+                                       _ptr(mult, torch.float32, geom.n_lors, "mult"), arr,
+                                       _ptr(xmax_out, torch.float32, 1, "xmax_out"), _stream(stream)))
+    return x
 
 
 def pet_objective_counts(geom, counts, x, sens, kappa, w27, beta, gamma, eps, out, stream=None):

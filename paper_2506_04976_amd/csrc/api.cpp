@@ -835,6 +835,40 @@ extern "C" pet_status pet_subset_grad_counts(pet_geom g, pet_counts c, int subse
     return hip_check(e, "pet_subset_grad_counts");
 }
 
+extern "C" pet_status pet_osem_epoch_counts(pet_geom g, pet_counts c, float *x, const float *mult,
+                                            const int32_t *order, float *xmax_out, void *stream) {
+    if (!g || !c || !x || !order) return fail(PET_E_ARG, "pet_osem_epoch_counts: null argument");
+    if (c->g != g) return fail(PET_E_ARG, "pet_osem_epoch_counts: counts were made for another geometry");
+    for (int j = 0; j < g->d.n_subsets; ++j)
+        if (order[j] < 0 || order[j] >= g->d.n_subsets)
+            return fail(PET_E_ARG, "pet_osem_epoch_counts: order entry out of range");
+    hipStream_t s = (hipStream_t)stream;
+    if (checking(g)) {
+        int64_t nl = 0;
+        pet_geom_info(g, -1, nullptr, &nl, nullptr);
+        const pet_status cs = check_domain(g->check_counts, s, "pet_osem_epoch_counts", nullptr, 0,
+                                           {{x, CHK_NONNEG, g->n_vox, MSG_X}, {mult, CHK_NONNEG, nl, MSG_MULT}});
+        if (cs != PET_OK) return cs;
+    }
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < g->d.n_subsets && e == hipSuccess; ++j) {
+        const int i = order[j];
+        // P_i^T mult
+        e = launch_zero_sheets(g, s);
+        ProjArgs a = base_args(g, i);
+        a.mult = mult;
+        if (e == hipSuccess) e = launch_line_kernel(g, M_BACK, i, a, s);
+        if (e == hipSuccess) e = launch_from_sheets(g, g->sensi, 0, s);
+        // -P_i^T (mult y / ybar) from the bins with counts; the update negates
+        if (e == hipSuccess) e = launch_to_sheets(g, x, s);
+        if (e == hipSuccess) e = counts_grad_sheets(g, c, i, nullptr, s);
+        if (e == hipSuccess) e = launch_from_sheets(g, g->num, 0, s);
+        if (e == hipSuccess) e = launch_osem_update(g, x, g->num, g->sensi, s, -1.f);
+    }
+    if (e == hipSuccess && xmax_out) e = launch_max(g, x, xmax_out, s);
+    return hip_check(e, "pet_osem_epoch_counts");
+}
+
 extern "C" pet_status pet_objective_counts(pet_geom g, pet_counts c, const float *x, const float *sens,
                                            const float *kappa, const float w[27], float beta, float gamma, float eps,
                                            double *out, void *stream) {

@@ -624,11 +624,13 @@ __global__ void __launch_bounds__(1024) k_subset_norms(const float *__restrict__
     }
 }
 
+// x <- x * (sgn num) / sens where sens > 0 (sgn = -1: num holds the negated
+// ratio backprojection of the zero-count-aware kernels)
 __global__ void k_osem_update(float *__restrict__ x, const float *__restrict__ num, const float *__restrict__ sens,
-                              int64_t n) {
+                              int64_t n, float sgn) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         float s = sens[v];
-        if (s > 0.f) x[v] = x[v] * num[v] / s;
+        if (s > 0.f) x[v] = x[v] * (sgn * num[v]) / s;
     }
 }
 
@@ -1074,8 +1076,9 @@ hipError_t launch_reduce_sum(const double *partial, int n, double *out, int accu
     return hipGetLastError();
 }
 
-hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s) {
-    hipLaunchKernelGGL(k_osem_update, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, num, sens, g->n_vox);
+hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s,
+                              float sgn) {
+    hipLaunchKernelGGL(k_osem_update, grid_for(g->n_vox), dim3(IMG_BLOCK), 0, s, x, num, sens, g->n_vox, sgn);
     return hipGetLastError();
 }
 

@@ -92,6 +92,9 @@ struct ProjArgs {
     // line kernels: workgroup b takes line order[b], the launch's lines
     // longest first (the hardware dispatches workgroups in index order)
     const int *order;
+    // non-TOF line kernel, M_BACK on a TOF geometry: each sample weighted by
+    // the sum of its TOF bins' weights (the backprojection of mult alone)
+    int tof_fold;
 };
 
 // ---- zero-count-aware data term (counts.hip) --------------------------------
@@ -308,7 +311,8 @@ hipError_t launch_rdp(const pet_geom_s *g, const float *x, const float *kappa, c
 hipError_t launch_precond(const pet_geom_s *g, const float *x, const float *sens, const float *hess,
                           float alpha, float delta, float *D, hipStream_t s);
 hipError_t launch_reduce_sum(const double *partial, int n, double *out, int accumulate, hipStream_t s);
-hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s);
+hipError_t launch_osem_update(const pet_geom_s *g, float *x, const float *num, const float *sens, hipStream_t s,
+                              float sgn = 1.f);
 hipError_t launch_max(const pet_geom_s *g, const float *x, float *out, hipStream_t s);
 // domain checks (debug mode, PET_CHECK): count violations of a condition
 enum DomainKind {

@@ -75,6 +75,30 @@ __device__ __forceinline__ int cut_count(float e, float len, float lam0, float d
 // Non-TOF: threads over planes (dense), one line per workgroup.
 // One transaxial line (all its planes) of a non-TOF geometry, by the whole
 // workgroup; returns this thread's FP64 partial (KL or sample count).
+__device__ __forceinline__ float clamped_erf(float u, float inv_s, float c) {
+    return erff(fminf(fmaxf(u * inv_s, -c), c));
+}
+
+// Sum over all TOF bins of the weights of a sample at signed distance t from
+// the LOR centre.  The bins [t_b - w/2, t_b + w/2] tile [lo, hi] = [t_first -
+// w/2, t_last + w/2] without gaps, so the sum of 1/2 [E(t_b + w/2 - t) -
+// E(t_b - w/2 - t)] telescopes to 1/2 [E(hi - t) - E(lo - t)]; where both
+// ends are clamped (t at least nsig sigma inside [lo, hi]) it is erf(c).
+struct TofFold {
+    float lo, hi, inv_s, c, inside;
+};
+
+__device__ __forceinline__ TofFold tof_fold_of(const TofTable &T) {
+    const float h = T.half_bin;
+    return {T.tb[0] - h, T.tb[T.n_tof - 1] + h, T.inv_sqrt2_sigma, T.erf_clamp, erff(T.erf_clamp)};
+}
+
+__device__ __forceinline__ float tof_fold_weight(const TofFold &f, float t) {
+    const float e1 = (f.hi - t) * f.inv_s, e0 = (f.lo - t) * f.inv_s;
+    if (e1 >= f.c && e0 <= -f.c) return f.inside;
+    return 0.5f * (erff(fminf(fmaxf(e1, -f.c), f.c)) - erff(fminf(fmaxf(e0, -f.c), f.c)));
+}
+
 template <int MODE>
 __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, float *smem, int64_t g_off = 0) {
     constexpr bool NEED_X = MODE != M_BACK && MODE != M_COUNT;
@@ -155,12 +179,27 @@ __device__ __forceinline__ double line_nt_body(const ProjArgs &a, int line, floa
         }
         if constexpr (NEED_Z) {
             double *zr = Z + (is + ch - L.i_lo) * rz;
-            for (int i = is + ch; i <= ie; i += cc, zr += cc * rz) {
-                const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
-                const int j = (int)u;
-                const float a1 = Q * __builtin_amdgcn_fractf(u);
-                atomicAdd(&zr[j], (double)(Q - a1));
-                atomicAdd(&zr[j + 1], (double)a1);
+            if (MODE == M_BACK && a.tof_fold) {
+                // TOF: sample i at t = (lambda(i) - 1/2) |u| carries the sum of
+                // its bins' weights (uniform branch)
+                const TofFold F = tof_fold_of(a.tof);
+                for (int i = is + ch; i <= ie; i += cc, zr += cc * rz) {
+                    const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+                    const int j = (int)u;
+                    const float t = (fmaf((float)i, L.dlam, L.lam0) - 0.5f) * len;
+                    const float q = Q * tof_fold_weight(F, t);
+                    const float a1 = q * __builtin_amdgcn_fractf(u);
+                    atomicAdd(&zr[j], (double)(q - a1));
+                    atomicAdd(&zr[j + 1], (double)a1);
+                }
+            } else {
+                for (int i = is + ch; i <= ie; i += cc, zr += cc * rz) {
+                    const float u = __builtin_amdgcn_fmed3f(fmaf((float)i, zA, zB), 0.f, umax);
+                    const int j = (int)u;
+                    const float a1 = Q * __builtin_amdgcn_fractf(u);
+                    atomicAdd(&zr[j], (double)(Q - a1));
+                    atomicAdd(&zr[j + 1], (double)a1);
+                }
             }
         }
     }
@@ -190,9 +229,6 @@ __global__ void __launch_bounds__(NT_BLOCK) k_line_nt(ProjArgs a) {
 // lambda and the sheet row follow from q and are the same for all lanes.
 
 // erf of u / (sqrt2 sigma) with the argument clamped to the truncation window.
-__device__ __forceinline__ float clamped_erf(float u, float inv_s, float c) {
-    return erff(fminf(fmaxf(u * inv_s, -c), c));
-}
 
 // Per-wave TOF weight table of one LOR (one segment of the line): lane s
 // computes the cut cuts[s] (rows before interval s in t order) and returns it;
@@ -756,11 +792,25 @@ void set_lds_attr(size_t need) {
     (void)hipGetLastError();
 }
 
+// TOF backprojection of mult alone (the sensitivity P^T mult, no sinogram):
+// with the bins' weights summed per sample, the non-TOF walk does it, one
+// sample loop per LOR instead of one per TOF bin.  Its FP64 gradient sheet
+// (rows_max x rz) is the only LDS it needs, less than the TOF kernels'.
+hipError_t launch_back_fold(const pet_geom_s *g, dim3 grid, const ProjArgs &a0, hipStream_t s) {
+    ProjArgs a = a0;
+    a.tof_fold = 1;
+    const size_t lds = sizeof(double) * (((size_t)g->rows_max * (g->d.nz + 2 * PADZ) + 3) & ~(size_t)3);
+    hipLaunchKernelGGL((k_line_nt<M_BACK>), grid, dim3(g->nt_threads), lds, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_line_kernel_impl(const pet_geom_s *g, int mode, dim3 grid, const ProjArgs &a, hipStream_t s) {
     set_lds_attr(g->lds_bytes);
     switch (mode) {
         case M_FWD: return launch_mode<M_FWD>(g, grid, a, s);
-        case M_BACK: return launch_mode<M_BACK>(g, grid, a, s);
+        case M_BACK:
+            if (g->d.n_tof > 1 && !a.sino) return launch_back_fold(g, grid, a, s);
+            return launch_mode<M_BACK>(g, grid, a, s);
         case M_GRAD: return launch_mode<M_GRAD>(g, grid, a, s);
         case M_EM: return launch_mode<M_EM>(g, grid, a, s);
         case M_OBJ: return launch_mode<M_OBJ>(g, grid, a, s);

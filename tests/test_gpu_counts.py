@@ -177,6 +177,44 @@ def test_counts_objective_parity(case):
     assert float(out.cpu()) == pytest.approx(case.prob.objective(case.x_np.astype(np.float64)), rel=1e-5)
 
 
+def test_counts_osem_epoch_parity(case):
+    # one OSEM epoch from the compacted bins (the numerator from the bins with
+    # counts alone; on TOF geometries P_i^T mult from the summed bin weights),
+    # in a shuffled subset order, against the FP64 oracle's dense epoch and the
+    # GPU's dense epoch
+    pm = case.pm
+    n = case.cfg["n_subsets"]
+    order = [int(v) for v in np.random.default_rng(3).permutation(n)]
+    x = torch.ones(case.geom.n_vox, device=case.dev)
+    xmax = torch.zeros(1, device=case.dev)
+    pm.pet_osem_epoch_counts(case.geom, case.counts, x, case.a, order, xmax)
+    got = x.cpu().double().numpy()
+    ref = recon.osem_epoch(case.prob, np.ones(case.prob.shape), order).ravel()
+    assert _rel(got, ref) <= 1e-5
+    assert float(xmax.cpu()) == float(got.max())
+    xd = torch.ones(case.geom.n_vox, device=case.dev)
+    pm.pet_osem_epoch(case.geom, xd, case.y, case.r, case.a, order, None)
+    assert _rel(got, xd.cpu().double().numpy()) <= 1e-5
+    # a second epoch from there (x no longer uniform)
+    pm.pet_osem_epoch_counts(case.geom, case.counts, x, case.a, order, None)
+    ref2 = recon.osem_epoch(case.prob, ref.reshape(case.prob.shape), order).ravel()
+    assert _rel(x.cpu().double().numpy(), ref2) <= 1e-5
+
+
+def test_counts_osem_epoch_errors(case):
+    pm = case.pm
+    n = case.cfg["n_subsets"]
+    x = torch.ones(case.geom.n_vox, device=case.dev)
+    other = pm.Geometry(case.cfg)
+    try:
+        with pytest.raises(pm.PetError, match="another geometry"):
+            pm.pet_osem_epoch_counts(other, case.counts, x, case.a, list(range(n)))
+    finally:
+        other.close()
+    with pytest.raises(pm.PetError, match="order entry out of range"):
+        pm.pet_osem_epoch_counts(case.geom, case.counts, x, case.a, [n] + list(range(n - 1)))
+
+
 def _svrg(case, counts, epochs, algo="svrg"):
     pm = case.pm
     cfg, n = case.cfg, case.cfg["n_subsets"]

@@ -106,6 +106,25 @@ def test_back_parity(case):
     assert _rel(acc.cpu().numpy(), 2 * case.prob.sens().ravel()) <= 1e-5
 
 
+def test_back_sensitivity_fold(case):
+    # sino = NULL on a TOF geometry: one walk per LOR with the bins' weights
+    # summed per sample (they telescope), against the per-bin backprojection of
+    # an all-ones sinogram, per subset and over all views
+    if case.T == 1:
+        pytest.skip("non-TOF: sino = NULL takes the same kernel")
+    pm = case.pm
+    ones = torch.ones(case.geom.n_bins, device=case.dev)
+    for subset in (-1, 0, case.cfg["n_subsets"] - 1):
+        fold = torch.full((case.geom.n_vox,), float("nan"), device=case.dev)
+        pm.pet_back(case.geom, subset, None, case.a, fold)
+        per_bin = torch.empty(case.geom.n_vox, device=case.dev)
+        pm.pet_back(case.geom, subset, ones, case.a, per_bin)
+        assert _rel(fold.cpu().numpy(), per_bin.cpu().double().numpy()) <= 2e-6
+        if subset >= 0:
+            ref = case.prob.sens_subset(subset).ravel()
+            assert _rel(fold.cpu().numpy(), ref) <= 1e-5
+
+
 def test_back_gather_parity(case):
     # the cell-driven gather adjoint gives the scatter's (sample, weight) pairs:
     # against the oracle (relative L2 <= 1e-5) and against the scatter
