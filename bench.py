@@ -181,7 +181,9 @@ def map_reference(cfg, geom, pm, cnt, sens, beta, eps, delta, x0, max_iter, targ
     # long and short BB lengths: gradients only, since the line search above
     # stops once objective differences fall below the objective's FP32
     # rounding.  The best iterate (lowest KKT residual) is kept; a residual ten
-    # times the best restarts from the best with half the step.
+    # times the best restarts from the best with half the step.  The loop
+    # aims at 0.8 target: the residual is re-evaluated at the end, and two
+    # evaluations at one point differ by the FP32 floor (about 0.6e-6 on C2).
     zt = torch.from_numpy(z).to(dev)
     polish = 0
     if kkt > target and polish_iters > 0:
@@ -208,7 +210,7 @@ def map_reference(cfg, geom, pm, cnt, sens, beta, eps, delta, x0, max_iter, targ
                 zt = best[1].clone()
                 _, gz, _ = grad_z(zt)
                 alpha *= 0.5
-            if best[0] <= target:
+            if best[0] <= 0.8 * target:
                 break
             if polish % 200 == 0:
                 log(f"[bench] BB polishing: {polish} iterations, best KKT {best[0]:.3e}")
