@@ -31,12 +31,13 @@ METRIC = "SVRG epochs/s (fwd+back+RDP), 3D TOF; HBM GB/s vs peak; time to NRMSE<
 
 PEAK_HBM_GBPS = 8000.0
 
-# HBM bytes per launch of the zero-count-aware subset-gradient kernel, from
+# HBM bytes per subset gradient of the zero-count-aware kernel (the counters'
+# sum over its launches divided by the subset gradients they computed), from
 # calibrated FETCH_SIZE / WRITE_SIZE counter runs, and its VALU issue fraction
 # (SQ counters), valid for the kernel source with this hash only (reported as
 # null otherwise).
-MEASURED_TRAFFIC = {"c2_tof": (234.8e6, "5ac3f37f5f4d562b")}
-MEASURED_VALU = {"c2_tof": (0.72, "5ac3f37f5f4d562b")}
+MEASURED_TRAFFIC = {"c2_tof": (237.2e6, "afc40bc26dfba892")}
+MEASURED_VALU = {"c2_tof": (0.75, "afc40bc26dfba892")}
 
 
 def log(msg):
@@ -594,13 +595,22 @@ def main():
     x_max = float(x.max())
     del x_dense, x_rerun, head
 
-    # algorithmic work of the line-kernel launches in the timed region
+    # algorithmic work of the subset gradients in the timed region.  The dense
+    # path launches one per subset; the zero-count-aware path takes a snapshot
+    # pass (all n subsets) in one launch, so its unit is the subset gradient.
     launched = []
+    snapshots = 0
     for e in range(args.warmup, total):
         for j in range(n):
             k = e * n + j
-            launched += list(range(n)) if k % (2 * n) == 0 else [int(orders[e][j])]
-    assert len(launched) == grad_launches == dense_launches, (len(launched), grad_launches, dense_launches)
+            if k % (2 * n) == 0:
+                launched += list(range(n))
+                snapshots += 1
+            else:
+                launched += [int(orders[e][j])]
+    units = len(launched)
+    assert units == dense_launches and grad_launches == units - snapshots * (n - 1), \
+        (units, grad_launches, dense_launches, snapshots)
     # HBM bytes per unit (Section 8(d)'s dense data pass): per bin y (its storage
     # type) + r (FP32), per LOR mult (FP32); plus the image in and the gradient out
     hbm = 0.0
@@ -703,11 +713,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": kernel_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": kernel_gbps / PEAK_HBM_GBPS, "traffic": traffic,
                      "kernel": "k_line_counts<TOF, M_GRAD> (zero-count-aware subset gradient)",
-                     "avg_launch_ms": grad_ms / grad_launches, "launches": grad_launches,
-                     "algorithmic_bytes_per_launch": hbm / grad_launches,
-                     "compulsory_bytes_per_launch": compulsory / grad_launches,
-                     # what the counters saw per launch, as a rate against the same peak
-                     "traffic_frac": (traffic / (grad_s / grad_launches) / 1e9 / PEAK_HBM_GBPS
+                     # per subset gradient: a launch per iteration, one launch for
+                     # all n subsets at a snapshot
+                     "avg_ms_per_subset_gradient": grad_ms / units, "subset_gradients": units,
+                     "launches": grad_launches,
+                     "algorithmic_bytes_per_subset_gradient": hbm / units,
+                     "compulsory_bytes_per_subset_gradient": compulsory / units,
+                     # what the counters saw per subset gradient, as a rate against the same peak
+                     "traffic_frac": (traffic / (grad_s / units) / 1e9 / PEAK_HBM_GBPS
                                       if traffic is not None else None),
                      "valu_issue": valu},
         "dense_path": {"value": args.steps / elapsed_d, "unit": "epochs/s",

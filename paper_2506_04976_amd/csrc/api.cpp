@@ -402,6 +402,23 @@ static pet_status check_epoch_domain(pet_geom g, const pet_svrg_state *st, const
     return cs;
 }
 
+// The per-subset gradient sheets of a one-launch snapshot pass (n pairs of
+// G0 and G1 sizes, about 10 MB per subset on the brain-sized grids), allocated
+// and cleared at first use; the snapshot accumulation clears each interior
+// after reading it.
+static hipError_t counts_slots(pet_geom g, pet_counts_s *c, hipStream_t s) {
+    if (c->slots) return hipSuccess;
+    const int64_t stride = ((int64_t)g->t0_elems + (int64_t)g->t1_elems + 3) & ~(int64_t)3;
+    const int64_t total = stride * g->d.n_subsets;
+    hipError_t e = hipMalloc(&c->slots, sizeof(float) * (size_t)total);
+    if (e != hipSuccess) {
+        c->slots = nullptr;
+        return e;
+    }
+    c->slot_floats = stride;
+    return launch_fill(c->slots, total, 0.f, s);
+}
+
 static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
                                   const float *tau, const uint8_t *update_pc, const pet_svrg_options *opt,
                                   double *objective_out, void *stream, const char *name) {
@@ -455,7 +472,27 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             // with snap_objective, the snapshot's own passes also sum the data
             // term at xhat (no extra projection)
             double *so = st->snap_objective;
-            for (int q = 0; q < n && e == hipSuccess; ++q) {
+            // zero-count-aware with fused steps: the n subset gradients in one
+            // launch over all lines (most counts first, so that no launch ends
+            // on a tail of long lines), each subset into its own pair of
+            // gradient sheets
+            const bool one_launch = st->counts && fuse;
+            if (one_launch) {
+                pet_counts_s *c = st->counts;
+                if (e == hipSuccess) e = counts_slots(g, c, s);
+                ProjArgs a = base_args(g, -1);
+                a.G0 = c->slots;
+                a.G1 = c->slots + g->t0_elems;
+                a.partial = so ? g->partial : nullptr;
+                if (e == hipSuccess) e = launch_line_counts(g, c, M_GRAD, -1, a, s, c->slot_floats);
+                if (e == hipSuccess && so) e = launch_reduce_sum(g->partial, counts_blocks(c, -1), so, 0, s);
+                for (int q = 0; q < n && e == hipSuccess; ++q) {
+                    float *G0q = c->slots + (size_t)q * c->slot_floats;
+                    e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s, st->sens,
+                                              1, G0q, G0q + g->t0_elems);
+                }
+            }
+            for (int q = 0; q < n && e == hipSuccess && !one_launch; ++q) {
                 e = st->counts ? counts_grad_sheets(g, st->counts, q, so, s, q > 0, zeroed)
                                : subset_grad_sheets(g, q, st->y, st->y_dtype, st->add, st->mult, so, q > 0, s,
                                                     zeroed);

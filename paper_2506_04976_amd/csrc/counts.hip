@@ -293,9 +293,10 @@ __device__ __forceinline__ float packed_cell_value(const unsigned long long *Zu,
 // adds NaN to every cell it covers.
 template <bool SIGNED>
 __device__ __forceinline__ void scatter_rows_packed(const ProjArgs &a, const LineP &L, int lo, int hi,
-                                                    const unsigned long long *Zu, float inv_scale, bool finite) {
+                                                    const unsigned long long *Zu, float inv_scale, bool finite,
+                                                    int64_t g_off) {
     const int rz = a.rz;
-    float *Gout = L.axis ? a.G1 : a.G0;
+    float *Gout = (L.axis ? a.G1 : a.G0) + g_off;
     const int other_stride = ((L.axis ? a.nx : a.ny) + 2 * PADA) * rz;
     if (rz <= (int)blockDim.x) {
         const SheetWalk w = sheet_walk(rz);
@@ -547,10 +548,11 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
                 }
             }
             __syncthreads();
+            const int64_t g_off = (int64_t)desc.slot * c.slot_floats;
             if (sgn)
-                scatter_rows_packed<true>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite);
+                scatter_rows_packed<true>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite, g_off);
             else
-                scatter_rows_packed<false>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite);
+                scatter_rows_packed<false>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite, g_off);
             // (before the next half clears the sheet, or the next chunk's X)
             __syncthreads();
         }
@@ -560,7 +562,8 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
 
 // Descriptors of a launch's lines (geometry and item ranges), one per line.
 __global__ void k_counts_desc(const int *__restrict__ lines, int n, const LineP *__restrict__ geo,
-                              const int64_t *__restrict__ line_off, CountLine *__restrict__ desc) {
+                              const int64_t *__restrict__ line_off, const int *__restrict__ view_subset, int n_rad,
+                              CountLine *__restrict__ desc) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int l = lines[k];
@@ -568,7 +571,7 @@ __global__ void k_counts_desc(const int *__restrict__ lines, int n, const LineP 
     d.L = geo[l];
     d.i0 = line_off[l];
     d.n = (int32_t)(line_off[l + 1] - line_off[l]);
-    d.line = l;
+    d.slot = view_subset[l / n_rad];
     desc[k] = d;
 }
 
@@ -647,10 +650,12 @@ static CountArgs count_args(const pet_geom_s *g) {
 }
 
 hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *cs, int mode, int subset, const ProjArgs &a,
-                              hipStream_t s) {
+                              hipStream_t s, int64_t slot_floats) {
     const int nblk = counts_blocks(cs, subset);
     if (nblk == 0) return hipSuccess;
+    if (slot_floats && (subset >= 0 || mode != M_GRAD)) return hipErrorInvalidValue;
     CountArgs c = count_args(g);
+    c.slot_floats = slot_floats;
     c.items = cs->items;
     c.desc = cs->desc + cs->lines_off[subset < 0 ? cs->n_subsets : subset];
     c.q_cap = mode != M_GRAD ? (1 << 30) : (g->flags & PET_SMALL_CHUNKS) ? std::min(16, counts_q_cap(g)) : counts_q_cap(g);
@@ -768,13 +773,21 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
     if (e == hipSuccess && !lines.empty())
         e = hipMemcpy(c->lines, lines.data(), sizeof(int) * lines.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&c->desc, sizeof(CountLine) * std::max<size_t>(lines.size(), 1));
+    // the subset of each view (the gradient-sheet slot of its lines)
+    std::vector<int> vsub(g->d.n_views, 0);
+    for (int q = 0; q < n; ++q)
+        for (int v : g->subset_views[q]) vsub[v] = q;
+    int *d_vsub = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&d_vsub, sizeof(int) * vsub.size());
+    if (e == hipSuccess) e = hipMemcpy(d_vsub, vsub.data(), sizeof(int) * vsub.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !lines.empty()) {
         const int nl = (int)lines.size();
         hipLaunchKernelGGL(k_counts_desc, dim3((nl + 255) / 256), dim3(256), 0, 0, c->lines, nl, g->lines,
-                           c->line_off, c->desc);
+                           c->line_off, d_vsub, g->d.n_rad, c->desc);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (d_vsub) (void)hipFree(d_vsub);
     if (d_cnt) (void)hipFree(d_cnt);
     if (d_ys) (void)hipFree(d_ys);
     if (d_as) (void)hipFree(d_as);
@@ -790,7 +803,7 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
 extern "C" pet_status pet_counts_destroy(pet_counts c) {
     if (!c) return PET_OK;
     (void)hipDeviceSynchronize();
-    void *ptrs[] = {c->items, c->line_off, c->lines, c->desc};
+    void *ptrs[] = {c->items, c->line_off, c->lines, c->desc, c->slots};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;

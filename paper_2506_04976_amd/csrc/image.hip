@@ -1058,7 +1058,8 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
 }
 
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
-                                 hipStream_t s, const float *base, int clear) {
+                                 hipStream_t s, const float *base, int clear, float *G0, float *G1) {
+    if (G0 && g->psf_passes) return hipErrorInvalidValue;  // (the resolution model reads the handle's sheets)
     if (g->psf_passes) {
         hipError_t e = launch_from_sheets(g, ghat_i, 0, s);
         if (e != hipSuccess) return e;
@@ -1066,8 +1067,8 @@ hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *gha
                            first, base);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_snapshot_accum, tile_grid(g), dim3(256), tile_lds(g), s, g->G0, g->G1, ghat_i, ghat, gcopy,
-                       g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first, base, clear);
+    hipLaunchKernelGGL(k_snapshot_accum, tile_grid(g), dim3(256), tile_lds(g), s, G0 ? G0 : g->G0, G1 ? G1 : g->G1,
+                       ghat_i, ghat, gcopy, g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first, base, clear);
     return hipGetLastError();
 }
 

@@ -120,9 +120,9 @@ constexpr int CU_LDS_BYTES = 160 * 1024;  // LDS of one gfx950 CU
 // line's geometry and the range of its bins in the item array.
 struct CountLine {
     LineP L;
-    int64_t i0;  // first item
-    int32_t n;   // items
-    int32_t line;
+    int64_t i0;    // first item
+    int32_t n;     // items
+    int32_t slot;  // subset of the line's view: its gradient sheets in a launch over all subsets
 };
 static_assert(sizeof(CountLine) == 48, "CountLine layout");
 
@@ -136,6 +136,7 @@ struct CountArgs {
     float inv_dx, pos0, pos_max;  // table position of d: d * inv_dx + pos0, clamped to [0, pos_max]
     int q_cap;                // bins per chunk of a line (their factors Q are kept in LDS)
     int force_signed;         // signed fixed-point sheets for every chunk (tests)
+    int64_t slot_floats;      // 0, or the stride of per-subset gradient sheets (G0, G1 + slot * stride)
 };
 
 // ---- batches of reconstructions -------------------------------------------
@@ -248,6 +249,11 @@ struct pet_counts_s {
     std::vector<int64_t> lines_off;        // [n_subsets + 2] offsets into lines
     std::vector<int64_t> items_per_subset; // [n_subsets + 1]
     std::vector<double> sum_y, sum_add;    // [n_subsets + 1] over every bin of the subset (then all)
+    // snapshot passes in one launch: n_subsets pairs of gradient sheets
+    // (G0 then G1 of each, slot_floats apart), allocated at first use, whose
+    // interiors are zero between snapshots
+    float *slots = nullptr;
+    int64_t slot_floats = 0;
 };
 
 namespace pet {
@@ -279,8 +285,10 @@ int n_line_blocks(const pet_geom_s *g, int subset);
 // zero-count-aware line kernels (counts.hip): mode M_GRAD (gradient sheets
 // receive -P^T[mult y / ybar], block partials of sum y log(y / ybar)) or M_OBJ
 // (partials only), over the lines with counts of `subset` (-1: all)
+// slot_floats > 0 (subset -1 only): each line's shares go to the sheets of
+// its view's subset, a.G0 / a.G1 + slot * slot_floats
 hipError_t launch_line_counts(pet_geom_s *g, const pet_counts_s *c, int mode, int subset, const ProjArgs &a,
-                              hipStream_t s);
+                              hipStream_t s, int64_t slot_floats = 0);
 int counts_blocks(const pet_counts_s *c, int subset);
 size_t counts_lds_bytes(const pet_geom_s *g, int mode);
 
@@ -361,8 +369,10 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
 // ghat_i <- the gradient sheets' image; ghat (+)= it in FP64 (first: ghat = base + it, base nullable)
 // clear (only without a resolution model): zero the gradient sheets' cells
 // after reading them
+// (G0, G1: other gradient sheets than the handle's, nullable)
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
-                                 hipStream_t s, const float *base = nullptr, int clear = 0);
+                                 hipStream_t s, const float *base = nullptr, int clear = 0, float *G0 = nullptr,
+                                 float *G1 = nullptr);
 // FP64 dot product into *out (accumulate: add), through `partial`
 int dot_blocks(int64_t n);
 hipError_t launch_dot(const float *a, const float *b, int64_t n, double *partial, double *out, int accumulate,
