@@ -294,7 +294,13 @@ typedef struct {
      * objective_out is computed from the compacted bins.  The iterates equal
      * the dense path's up to rounding.  Not with gnorm (PET_E_ARG).  SAGA and
      * SGD take it too (see pet_saga_epoch); the reverse mode and batches use
-     * the dense kernels (PET_E_ARG if set). */
+     * the dense kernels (PET_E_ARG if set).  Without a kappa image or a
+     * resolution model, a snapshot pass runs as one launch over the lines of
+     * all subsets, each subset into gradient sheets of its own: the first
+     * such epoch allocates n_subsets pairs of sheet-sized buffers (about
+     * 10 MB per subset on a 128x128x71 grid), owned by the counts handle
+     * until pet_counts_destroy; concurrent epochs sharing one counts handle
+     * are not allowed (as for a geometry handle). */
     pet_counts counts;
     /* Objective at the snapshots (nullable device double): every snapshot
      * iteration writes Phi(xhat) = D(A xhat + r, y) + beta S(xhat) in FP64,
