@@ -192,7 +192,10 @@ typedef struct pet_counts_s *pet_counts;
 
 /* Compact the bins with y > 0 of (y, add, mult) for geometry g (full
  * sinograms; add, mult nullable: 0 and 1).  Synchronous; allocates the list
- * and its index on the current device (the inputs may be freed afterwards).
+ * and its index on the current device (the inputs may be freed afterwards),
+ * and, for geometries without a resolution model, n_subsets pairs of
+ * gradient-sheet buffers for one-launch snapshot passes (about 10 MB per
+ * subset on a 128x128x71 grid).
  * PET_E_ARG if the geometry's sheets and TOF table exceed the LDS; PET_E_OOM if
  * device allocation fails. */
 pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, const float *add, const float *mult,
@@ -296,11 +299,9 @@ typedef struct {
      * SGD take it too (see pet_saga_epoch); the reverse mode and batches use
      * the dense kernels (PET_E_ARG if set).  Without a kappa image or a
      * resolution model, a snapshot pass runs as one launch over the lines of
-     * all subsets, each subset into gradient sheets of its own: the first
-     * such epoch allocates n_subsets pairs of sheet-sized buffers (about
-     * 10 MB per subset on a 128x128x71 grid), owned by the counts handle
-     * until pet_counts_destroy; concurrent epochs sharing one counts handle
-     * are not allowed (as for a geometry handle). */
+     * all subsets, each subset into gradient sheets of its own (held by the
+     * counts handle, see pet_counts_create); epochs that share one counts
+     * handle must not overlap in time (as for a geometry handle). */
     pet_counts counts;
     /* Objective at the snapshots (nullable device double): every snapshot
      * iteration writes Phi(xhat) = D(A xhat + r, y) + beta S(xhat) in FP64,

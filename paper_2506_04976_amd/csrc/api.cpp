@@ -402,23 +402,6 @@ static pet_status check_epoch_domain(pet_geom g, const pet_svrg_state *st, const
     return cs;
 }
 
-// The per-subset gradient sheets of a one-launch snapshot pass (n pairs of
-// G0 and G1 sizes, about 10 MB per subset on the brain-sized grids), allocated
-// and cleared at first use; the snapshot accumulation clears each interior
-// after reading it.
-static hipError_t counts_slots(pet_geom g, pet_counts_s *c, hipStream_t s) {
-    if (c->slots) return hipSuccess;
-    const int64_t stride = ((int64_t)g->t0_elems + (int64_t)g->t1_elems + 3) & ~(int64_t)3;
-    const int64_t total = stride * g->d.n_subsets;
-    hipError_t e = hipMalloc(&c->slots, sizeof(float) * (size_t)total);
-    if (e != hipSuccess) {
-        c->slots = nullptr;
-        return e;
-    }
-    c->slot_floats = stride;
-    return launch_fill(c->slots, total, 0.f, s);
-}
-
 static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, const int32_t *subset_seq,
                                   const float *tau, const uint8_t *update_pc, const pet_svrg_options *opt,
                                   double *objective_out, void *stream, const char *name) {
@@ -476,10 +459,9 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
             // launch over all lines (most counts first, so that no launch ends
             // on a tail of long lines), each subset into its own pair of
             // gradient sheets
-            const bool one_launch = st->counts && fuse;
+            const bool one_launch = st->counts && st->counts->slots && fuse;
             if (one_launch) {
                 pet_counts_s *c = st->counts;
-                if (e == hipSuccess) e = counts_slots(g, c, s);
                 ProjArgs a = base_args(g, -1);
                 a.G0 = c->slots;
                 a.G1 = c->slots + g->t0_elems;

@@ -786,6 +786,14 @@ extern "C" pet_status pet_counts_create(pet_geom g, const void *y, int y_dtype, 
                            c->line_off, d_vsub, g->d.n_rad, c->desc);
         e = hipGetLastError();
     }
+    // gradient sheets of a one-launch snapshot pass (n pairs, interiors zero
+    // between snapshots), where the fused step serves the geometry
+    if (e == hipSuccess && step_tile_ok(g)) {
+        const int64_t stride = ((int64_t)g->t0_elems + (int64_t)g->t1_elems + 3) & ~(int64_t)3;
+        e = hipMalloc(&c->slots, sizeof(float) * (size_t)(stride * n));
+        if (e == hipSuccess) e = hipMemset(c->slots, 0, sizeof(float) * (size_t)(stride * n));
+        if (e == hipSuccess) c->slot_floats = stride;
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (d_vsub) (void)hipFree(d_vsub);
     if (d_cnt) (void)hipFree(d_cnt);

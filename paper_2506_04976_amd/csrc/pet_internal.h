@@ -250,8 +250,9 @@ struct pet_counts_s {
     std::vector<int64_t> items_per_subset; // [n_subsets + 1]
     std::vector<double> sum_y, sum_add;    // [n_subsets + 1] over every bin of the subset (then all)
     // snapshot passes in one launch: n_subsets pairs of gradient sheets
-    // (G0 then G1 of each, slot_floats apart), allocated at first use, whose
-    // interiors are zero between snapshots
+    // (G0 then G1 of each, slot_floats apart), allocated at creation where the
+    // fused step serves the geometry (else null), interiors zero between
+    // snapshots
     float *slots = nullptr;
     int64_t slot_floats = 0;
 };
