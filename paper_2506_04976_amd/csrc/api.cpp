@@ -468,11 +468,9 @@ static pet_status svrg_epoch_impl(pet_geom g, pet_svrg_state *st, float *x, cons
                 a.partial = so ? g->partial : nullptr;
                 if (e == hipSuccess) e = launch_line_counts(g, c, M_GRAD, -1, a, s, c->slot_floats);
                 if (e == hipSuccess && so) e = launch_reduce_sum(g->partial, counts_blocks(c, -1), so, 0, s);
-                for (int q = 0; q < n && e == hipSuccess; ++q) {
-                    float *G0q = c->slots + (size_t)q * c->slot_floats;
-                    e = launch_snapshot_accum(g, st->ghat_i + (size_t)q * nv, st->ghat, nullptr, q == 0, s, st->sens,
-                                              1, G0q, G0q + g->t0_elems);
-                }
+                if (e == hipSuccess)
+                    e = launch_snapshot_accum_slots(g, c->slots, c->slots + g->t0_elems, c->slot_floats, n,
+                                                    st->ghat_i, st->ghat, st->sens, s);
             }
             for (int q = 0; q < n && e == hipSuccess && !one_launch; ++q) {
                 e = st->counts ? counts_grad_sheets(g, st->counts, q, so, s, q > 0, zeroed)

@@ -510,6 +510,58 @@ __global__ void __launch_bounds__(256) k_snapshot_accum(float *__restrict__ G0, 
     }
 }
 
+// The snapshot table from a one-launch snapshot pass: for each subset q in
+// turn, its gradient from the q-th pair of sheets (G0, G1 + q stride) into
+// ghat_i[q], those cells zeroed after reading; ghat = base + the n gradients
+// in FP64, added in subset order (as one k_snapshot_accum per subset does)
+// and held in registers over the subsets.  A thread keeps the same voxels of
+// the tile for every subset: at most SNAP_VPT of them (nz TT <= SNAP_VPT 256).
+constexpr int SNAP_VPT = 16;
+
+__global__ void __launch_bounds__(256) k_snapshot_accum_slots(float *__restrict__ G0, float *__restrict__ G1,
+                                                              int64_t stride, int n_sub, float *__restrict__ ghat_i,
+                                                              int64_t nv, double *__restrict__ ghat, int nx, int ny,
+                                                              int nz, int rz, const float *__restrict__ base) {
+    extern __shared__ float tile[];
+    const int x0 = blockIdx.x * TT, iy = blockIdx.y;
+    const int w = min(TT, nx - x0);
+    double acc[SNAP_VPT];
+#pragma unroll
+    for (int u = 0; u < SNAP_VPT; ++u) {
+        const int e = threadIdx.x + u * blockDim.x;
+        const int z = e / TT, xx = e - z * TT;
+        acc[u] = base && e < nz * TT && xx < w ? (double)base[((size_t)z * ny + iy) * nx + x0 + xx] : 0.0;
+    }
+    for (int q = 0; q < n_sub; ++q) {
+        float *g0 = G0 + (size_t)q * stride, *g1 = G1 + (size_t)q * stride;
+        sheets_to_tile(g0, g1, tile, x0, w, iy, nx, ny, nz, rz);
+        for (int e = threadIdx.x; e < w * nz; e += blockDim.x) {
+            const int xx = e / nz, z = e - xx * nz;
+            const int ix = x0 + xx;
+            g1[((size_t)iy * (nx + 2 * PADA) + ix + PADA) * rz + z + PADZ] = 0.f;
+            g0[((size_t)ix * (ny + 2 * PADA) + iy + PADA) * rz + z + PADZ] = 0.f;
+        }
+        float *gq = ghat_i + (size_t)q * nv;
+#pragma unroll
+        for (int u = 0; u < SNAP_VPT; ++u) {
+            const int e = threadIdx.x + u * blockDim.x;
+            const int z = e / TT, xx = e - z * TT;
+            if (e < nz * TT && xx < w) {
+                const float s = tile[z * (TT + 1) + xx];
+                gq[((size_t)z * ny + iy) * nx + x0 + xx] = s;
+                acc[u] += (double)s;
+            }
+        }
+        __syncthreads();  // (before the next subset's tile)
+    }
+#pragma unroll
+    for (int u = 0; u < SNAP_VPT; ++u) {
+        const int e = threadIdx.x + u * blockDim.x;
+        const int z = e / TT, xx = e - z * TT;
+        if (e < nz * TT && xx < w) ghat[((size_t)z * ny + iy) * nx + x0 + xx] = acc[u];
+    }
+}
+
 // SAGA table at the first iteration: the data gradients of every subset are
 // in table (n x nvox); add each subset's prior share (beta / n) grad S(x) and
 // form the table's sum in FP64 from the stored entries.
@@ -1069,6 +1121,22 @@ hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *gha
     }
     hipLaunchKernelGGL(k_snapshot_accum, tile_grid(g), dim3(256), tile_lds(g), s, G0 ? G0 : g->G0, G1 ? G1 : g->G1,
                        ghat_i, ghat, gcopy, g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, first, base, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot_accum_slots(const pet_geom_s *g, float *G0, float *G1, int64_t stride, int n_sub,
+                                       float *ghat_i, double *ghat, const float *base, hipStream_t s) {
+    if (g->psf_passes) return hipErrorInvalidValue;  // (the resolution model reads the handle's sheets)
+    if ((int64_t)g->d.nz * TT > (int64_t)SNAP_VPT * 256) {
+        // taller tiles than a thread's registers hold: one launch per subset
+        hipError_t e = hipSuccess;
+        for (int q = 0; q < n_sub && e == hipSuccess; ++q)
+            e = launch_snapshot_accum(g, ghat_i + (size_t)q * g->n_vox, ghat, nullptr, q == 0, s, base, 1,
+                                      G0 + (size_t)q * stride, G1 + (size_t)q * stride);
+        return e;
+    }
+    hipLaunchKernelGGL(k_snapshot_accum_slots, tile_grid(g), dim3(256), tile_lds(g), s, G0, G1, stride, n_sub, ghat_i,
+                       g->n_vox, ghat, g->d.nx, g->d.ny, g->d.nz, g->d.nz + 2 * PADZ, base);
     return hipGetLastError();
 }
 

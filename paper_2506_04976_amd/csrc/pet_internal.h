@@ -374,6 +374,11 @@ hipError_t launch_sgm_step(const pet_geom_s *g, int estimator, const float *x, c
 hipError_t launch_snapshot_accum(const pet_geom_s *g, float *ghat_i, double *ghat, float *gcopy, int first,
                                  hipStream_t s, const float *base = nullptr, int clear = 0, float *G0 = nullptr,
                                  float *G1 = nullptr);
+// the same for the n_sub pairs of sheets (G0, G1 + q stride) of a one-launch
+// snapshot pass, in one launch: ghat_i[q] for every q, ghat = base + their sum
+// in FP64 (subset order), every pair's cells cleared after reading
+hipError_t launch_snapshot_accum_slots(const pet_geom_s *g, float *G0, float *G1, int64_t stride, int n_sub,
+                                       float *ghat_i, double *ghat, const float *base, hipStream_t s);
 // FP64 dot product into *out (accumulate: add), through `partial`
 int dot_blocks(int64_t n);
 hipError_t launch_dot(const float *a, const float *b, int64_t n, double *partial, double *out, int accumulate,
