@@ -363,24 +363,39 @@ __device__ __forceinline__ void build_x(const ProjArgs &a, const LineP &L, int n
     }
 }
 
+// What phase two needs of a bin: its rows (is and ie as the two 16-bit
+// halves of one word), the affine table and axial positions, and its factor Q.
+struct BinB {
+    uint32_t isie;
+    float pA, pB, zA, zB, Q;
+};
+
+__device__ __forceinline__ BinB bin_b(const CountRec &e, float Q) {
+    return {(uint32_t)(uint16_t)e.is | ((uint32_t)(uint16_t)e.ie << 16), e.pA, e.pB, e.zA, e.zB, Q};
+}
+
+// Rounds of a chunk (bins per thread) that phase two keeps in registers.
+constexpr int CNT_ROUNDS = 4;
+static_assert(CNT_QCAP <= CNT_ROUNDS * CNT_BLOCK, "a chunk takes at most CNT_ROUNDS rounds of one bin per thread");
+
 // One workgroup per line with counts.  MODE M_GRAD: gradient sheets receive
 // -P^T [mult y / ybar]; M_OBJ: no gradient.  Both write the workgroup's FP64
 // sum of y log(y / ybar) when a.partial is set.
 //
 // LDS: one sheet region that holds the image sheet X (nrow x rz floats) while
 // the bins are walked forward, and then the packed gradient sheet of half the
-// rows (ceil(nrow / 2) x rz 64-bit words, the same bytes); the TOF table; the
-// factors Q of a chunk.  About 63 KB on the brain-sized workloads, so that
-// two workgroups share a CU and one's barriers overlap the other's samples.
+// rows (ceil(nrow / 2) x rz 64-bit words, the same bytes); the TOF table.
+// About 71 KB on the brain-sized workloads, so that two workgroups share a CU
+// and one's barriers overlap the other's samples.
 //
 // The line's bins are taken in chunks of at most c.q_cap.  Phase one walks
 // every bin of the chunk forward (ybar, the log term, Q = mult y / ybar ell).
 // With M_GRAD, phase two runs once per half of the rows: it clears the packed
 // sheet, adds the chunk's shares -Q W(t - t_b) (times the axial interpolation
 // weights, scaled by 2^30 / sum |Q|) of the samples in those rows, and reads
-// the half out.  When a chunk has at most one bin per lane group, its bin and
-// Q stay in registers between the phases; otherwise Q goes through LDS and
-// phase two reloads the bins.  A next chunk rebuilds X.
+// the half out.  Each thread keeps what phase two needs of its bins (one per
+// round of the chunk, at most CNT_ROUNDS) and their factors in registers
+// between the phases.  A next chunk rebuilds X.
 template <bool TOF, int MODE>
 __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs c) {
     extern __shared__ float4 smem4[];
@@ -394,7 +409,6 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     float *X = smem;
     unsigned long long *Zu = reinterpret_cast<unsigned long long *>(smem);  // (X's bytes, after phase one)
     float2 *tab = reinterpret_cast<float2 *>(smem + c.sheet_floats);
-    float *Qs = smem + c.sheet_floats + (TOF ? c.tab_floats : 0);
     const int64_t i0 = desc.i0, i1 = desc.i0 + desc.n;
     const int hrows = (nrow + 1) >> 1;
     const CountRec none{1, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // no rows, no count
@@ -431,12 +445,13 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
         const int lc = __builtin_ctz((unsigned)C);
         const int ch = threadIdx.x & (C - 1);
         const int nslot = blockDim.x / C;
-        const bool one_round = n_c <= nslot;  // uniform
         const float fC = (float)C;
         float qabs = 0.f, qneg = 0.f;
-        // one-round chunks: the thread's bin and factor for phase two
-        CountRec ek = none;
-        float Qk = 0.f;
+        // the thread's bins of the chunk's rounds (at most CNT_ROUNDS: C = 1
+        // when a chunk has more bins than the workgroup's threads) and their
+        // factors, for phase two
+        BinB b0 = bin_b(none, 0.f), b1 = b0, b2 = b0, b3 = b0;
+        int rr = 0;
         for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
             // every lane runs every round: the forward sums are added across
             // the C lanes of a bin by shuffles
@@ -481,16 +496,19 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
                     qabs += fabsf(Q);
                     qneg += Q < 0.f ? 1.f : 0.f;
                 }
-                if (one_round) {
-                    ek = e;
-                    Qk = Q;
-                } else if (act && ch == 0) {
-                    Qs[it - c0] = Q;
+                // (a uniform switch keeps every register index static)
+                const BinB b = bin_b(e, Q);
+                switch (rr) {
+                    case 0: b0 = b; break;
+                    case 1: b1 = b; break;
+                    case 2: b2 = b; break;
+                    default: b3 = b; break;
                 }
             }
+            ++rr;
         }
         if (!NEED_Z) continue;  // uniform
-        // (the barrier inside also publishes Qs and ends every read of X)
+        // (the barrier inside also ends every read of X)
         const float2 tot = block_sum_all(make_float2(qabs, qneg), red);
         const float bound = tot.x;
         const bool finite = bound < INFINITY;  // false for inf and NaN
@@ -503,22 +521,20 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             for (int k = threadIdx.x; k < (hi - lo) * rz; k += blockDim.x) Zu[k] = 0ull;
             __syncthreads();
             if (scale > 0.f) {
-                for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
-                    const int64_t it = it0 + threadIdx.x / C;
-                    const bool act = it < c1;
-                    CountRec g;
-                    float qsc;
-                    if (one_round) {
-                        g = ek;
-                        qsc = Qk * scale;
-                    } else {
-                        g = act ? c.items[it] : none;
-                        qsc = act ? Qs[act ? (int)(it - c0) : 0] * scale : 0.f;  // (index < q_cap)
+                for (int q = 0; q < rr; ++q) {  // (uniform)
+                    BinB g;
+                    switch (q) {
+                        case 0: g = b0; break;
+                        case 1: g = b1; break;
+                        case 2: g = b2; break;
+                        default: g = b3; break;
                     }
-                    // this lane's rows g.is + ch + kC that fall in [ra, rb]
-                    int r0 = g.is + ch;
+                    const float qsc = g.Q * scale;
+                    const int gis = (int)(int16_t)(g.isie & 0xffffu), gie = (int)(int16_t)(g.isie >> 16);
+                    // this lane's rows is + ch + kC that fall in [ra, rb]
+                    int r0 = gis + ch;
                     if (r0 < ra) r0 += ((ra - r0 + C - 1) >> lc) << lc;
-                    const int r1 = g.ie < rb ? g.ie : rb;
+                    const int r1 = gie < rb ? gie : rb;
                     const float fis = (float)r0, fie = (float)r1;
                     unsigned long long *zr = Zu + (r0 - ra) * rz;
                     if (!sgn) {
@@ -611,23 +627,14 @@ static size_t counts_lds_base(const pet_geom_s *g) {
     return sizeof(float) * (counts_sheet_floats(g) + counts_tab_floats(g));
 }
 
-// Bins per chunk with M_GRAD: at most CNT_QCAP, fewer if the LDS cannot hold
-// their factors next to the sheet and the table (0 if less than 256 fit).
-// When at least 256 fit in half a CU's LDS (with 1 KB of static shared
-// memory), the chunk is sized for that, so that two workgroups share a CU.
+// Bins per chunk with M_GRAD: CNT_QCAP (their factors live in registers), or
+// 0 if the sheet and the table (with 1 KB of static shared memory) exceed the
+// LDS.
 static int counts_q_cap(const pet_geom_s *g) {
-    const size_t base = counts_lds_base(g) + 1024;
-    for (size_t budget : {(size_t)CU_LDS_BYTES / 2, g->max_lds}) {
-        if (base >= budget) continue;
-        const size_t fit = ((budget - base) / sizeof(float)) & ~(size_t)3;
-        if (fit >= 256) return (int)std::min<size_t>(fit, CNT_QCAP);
-    }
-    return 0;
+    return counts_lds_base(g) + 1024 <= g->max_lds ? CNT_QCAP : 0;
 }
 
-size_t counts_lds_bytes(const pet_geom_s *g, int mode) {
-    return counts_lds_base(g) + (mode == M_GRAD ? sizeof(float) * (size_t)counts_q_cap(g) : 0);
-}
+size_t counts_lds_bytes(const pet_geom_s *g, int) { return counts_lds_base(g); }
 
 int counts_blocks(const pet_counts_s *cs, int subset) {
     const int row = subset < 0 ? cs->n_subsets : subset;

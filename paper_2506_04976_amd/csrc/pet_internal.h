@@ -113,7 +113,7 @@ struct CountRec {
 static_assert(sizeof(CountRec) == 32, "CountRec layout");
 constexpr int NW_TAB = 4096;    // intervals of the tabulated TOF weight W(d)
 constexpr int CNT_BLOCK = 512;   // threads per workgroup of the counts line kernel
-constexpr int CNT_QCAP = 2048;   // bins per chunk of the counts line kernel (their factors in LDS)
+constexpr int CNT_QCAP = 2048;   // bins per chunk of the counts line kernel (four rounds of one bin per thread)
 constexpr int CU_LDS_BYTES = 160 * 1024;  // LDS of one gfx950 CU
 
 // One line with counts as a workgroup of the counts kernel sees it: the
@@ -134,7 +134,7 @@ struct CountArgs {
     int nw, n_tof;
     float wD;                 // support of W: |d| <= wD
     float inv_dx, pos0, pos_max;  // table position of d: d * inv_dx + pos0, clamped to [0, pos_max]
-    int q_cap;                // bins per chunk of a line (their factors Q are kept in LDS)
+    int q_cap;                // bins per chunk of a line (at most CNT_QCAP with M_GRAD)
     int force_signed;         // signed fixed-point sheets for every chunk (tests)
     int64_t slot_floats;      // 0, or the stride of per-subset gradient sheets (G0, G1 + slot * stride)
 };

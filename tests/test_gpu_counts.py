@@ -330,3 +330,45 @@ def test_snapshot_objective(case):
                 got = float(st.snap_objective.cpu())
                 ref = prob.objective(st.x_snap.cpu().double().numpy().reshape(prob.shape))
                 assert got == pytest.approx(ref, rel=1e-5), (counts is not None, e)
+
+
+@pytest.mark.parametrize("n_rings,counts", [(18, 4e7), (20, 5e8)])
+def test_counts_many_bins_per_line(n_rings, counts):
+    # Lines with more bins with counts than the workgroup has threads: phase
+    # two keeps up to four rounds of bins per thread in registers, and a line
+    # with more than 2048 takes a second chunk (the image sheet rebuilt).  A
+    # small TOF geometry with many planes and high counts; the subset gradient
+    # and KL against the FP64 oracle's dense formulas.
+    import paper_2506_04976_amd as pm
+    cfg = configs.get("mini_tof_many", n_rings=n_rings, counts=counts)
+    d = data.make_dataset(cfg)
+    per_line = (d["y"] > 0).reshape(cfg["n_views"], cfg["n_rad"], -1).sum(-1)
+    assert per_line.max() > (2048 if counts > 1e8 else 1024)
+    dev = torch.device("cuda:0")
+    geom = pm.Geometry(cfg)
+    y = torch.from_numpy(d["y"].ravel()).to(dev)
+    r = torch.from_numpy(d["r"].ravel()).to(dev)
+    a = torch.from_numpy(d["mult"].ravel()).to(dev)
+    cnt = pm.Counts(geom, y, r, a)
+    rng = np.random.default_rng(8)
+    x_np = (d["x_true"] * rng.uniform(0.7, 1.3, d["x_true"].shape) + 0.05 * d["x_true"].max()).astype(np.float32)
+    x = torch.from_numpy(x_np.ravel()).to(dev)
+    prob = recon.Problem(cfg, d["y"], d["r"], d["mult"], beta=0.0, gamma=2.0, eps=1e-3)
+    xo = x_np.astype(np.float64)
+    try:
+        for subset in (0, cfg["n_subsets"] - 1):
+            sens = torch.empty(geom.n_vox, device=dev)
+            pm.pet_back(geom, subset, None, a, sens)
+            g = torch.full((geom.n_vox,), float("nan"), device=dev)
+            kl = torch.zeros(1, dtype=torch.float64, device=dev)
+            pm.pet_subset_grad_counts(geom, cnt, subset, x, sens, g, kl)
+            ref = prob.data_grad(xo, subset).ravel()
+            yb = prob.ybar(xo, subset)
+            scale = np.linalg.norm(prob.back(prob.a[subset] * (1 + prob.y[subset] / yb), subset))
+            err = np.linalg.norm(g.cpu().double().numpy() - ref) / scale
+            print(f"[mini_tof_many, {n_rings} rings, {counts:.0e} counts] subset {subset}: {err:.2e}", flush=True)
+            assert err <= 1e-5
+            assert float(kl.cpu()) == pytest.approx(float(np.sum(poisson.kl(yb, prob.y[subset]))), rel=1e-5)
+    finally:
+        cnt.close()
+        geom.close()
