@@ -317,9 +317,9 @@ __device__ __forceinline__ void scatter_rows_packed(const ProjArgs &a, const Lin
     }
 }
 
-// Lanes per bin of a chunk of n_c bins: a power of two C <= 16, doubled while
-// the chunk's bins still fill the workgroup, so that lines with few bins keep
-// every wave busy.
+// Lanes per bin of a round of n_c bins: a power of two C <= 16, doubled while
+// the round's bins still fill the workgroup, so that lines with few bins (and
+// the last, partial round of a long line) keep every wave busy.
 __device__ __forceinline__ int lanes_per_bin(int n_c) {
     int C = 1;
     while (C < 16 && n_c * (2 * C) <= (int)blockDim.x) C *= 2;
@@ -438,26 +438,25 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             if (nrow > 0) build_x(a, L, nrow, X);
             __syncthreads();
         }
-        // C lanes per bin (consecutive lanes of one wave) take every C-th
-        // sample of its window
+        // Rounds of up to one bin per thread (CNT_BLOCK threads); a round with
+        // fewer bins, the chunk's last, gives each bin C lanes (consecutive
+        // lanes of one wave) that take every C-th sample of its window
         const int n_c = (int)(c1 - c0);
-        const int C = lanes_per_bin(n_c);
-        const int lc = __builtin_ctz((unsigned)C);
-        const int ch = threadIdx.x & (C - 1);
-        const int nslot = blockDim.x / C;
-        const float fC = (float)C;
+        const int nr = (n_c + CNT_BLOCK - 1) / CNT_BLOCK;
         float qabs = 0.f, qneg = 0.f;
-        // the thread's bins of the chunk's rounds (at most CNT_ROUNDS: C = 1
-        // when a chunk has more bins than the workgroup's threads) and their
-        // factors, for phase two
+        // the thread's bins of the chunk's rounds (at most CNT_ROUNDS) and
+        // their factors, for phase two
         BinB b0 = bin_b(none, 0.f), b1 = b0, b2 = b0, b3 = b0;
-        int rr = 0;
-        for (int64_t it0 = c0; it0 < c1; it0 += nslot) {
+        for (int rr = 0; rr < nr; ++rr) {
+            const int m = min(CNT_BLOCK, n_c - rr * CNT_BLOCK);
+            const int C = lanes_per_bin(m);
+            const int ch = threadIdx.x & (C - 1);
+            const float fC = (float)C;
             // every lane runs every round: the forward sums are added across
             // the C lanes of a bin by shuffles
-            const int64_t it = it0 + threadIdx.x / C;
-            const bool act = it < c1;
-            const CountRec e = act ? c.items[it] : none;
+            const int k = (int)threadIdx.x / C;
+            const bool act = k < m;
+            const CountRec e = act ? c.items[c0 + (int64_t)rr * CNT_BLOCK + k] : none;
             // rows as floats (exact integers): no conversion per sample
             const float fis = (float)(e.is + ch), fie = (float)e.ie;
             // two samples per iteration (their LDS reads in flight together,
@@ -505,7 +504,6 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
                     default: b3 = b; break;
                 }
             }
-            ++rr;
         }
         if (!NEED_Z) continue;  // uniform
         // (the barrier inside also ends every read of X)
@@ -521,7 +519,12 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             for (int k = threadIdx.x; k < (hi - lo) * rz; k += blockDim.x) Zu[k] = 0ull;
             __syncthreads();
             if (scale > 0.f) {
-                for (int q = 0; q < rr; ++q) {  // (uniform)
+                for (int q = 0; q < nr; ++q) {  // (uniform)
+                    const int m = min(CNT_BLOCK, n_c - q * CNT_BLOCK);
+                    const int C = lanes_per_bin(m);
+                    const int lc = __builtin_ctz((unsigned)C);
+                    const int ch = threadIdx.x & (C - 1);
+                    const float fC = (float)C;
                     BinB g;
                     switch (q) {
                         case 0: g = b0; break;
