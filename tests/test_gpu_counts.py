@@ -372,3 +372,42 @@ def test_counts_many_bins_per_line(n_rings, counts):
     finally:
         cnt.close()
         geom.close()
+
+
+def test_counts_alg2_bb_parity(case):
+    # ALG2 on the zero-count-aware path: preconditioner updates at the start
+    # of epochs 1, 2, 4, 6, short BB step at the snapshots of epochs 3 and 5
+    # (the snapshot's full gradient from the compacted bins, in one launch
+    # where the fused step serves the geometry), capped by the schedule;
+    # against the FP64 oracle's dense iteration (Algorithm 1 with the short BB
+    # step of Section 2.2)
+    from oracle import schedules
+    pm = case.pm
+    cfg, n = case.cfg, case.cfg["n_subsets"]
+    epochs = 6
+    beta = configs.beta_value(cfg)
+    x = torch.ones(case.geom.n_vox, device=case.dev)
+    xmax = torch.zeros(1, device=case.dev)
+    pm.pet_osem_epoch_counts(case.geom, case.counts, x, case.a, list(range(n)), xmax)
+    mx = float(xmax.cpu())
+    sens = case.sens_subset(-1)
+    st = pm.SvrgStateBuffers(case.geom, case.y, case.r, case.a, sens, beta=beta, gamma=2.0, eps=1e-3 * mx,
+                             alpha=1.0, delta=1e-3 * mx, bb=True, counts=case.counts)
+    orders = data.subset_orders(cfg, epochs)
+    upd = {0, n, 3 * n, 5 * n}
+    bb_it = {2 * n, 4 * n}
+    cap = lambda k: schedules.alg2_cap(k, n)  # noqa: E731
+    for e in range(epochs):
+        ks = [e * n + j for j in range(n)]
+        pm.pet_svrg_epoch(case.geom, st, x, orders[e], [cap(k) for k in ks], [k in upd for k in ks],
+                          bb_update=[k in bb_it for k in ks])
+    x0 = recon.osem_epoch(case.prob, np.ones(case.prob.shape))
+    m0 = float(x0.max())
+    prob = recon.Problem(cfg, case.d["y"], case.d["r"], case.d["mult"], beta=beta, gamma=2.0, eps=1e-3 * m0,
+                         alpha=1.0, delta=1e-3 * m0)
+    rec = []
+    x_orc = recon.svrg(prob, x0, epochs, recon.order_rule(orders), cap, upd, bb_iters=bb_it, record=rec)
+    assert st.bb.cpu().numpy()[3] == len(bb_it)
+    err = _rel(x.cpu().double().numpy(), x_orc.ravel())
+    print(f"[{cfg['name']}] zero-count-aware ALG2, {epochs} epochs: relative L2 {err:.2e}", flush=True)
+    assert err <= 1e-4
