@@ -267,10 +267,11 @@ def time_to_nrmse(args, cfg, geom, pm, cnt, epochs, y, r, a, beta, eps, delta, x
         t_epochs = 0.0
         t0 = time.perf_counter()
         x1.fill_(1.0)
-        pm.pet_back(geom_run, -1, None, a, sens)
         if cnt_run is not None:
-            pm.pet_osem_epoch_counts(geom_run, cnt_run, x1, a, list(range(n_run)), xmax)
+            # (the OSEM epoch also sums its subset sensitivities into sens)
+            pm.pet_osem_epoch_counts(geom_run, cnt_run, x1, a, list(range(n_run)), xmax, sens_out=sens)
         else:
+            pm.pet_back(geom_run, -1, None, a, sens)
             pm.pet_osem_epoch(geom_run, x1, y, r, a, list(range(n_run)), xmax)
         st1 = pm.SvrgStateBuffers(geom_run, y, r, a, sens, beta=beta, gamma=cfg["gamma"], eps=eps, alpha=1.0,
                                   delta=delta, bb=bb, counts=cnt_run)
@@ -298,9 +299,9 @@ def time_to_nrmse(args, cfg, geom, pm, cnt, epochs, y, r, a, beta, eps, delta, x
                      "min_nrmse": min(trace), "final_nrmse": trace[-1]}
         del st1, x1, sens
     return out, {"reference": ref, "region_voxels": int(nm), "level": level,
-                 "includes": "sensitivity backprojection, 1 OSEM epoch (on the run's data-term path), the "
-                             "estimator's epochs and, on the zero-count-aware path, the compaction of the counts "
-                             "(NRMSE evaluation excluded)"}
+                 "includes": "sensitivity, 1 OSEM epoch (on the run's data-term path; the zero-count-aware "
+                             "epoch sums its subset sensitivities into the sensitivity), the estimator's epochs and, "
+                             "on the zero-count-aware path, the compaction of the counts (NRMSE evaluation excluded)"}
 
 
 def differentiable_leg(pm):

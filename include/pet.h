@@ -226,9 +226,13 @@ pet_status pet_objective_counts(pet_geom g, pet_counts c, const float *x, const 
  * were made with (nullable: 1); it enters P_i^T mult, which on a TOF geometry
  * is computed with the bins' weights summed per sample.  Voxels with
  * P_i^T mult = 0 keep x.  xmax_out (device float, nullable) receives max(x)
- * after the epoch.  PET_E_ARG if c was made for another geometry. */
+ * after the epoch; sens_out (device, n_vox floats, nullable) the sensitivity
+ * P^T mult over all subsets, summed in FP32 from the epoch's subset
+ * sensitivities in order[] (equal to pet_back's up to rounding), so that a
+ * reconstruction needs no separate sensitivity pass.  PET_E_ARG if c was made
+ * for another geometry. */
 pet_status pet_osem_epoch_counts(pet_geom g, pet_counts c, float *x, const float *mult, const int32_t *order,
-                                 float *xmax_out, void *stream);
+                                 float *xmax_out, float *sens_out, void *stream);
 
 /* Relative difference prior (eq. (rdp)) and its derivatives (Appendix A),
  * scaled by beta: grad_out = beta dS/dx, hessdiag_out = beta d2S/dx2 (nullable),

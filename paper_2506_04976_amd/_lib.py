@@ -138,7 +138,7 @@ def lib():
         L.pet_counts_info.argtypes = [P, I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.pet_subset_grad_counts.argtypes = [P, P, I, P, P, P, P, P]
         L.pet_objective_counts.argtypes = [P, P, P, P, P, ctypes.POINTER(F), F, F, F, P, P]
-        L.pet_osem_epoch_counts.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_int32), P, P]
+        L.pet_osem_epoch_counts.argtypes = [P, P, P, P, ctypes.POINTER(ctypes.c_int32), P, P, P]
         L.pet_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
@@ -474,14 +474,15 @@ def pet_subset_grad_counts(geom, counts, subset, x, sens_subset, grad_out, kl_ou
     return grad_out
 
 
-def pet_osem_epoch_counts(geom, counts, x, mult, order, xmax_out=None, stream=None):
+def pet_osem_epoch_counts(geom, counts, x, mult, order, xmax_out=None, sens_out=None, stream=None):
     order = [int(v) for v in order]
     if len(order) != geom.n_subsets:
         raise ValueError("order must list every subset once per epoch")
     arr = (ctypes.c_int32 * len(order))(*order)
     _check(lib().pet_osem_epoch_counts(geom.handle, counts.handle, _ptr(x, torch.float32, geom.n_vox, "x"),
                                        _ptr(mult, torch.float32, geom.n_lors, "mult"), arr,
-                                       _ptr(xmax_out, torch.float32, 1, "xmax_out"), _stream(stream)))
+                                       _ptr(xmax_out, torch.float32, 1, "xmax_out"),
+                                       _ptr(sens_out, torch.float32, geom.n_vox, "sens_out"), _stream(stream)))
     return x
 
 

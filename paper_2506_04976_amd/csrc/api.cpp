@@ -853,7 +853,7 @@ extern "C" pet_status pet_subset_grad_counts(pet_geom g, pet_counts c, int subse
 }
 
 extern "C" pet_status pet_osem_epoch_counts(pet_geom g, pet_counts c, float *x, const float *mult,
-                                            const int32_t *order, float *xmax_out, void *stream) {
+                                            const int32_t *order, float *xmax_out, float *sens_out, void *stream) {
     if (!g || !c || !x || !order) return fail(PET_E_ARG, "pet_osem_epoch_counts: null argument");
     if (c->g != g) return fail(PET_E_ARG, "pet_osem_epoch_counts: counts were made for another geometry");
     for (int j = 0; j < g->d.n_subsets; ++j)
@@ -876,6 +876,9 @@ extern "C" pet_status pet_osem_epoch_counts(pet_geom g, pet_counts c, float *x, 
         a.mult = mult;
         if (e == hipSuccess) e = launch_line_kernel(g, M_BACK, i, a, s);
         if (e == hipSuccess) e = launch_from_sheets(g, g->sensi, 0, s);
+        if (e == hipSuccess && sens_out)
+            e = j == 0 ? launch_copy(sens_out, g->sensi, g->n_vox, s)
+                       : launch_lincomb(sens_out, 1.f, sens_out, 1.f, g->sensi, g->n_vox, s);
         // -P_i^T (mult y / ybar) from the bins with counts; the update negates
         if (e == hipSuccess) e = launch_to_sheets(g, x, s);
         if (e == hipSuccess) e = counts_grad_sheets(g, c, i, nullptr, s);

@@ -187,11 +187,14 @@ def test_counts_osem_epoch_parity(case):
     order = [int(v) for v in np.random.default_rng(3).permutation(n)]
     x = torch.ones(case.geom.n_vox, device=case.dev)
     xmax = torch.zeros(1, device=case.dev)
-    pm.pet_osem_epoch_counts(case.geom, case.counts, x, case.a, order, xmax)
+    sens = torch.full((case.geom.n_vox,), float("nan"), device=case.dev)
+    pm.pet_osem_epoch_counts(case.geom, case.counts, x, case.a, order, xmax, sens_out=sens)
     got = x.cpu().double().numpy()
     ref = recon.osem_epoch(case.prob, np.ones(case.prob.shape), order).ravel()
     assert _rel(got, ref) <= 1e-5
     assert float(xmax.cpu()) == float(got.max())
+    # the sensitivity summed over the epoch's subsets: the oracle's A^T 1
+    assert _rel(sens.cpu().numpy(), case.prob.sens().ravel()) <= 1e-5
     xd = torch.ones(case.geom.n_vox, device=case.dev)
     pm.pet_osem_epoch(case.geom, xd, case.y, case.r, case.a, order, None)
     assert _rel(got, xd.cpu().double().numpy()) <= 1e-5
