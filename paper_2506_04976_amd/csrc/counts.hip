@@ -287,12 +287,12 @@ __device__ __forceinline__ float packed_cell_value(const unsigned long long *Zu,
     return finite ? (float)V * inv_scale : __builtin_nanf("");
 }
 
-// Readout of the packed sheet rows [lo, hi) of the line (Zu holds them from
-// row lo on), spread over the two transaxial neighbours like the FP64 sheet of
-// the dense kernels.  A line whose bound is not finite (a bin with ybar = 0)
-// adds NaN to every cell it covers.
+// Readout of the packed sheet of the line's rows of parity par (row par + 2k
+// of the line in Zu row k, k < nh), spread over the two transaxial neighbours
+// like the FP64 sheet of the dense kernels.  A line whose bound is not finite
+// (a bin with ybar = 0) adds NaN to every cell it covers.
 template <bool SIGNED>
-__device__ __forceinline__ void scatter_rows_packed(const ProjArgs &a, const LineP &L, int lo, int hi,
+__device__ __forceinline__ void scatter_rows_parity(const ProjArgs &a, const LineP &L, int par, int nh,
                                                     const unsigned long long *Zu, float inv_scale, bool finite,
                                                     int64_t g_off) {
     const int rz = a.rz;
@@ -301,18 +301,18 @@ __device__ __forceinline__ void scatter_rows_packed(const ProjArgs &a, const Lin
     if (rz <= (int)blockDim.x) {
         const SheetWalk w = sheet_walk(rz);
         if (!w.on) return;
-        for (int r = lo + w.r0; r < hi; r += w.R) {
-            const float val = packed_cell_value<SIGNED>(Zu, (r - lo) * rz + w.zp, w.zp, inv_scale, finite);
+        for (int k = w.r0; k < nh; k += w.R) {
+            const float val = packed_cell_value<SIGNED>(Zu, k * rz + w.zp, w.zp, inv_scale, finite);
             if (val == 0.f) continue;
-            spread_cell(Gout, sheet_row(L, L.i_lo + r, other_stride, rz), w.zp, rz, val);
+            spread_cell(Gout, sheet_row(L, L.i_lo + par + 2 * k, other_stride, rz), w.zp, rz, val);
         }
     } else {
-        for (int e = threadIdx.x; e < (hi - lo) * rz; e += blockDim.x) {
-            const int r = e / rz;
-            const int zp = e - r * rz;
+        for (int e = threadIdx.x; e < nh * rz; e += blockDim.x) {
+            const int k = e / rz;
+            const int zp = e - k * rz;
             const float val = packed_cell_value<SIGNED>(Zu, e, zp, inv_scale, finite);
             if (val == 0.f) continue;
-            spread_cell(Gout, sheet_row(L, L.i_lo + lo + r, other_stride, rz), zp, rz, val);
+            spread_cell(Gout, sheet_row(L, L.i_lo + par + 2 * k, other_stride, rz), zp, rz, val);
         }
     }
 }
@@ -383,17 +383,19 @@ static_assert(CNT_QCAP <= CNT_ROUNDS * CNT_BLOCK, "a chunk takes at most CNT_ROU
 // sum of y log(y / ybar) when a.partial is set.
 //
 // LDS: one sheet region that holds the image sheet X (nrow x rz floats) while
-// the bins are walked forward, and then the packed gradient sheet of half the
-// rows (ceil(nrow / 2) x rz 64-bit words, the same bytes); the TOF table.
+// the bins are walked forward, and then the packed gradient sheet of the rows
+// of one parity (ceil(nrow / 2) x rz 64-bit words, the same bytes); the TOF
+// table.
 // About 71 KB on the brain-sized workloads, so that two workgroups share a CU
 // and one's barriers overlap the other's samples.
 //
 // The line's bins are taken in chunks of at most c.q_cap.  Phase one walks
 // every bin of the chunk forward (ybar, the log term, Q = mult y / ybar ell).
-// With M_GRAD, phase two runs once per half of the rows: it clears the packed
-// sheet, adds the chunk's shares -Q W(t - t_b) (times the axial interpolation
-// weights, scaled by 2^30 / sum |Q|) of the samples in those rows, and reads
-// the half out.  Each thread keeps what phase two needs of its bins (one per
+// With M_GRAD, phase two runs once per parity of the rows (even rows, then
+// odd ones, so that every bin's window splits about evenly between the two
+// passes): it clears the packed sheet, adds the chunk's shares -Q W(t - t_b)
+// (times the axial interpolation weights, scaled by 2^30 / sum |Q|) of the
+// samples in those rows, and reads them out.  Each thread keeps what phase two needs of its bins (one per
 // round of the chunk, at most CNT_ROUNDS) and their factors in registers
 // between the phases.  A next chunk rebuilds X.
 template <bool TOF, int MODE>
@@ -410,7 +412,6 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
     unsigned long long *Zu = reinterpret_cast<unsigned long long *>(smem);  // (X's bytes, after phase one)
     float2 *tab = reinterpret_cast<float2 *>(smem + c.sheet_floats);
     const int64_t i0 = desc.i0, i1 = desc.i0 + desc.n;
-    const int hrows = (nrow + 1) >> 1;
     const CountRec none{1, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // no rows, no count
 
     if (TOF) {
@@ -513,18 +514,19 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
         const bool sgn = tot.y > 0.f || c.force_signed;  // some Q < 0 (uniform)
         const float scale = finite && bound > 0.f ? 0x1p30f / bound : 0.f;
         if (nrow == 0 || (scale == 0.f && finite)) continue;  // (nothing to add; uniform)
-        for (int lo = 0; lo < nrow; lo += hrows) {
-            const int hi = lo + hrows < nrow ? lo + hrows : nrow;
-            const int ra = L.i_lo + lo, rb = L.i_lo + hi - 1;  // absolute rows of this half
-            for (int k = threadIdx.x; k < (hi - lo) * rz; k += blockDim.x) Zu[k] = 0ull;
+        for (int par = 0; par < 2; ++par) {
+            // the line's rows of parity par, so that every bin's window splits
+            // about evenly between the two passes
+            const int nh = (nrow - par + 1) >> 1;
+            if (nh <= 0) break;  // (uniform)
+            for (int k = threadIdx.x; k < nh * rz; k += blockDim.x) Zu[k] = 0ull;
             __syncthreads();
             if (scale > 0.f) {
                 for (int q = 0; q < nr; ++q) {  // (uniform)
                     const int m = min(CNT_BLOCK, n_c - q * CNT_BLOCK);
                     const int C = lanes_per_bin(m);
-                    const int lc = __builtin_ctz((unsigned)C);
                     const int ch = threadIdx.x & (C - 1);
-                    const float fC = (float)C;
+                    const float fS = 2.f * (float)C;  // rows per step of a lane
                     BinB g;
                     switch (q) {
                         case 0: g = b0; break;
@@ -534,18 +536,17 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
                     }
                     const float qsc = g.Q * scale;
                     const int gis = (int)(int16_t)(g.isie & 0xffffu), gie = (int)(int16_t)(g.isie >> 16);
-                    // this lane's rows is + ch + kC that fall in [ra, rb]
-                    int r0 = gis + ch;
-                    if (r0 < ra) r0 += ((ra - r0 + C - 1) >> lc) << lc;
-                    const int r1 = gie < rb ? gie : rb;
-                    const float fis = (float)r0, fie = (float)r1;
-                    unsigned long long *zr = Zu + (r0 - ra) * rz;
+                    // this lane's rows: the bin's first row of parity par, then
+                    // every 2C-th row from 2 ch on
+                    const int r0 = gis + ((gis - L.i_lo - par) & 1) + 2 * ch;
+                    const float fis = (float)r0, fie = (float)gie;
+                    unsigned long long *zr = Zu + ((r0 - L.i_lo - par) >> 1) * rz;
+                    const int step = C * rz;  // (Zu rows per step of a lane)
                     if (!sgn) {
                         // (two samples per iteration, as forward)
-                        const int step = C * rz;
                         float fi = fis;
-                        for (; fi + fC <= fie; fi += 2.f * fC, zr += 2 * step) {
-                            const float fj = fi + fC;
+                        for (; fi + fS <= fie; fi += 2.f * fS, zr += 2 * step) {
+                            const float fj = fi + fS;
                             const float qw0 = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB)) : qsc;
                             const float qw1 = TOF ? qsc * tof_weight_at(tab, fmaf(fj, g.pA, g.pB)) : qsc;
                             const float u0 = fmaf(fi, g.zA, g.zB), u1 = fmaf(fj, g.zA, g.zB);
@@ -558,7 +559,7 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
                             deposit_pos(zr, (int)u, qw, __builtin_amdgcn_fractf(u));
                         }
                     } else {
-                        for (float fi = fis; fi <= fie; fi += fC, zr += C * rz) {
+                        for (float fi = fis; fi <= fie; fi += fS, zr += step) {
                             const float qw = TOF ? qsc * tof_weight_at(tab, fmaf(fi, g.pA, g.pB)) : qsc;
                             const float u = fmaf(fi, g.zA, g.zB);
                             deposit_packed(zr, (int)u, -qw, __builtin_amdgcn_fractf(u));
@@ -569,10 +570,10 @@ __global__ void __launch_bounds__(CNT_BLOCK) k_line_counts(ProjArgs a, CountArgs
             __syncthreads();
             const int64_t g_off = (int64_t)desc.slot * c.slot_floats;
             if (sgn)
-                scatter_rows_packed<true>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite, g_off);
+                scatter_rows_parity<true>(a, L, par, nh, Zu, finite ? 1.f / scale : 0.f, finite, g_off);
             else
-                scatter_rows_packed<false>(a, L, lo, hi, Zu, finite ? 1.f / scale : 0.f, finite, g_off);
-            // (before the next half clears the sheet, or the next chunk's X)
+                scatter_rows_parity<false>(a, L, par, nh, Zu, finite ? 1.f / scale : 0.f, finite, g_off);
+            // (before the next pass clears the sheet, or the next chunk's X)
             __syncthreads();
         }
     }
@@ -615,8 +616,8 @@ hipError_t launch_counts_mode(const pet_geom_s *g, const pet_counts_s *cs, int n
 }  // namespace
 
 // LDS of the counts kernel (dynamic), in floats: the sheet region (X, or the
-// packed gradient sheet of half the rows), the TOF table (NW_TAB + 1 nodes),
-// each rounded up to 16 bytes.
+// packed gradient sheet of the rows of one parity), the TOF table (NW_TAB
+// (W, dW) pairs), each rounded up to 16 bytes.
 static size_t counts_sheet_floats(const pet_geom_s *g) {
     const size_t rz = (size_t)g->d.nz + 2 * PADZ;
     const size_t x = (size_t)g->rows_max * rz;
